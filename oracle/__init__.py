@@ -1,0 +1,451 @@
+"""FP64 CPU oracle for the space-time power iteration (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package. It shares no code with the HIP
+library and never imports it; the two meet only through the seeded inputs of
+the ``synth`` module.
+
+What it computes, each function citing the passage it restates:
+
+* ``apply``/``apply_at``: one application of the affinity matrix
+  A = diag(f) G diag(f) as a direct 3D neighbourhood sum (C, ``stpi_oracle.c``)
+  -- Eq. 2 with alpha = 0, Eq. 4, first convolution term of Eq. 7.
+* ``iterate``: power iteration with global L2 normalisation after every
+  application (Eq. 4 + Eq. 8, Alg. 1 outer loop).
+* ``dense_matrix``/``perron``: the explicit N x N adjacency on tiny volumes and
+  its principal eigenvector (Eq. 3, Perron-Frobenius).
+* ``combine``/``combine_bwd``: softmax-weighted channel sum f = sum_c
+  softmax(w)_c f_c (the multi-channel combination of Eq. 9, in the
+  convex-combination form used for learning the channel weights).
+* ``forward_train``/``adjoint``: reverse-mode derivative of the normalised
+  iteration (gradient through the full spectral algorithm, Sec. 3.4).
+* ``bce``: binary cross-entropy on x / max(x).
+* ``net_forward``/``net_backward``: 4-layer 3x3x3 'same' conv net (C).
+* ``adamw_step``: AdamW with AMSGrad (Eq. 13).
+* ``fallback``: warm-start fallback rule.
+
+Readings of points the paper leaves open (unnormalised Gaussian with G(0)=1,
+the 2*sigma^2 convention, box support, zero padding, global normalisation,
+residual = ||x_{k+1} - x_k||_2 between unit vectors) are fixed here and
+listed in the design notes.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "stpi_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (OpenMP, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        ci, cd = ctypes.c_int, ctypes.c_double
+        lib.oracle_apply.argtypes = [ci, ci, ci, dp, dp, cd, cd, ci, ci, dp]
+        lib.oracle_apply_at.argtypes = [ci, ci, ci, dp, dp, cd, cd, ci, ci, i64p, ctypes.c_int64, dp]
+        lib.oracle_conv3d_fwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp]
+        lib.oracle_conv3d_bwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp, dp, dp]
+        lib.oracle_num_threads.restype = ci
+        lib.oracle_set_threads.argtypes = [ci]
+        _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def set_threads(n: int) -> None:
+    _load().oracle_set_threads(int(n))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+@dataclass(frozen=True)
+class Kernel:
+    """Truncated space-time Gaussian: sigmas in pixels / frames, box radii."""
+    sigma_s: float
+    sigma_t: float
+    r_s: int
+    r_t: int
+
+
+# ---------------------------------------------------------------------------
+# Operator and power iteration
+# ---------------------------------------------------------------------------
+
+def apply(f, x, k: Kernel) -> np.ndarray:
+    """z = A x with A_ij = f_i f_j G_ij (direct neighbourhood loop, FP64)."""
+    f = _f64(f)
+    x = _f64(x)
+    assert f.ndim == 3 and f.shape == x.shape
+    T, H, W = f.shape
+    z = np.empty_like(f)
+    rc = _load().oracle_apply(T, H, W, _dptr(f), _dptr(x), k.sigma_s, k.sigma_t, k.r_s, k.r_t, _dptr(z))
+    if rc != 0:
+        raise ValueError("oracle_apply: invalid arguments")
+    return z
+
+
+def apply_at(f, x, k: Kernel, idx) -> np.ndarray:
+    """(A x)_i for the flat indices ``idx`` only."""
+    f = _f64(f)
+    x = _f64(x)
+    T, H, W = f.shape
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    out = np.empty(idx.shape, dtype=np.float64)
+    rc = _load().oracle_apply_at(T, H, W, _dptr(f), _dptr(x), k.sigma_s, k.sigma_t, k.r_s, k.r_t,
+                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.size, _dptr(out))
+    if rc != 0:
+        raise ValueError("oracle_apply_at: invalid arguments or index out of range")
+    return out
+
+
+@dataclass
+class IterInfo:
+    iters: int = 0
+    converged: bool = False
+    residuals: list = None
+    lambdas: list = None        # ||A x_k|| for each application (x_k unit)
+    rayleigh: list = None       # <x_k, A x_k>
+    status: str = "ok"          # "ok" | "zero_norm" | "nonfinite"
+
+
+def iterate(f, k: Kernel, x0=None, iters: int | None = None, tol: float | None = None,
+            cap: int | None = None, keep=False):
+    """Power iteration x_{k+1} = A x_k / ||A x_k|| (Eq. 4, Eq. 8).
+
+    x0 defaults to the uniform unit vector 1/sqrt(N) (Sec. 4: uniform or the
+    unary map). It is normalised before the first application. With ``iters``
+    the loop runs exactly that many applications; with ``tol`` it stops at the
+    first k whose residual ||x_k - x_{k-1}|| < tol, or at ``cap``. The
+    residual is taken directly on the difference of the two unit vectors.
+    Returns (x, IterInfo) or, with keep=True, (x, IterInfo, [x_0 .. x_K]).
+    """
+    f = _f64(f)
+    N = f.size
+    x = np.full(f.shape, 1.0 / math.sqrt(N)) if x0 is None else _f64(x0).copy()
+    nx = math.sqrt(float(np.sum(x * x)))
+    if not nx > 0:
+        raise ValueError("x0 has zero norm")
+    x = x / nx
+    limit = iters if iters is not None else (cap if cap is not None else 1000)
+    info = IterInfo(residuals=[], lambdas=[], rayleigh=[])
+    traj = [x.copy()] if keep else None
+    for _ in range(limit):
+        z = apply(f, x, k)
+        n = math.sqrt(float(np.sum(z * z)))
+        if not math.isfinite(n):
+            info.status = "nonfinite"
+            break
+        if n == 0.0:
+            info.status = "zero_norm"
+            break
+        info.rayleigh.append(float(np.sum(x * z)))
+        x1 = z / n
+        r = math.sqrt(float(np.sum((x1 - x) ** 2)))
+        info.iters += 1
+        info.residuals.append(r)
+        info.lambdas.append(n)
+        x = x1
+        if keep:
+            traj.append(x.copy())
+        if iters is None and tol is not None and r < tol:
+            info.converged = True
+            break
+    if keep:
+        return x, info, traj
+    return x, info
+
+
+def dense_matrix(f, k: Kernel) -> np.ndarray:
+    """Explicit adjacency (tiny volumes only): A_ij = f_i f_j G_ij, built pair by pair."""
+    f = _f64(f)
+    T, H, W = f.shape
+    N = f.size
+    if N > 4096:
+        raise ValueError("dense_matrix is for tiny volumes")
+    coords = [(t, y, x) for t in range(T) for y in range(H) for x in range(W)]
+    flat = f.reshape(-1)
+    A = np.zeros((N, N))
+    for i, (ti, yi, xi) in enumerate(coords):
+        for j, (tj, yj, xj) in enumerate(coords):
+            dt, dy, dx = tj - ti, yj - yi, xj - xi
+            if abs(dt) <= k.r_t and abs(dy) <= k.r_s and abs(dx) <= k.r_s:
+                g = math.exp(-(dt * dt) / (2 * k.sigma_t ** 2) - (dy * dy + dx * dx) / (2 * k.sigma_s ** 2))
+                A[i, j] = flat[i] * flat[j] * g
+    return A
+
+
+def perron(A: np.ndarray):
+    """Principal eigenpair of a symmetric nonnegative matrix via numpy.linalg.eigh.
+
+    The eigenvector's sign is fixed so that it sums to a nonnegative value
+    (Perron-Frobenius: the principal eigenvector is nonnegative, Eq. 3).
+    """
+    w, V = np.linalg.eigh(A)
+    v = V[:, -1]
+    if v.sum() < 0:
+        v = -v
+    return float(w[-1]), v, w
+
+
+# ---------------------------------------------------------------------------
+# Channel combination (learned weights) and loss
+# ---------------------------------------------------------------------------
+
+def softmax(w) -> np.ndarray:
+    w = _f64(w)
+    e = np.exp(w - w.max())
+    return e / e.sum()
+
+
+def combine(fc, w) -> np.ndarray:
+    """f = sum_c softmax(w)_c * fc[c]."""
+    fc = _f64(fc)
+    a = softmax(w)
+    return np.tensordot(a, fc, axes=(0, 0))
+
+
+def combine_bwd(fc, w, g_f) -> np.ndarray:
+    """dL/dw from dL/df: g_a_c = <g_f, fc_c>, then the softmax Jacobian."""
+    fc = _f64(fc)
+    g_f = _f64(g_f)
+    a = softmax(w)
+    g_a = np.array([float(np.sum(g_f * fc[c])) for c in range(fc.shape[0])])
+    return a * (g_a - float(np.dot(a, g_a)))
+
+
+BCE_EPS = 1e-7
+
+
+def bce(x, gt):
+    """BCE(y, gt) with y = clip(x / max(x), eps, 1 - eps), mean over voxels.
+
+    Returns (loss, dL/dx). The max term's derivative goes to the first argmax;
+    clipped entries pass no gradient.
+    """
+    x = _f64(x)
+    g = np.asarray(gt, dtype=np.float64)
+    m = float(x.max())
+    y_raw = x / m
+    y = np.clip(y_raw, BCE_EPS, 1.0 - BCE_EPS)
+    N = x.size
+    loss = -float(np.mean(g * np.log(y) + (1.0 - g) * np.log(1.0 - y)))
+    g_y = (y - g) / (y * (1.0 - y)) / N
+    g_y = np.where((y_raw > BCE_EPS) & (y_raw < 1.0 - BCE_EPS), g_y, 0.0)
+    g_x = g_y / m
+    a = int(np.argmax(x.reshape(-1)))
+    g_x.reshape(-1)[a] -= float(np.sum(g_y * x)) / (m * m)
+    return loss, g_x
+
+
+# ---------------------------------------------------------------------------
+# Reverse mode through the normalised iteration
+# ---------------------------------------------------------------------------
+
+def forward_train(f, k: Kernel, iters: int, x0=None):
+    """Run `iters` steps keeping everything the derivative needs.
+
+    Per step (x_k unit): u = f x_k, v = G u, z = f v, n = ||z||, x_{k+1} = z / n.
+    Returns dict(xs=[x_0..x_K], vs=[v_0..v_{K-1}], ns=[n_1..n_K]).
+    """
+    f = _f64(f)
+    N = f.size
+    x = np.full(f.shape, 1.0 / math.sqrt(N)) if x0 is None else _f64(x0) / np.linalg.norm(x0)
+    xs, vs, ns = [x], [], []
+    ones = np.ones_like(f)
+    for _ in range(iters):
+        # G u through the direct loop: A with unit features applied to u.
+        v = apply(ones, f * x, k)
+        z = f * v
+        n = math.sqrt(float(np.sum(z * z)))
+        x = z / n
+        xs.append(x)
+        vs.append(v)
+        ns.append(n)
+    return dict(xs=xs, vs=vs, ns=ns)
+
+
+def adjoint(f, k: Kernel, tape, g_xK):
+    """dL/df given dL/dx_K, by the chain rule through every step in reverse.
+
+    For x_{k+1} = z / ||z||, z = f (G (f x_k)):
+      g_z = (g - x_{k+1} <x_{k+1}, g>) / n
+      g_f += v g_z ;  g_u = G (f g_z) ;  g_f += x_k g_u ;  g_{x_k} = f g_u
+    x_0 is a constant (uniform start), so the chain stops there.
+    """
+    f = _f64(f)
+    ones = np.ones_like(f)
+    g = _f64(g_xK).copy()
+    g_f = np.zeros_like(f)
+    K = len(tape["ns"])
+    for j in range(K - 1, -1, -1):
+        x1 = tape["xs"][j + 1]
+        x0 = tape["xs"][j]
+        n = tape["ns"][j]
+        v = tape["vs"][j]
+        g_z = (g - x1 * float(np.sum(x1 * g))) / n
+        g_f += v * g_z
+        g_u = apply(ones, f * g_z, k)
+        g_f += x0 * g_u
+        g = f * g_u
+    return g_f
+
+
+def loss_and_grad(fc, w, gt, k: Kernel, iters: int):
+    """End to end: f = combine(fc, w); x = iterate(f); L = bce(x, gt); dL/dw."""
+    f = combine(fc, w)
+    tape = forward_train(f, k, iters)
+    loss, g_x = bce(tape["xs"][-1], gt)
+    g_f = adjoint(f, k, tape, g_x)
+    return loss, combine_bwd(fc, w, g_f), tape
+
+
+# ---------------------------------------------------------------------------
+# Warm-start network (4 x conv3d 3x3x3, ReLU between layers)
+# ---------------------------------------------------------------------------
+
+def bf16_round(a) -> np.ndarray:
+    """Round float values to bfloat16 (round to nearest, ties to even), returned as float64."""
+    a32 = np.asarray(a, dtype=np.float32)
+    bits = a32.view(np.uint32).astype(np.uint64)
+    lsb = (bits >> 16) & 1
+    rounded = ((bits + 0x7FFF + lsb) >> 16) << 16
+    nan = np.isnan(a32)
+    out = rounded.astype(np.uint32).view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out
+
+
+def conv3d(x, wgt, bias):
+    """'same' 3x3x3 conv with zero padding. x [Cin][T][H][W], wgt [Cout][Cin][3][3][3]."""
+    x = _f64(x)
+    wgt = _f64(wgt)
+    bias = _f64(bias)
+    Cin, T, H, W = x.shape
+    Cout = wgt.shape[0]
+    assert wgt.shape == (Cout, Cin, 3, 3, 3)
+    out = np.empty((Cout, T, H, W))
+    rc = _load().oracle_conv3d_fwd(Cin, Cout, T, H, W, _dptr(x), _dptr(wgt), _dptr(bias), _dptr(out))
+    if rc:
+        raise ValueError("oracle_conv3d_fwd: bad arguments")
+    return out
+
+
+def conv3d_bwd(x, wgt, g_out, need_input_grad=True):
+    x = _f64(x)
+    wgt = _f64(wgt)
+    g_out = _f64(g_out)
+    Cin, T, H, W = x.shape
+    Cout = wgt.shape[0]
+    g_in = np.empty_like(x) if need_input_grad else None
+    g_w = np.empty_like(wgt)
+    g_b = np.empty(Cout)
+    null = ctypes.POINTER(ctypes.c_double)()
+    rc = _load().oracle_conv3d_bwd(Cin, Cout, T, H, W, _dptr(x), _dptr(wgt), _dptr(g_out),
+                                   _dptr(g_in) if g_in is not None else null, _dptr(g_w), _dptr(g_b))
+    if rc:
+        raise ValueError("oracle_conv3d_bwd: bad arguments")
+    return g_in, g_w, g_b
+
+
+NET_CHANNELS = (1, 16, 16, 16, 1)
+
+
+def net_forward(f, params, bf16: bool = False):
+    """y = L4(relu(L3(relu(L2(relu(L1(f))))))); params = [(w1,b1),..,(w4,b4)].
+
+    With bf16=True the weights and each layer's input activations are rounded
+    to bfloat16 before the (FP64-accumulated) convolution, and the output is
+    left unrounded. Returns (y [T][H][W], cache for net_backward).
+    """
+    h = _f64(f)[None]
+    cache = []
+    nl = len(params)
+    for li, (w, b) in enumerate(params):
+        hin = bf16_round(h) if bf16 else h
+        wq = bf16_round(w) if bf16 else _f64(w)
+        pre = conv3d(hin, wq, b)
+        cache.append((hin, wq, pre))
+        h = np.maximum(pre, 0.0) if li < nl - 1 else pre
+    return h[0], cache
+
+
+def net_backward(cache, g_y):
+    """Gradients [(g_w, g_b)] of the loss w.r.t. each layer's (rounded) weights."""
+    g = _f64(g_y)[None]
+    grads = [None] * len(cache)
+    for li in range(len(cache) - 1, -1, -1):
+        hin, wq, pre = cache[li]
+        if li < len(cache) - 1:
+            g = g * (pre > 0)
+        g_in, g_w, g_b = conv3d_bwd(hin, wq, g, need_input_grad=li > 0)
+        grads[li] = (g_w, g_b)
+        g = g_in
+    return grads
+
+
+def warm_start_x0(y, eps: float = 1e-6) -> np.ndarray:
+    """Initial vector from the net output: normalize(max(y, 0) + eps)."""
+    x = np.maximum(_f64(y), 0.0) + eps
+    return x / np.linalg.norm(x)
+
+
+def net_loss(y, x_star):
+    """MSE between the net output and the target eigenvector scaled by sqrt(N)."""
+    y = _f64(y)
+    tgt = _f64(x_star) * math.sqrt(y.size)
+    d = y - tgt
+    return float(np.mean(d * d)), 2.0 * d / y.size
+
+
+def adamw_step(w, g, m, v, vmax, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+               weight_decay=0.01, amsgrad=True):
+    """AdamW (Eq. 13) with decoupled weight decay and AMSGrad; returns new (w, m, v, vmax).
+
+    step is 1-based. Decay first (w <- w (1 - lr wd)), then the moment
+    updates, bias corrections and w <- w - lr m_hat / (sqrt(v_hat) + eps).
+    """
+    w = _f64(w) * (1.0 - lr * weight_decay)
+    g = _f64(g)
+    m = beta1 * _f64(m) + (1.0 - beta1) * g
+    v = beta2 * _f64(v) + (1.0 - beta2) * g * g
+    vmax = np.maximum(_f64(vmax), v) if amsgrad else v
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = vmax / (1.0 - beta2 ** step)
+    w = w - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return w, m, v, vmax
+
+
+def fallback(r1: float, r2: float) -> bool:
+    """Warm-start fallback: restart from uniform when the residual rises (r2 > r1)."""
+    return not (r2 <= r1)
