@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark: voxel-iterations/s of the space-time power iteration on one MI355X.
+
+Workload: one synthetic full-resolution clip, 64 x 480 x 854 (the paper's
+DAVIS frame size), 5 moving Gaussian blobs plus U[0, 0.1] noise, filter
+sigma_s = 5, sigma_t = 2, r_s = 15, r_t = 5. One benchmark step is one
+complete stpi_iterate call: uniform start, 20 (step, finalise) pairs on the
+device, final normalisation, one host synchronisation.
+
+value = 64*480*854 * 20 / (seconds per step), inputs resident in HBM.
+roofline: the fused step kernel alone, timed with HIP events on the stream it
+runs on; its bound is the vector ALU (non-packed FP32 FMA, 78.6 TFLOP/s on
+256 CUs at 2.4 GHz) and its HBM fraction is reported beside it.
+cpu_baseline: the FP64 oracle on a bounded sample of the same voxels.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 78.6: FMA lanes x 2 flop x clock
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(f_np, kern, seconds: float):
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    k = oracle.Kernel(kern.sigma_s, kern.sigma_t, kern.r_s, kern.r_t)
+    x = np.full(f_np.shape, 1.0 / math.sqrt(f_np.size))
+    f64 = f_np.astype(np.float64)
+    rng = np.random.default_rng(0)
+    # a short probe sizes the timed sample to about `seconds` of CPU work
+    idx = rng.integers(0, f_np.size, 2000)
+    t0 = time.perf_counter()
+    oracle.apply_at(f64, x, k, idx)
+    rate = idx.size / max(time.perf_counter() - t0, 1e-6)
+    n = int(min(max(rate * seconds, 2000), 50_000_000))
+    idx = rng.integers(0, f_np.size, n)
+    t0 = time.perf_counter()
+    oracle.apply_at(f64, x, k, idx)
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="voxel-iters/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{n} voxels drawn uniformly from the 64x480x854 clip, one application each "
+                       f"(direct FP64 neighbourhood loop, {(2 * k.r_t + 1) * (2 * k.r_s + 1) ** 2} taps/voxel), "
+                       f"{dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32")
+    ap.add_argument("--kernel-reps", type=int, default=40, help="launches timed for the roofline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(clips shard across GPUs without per-iteration communication; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2212_08058_amd as P
+
+    c = synth.CONFIGS["full"]
+    T, H, W, iters = c["T"], c["H"], c["W"], c["iters"]
+    Nvox = T * H * W
+    kern = P.Kernel(c["sigma_s"], c["sigma_t"], c["r_s"], c["r_t"])
+    dtype = torch.float32 if args.dtype == "f32" else torch.bfloat16
+    elem = 4 if args.dtype == "f32" else 2
+    log(f"generating {T}x{H}x{W} clip")
+    f_np, _ = synth.blob_clip(T, H, W, c["nblobs"], c["seed"])
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        f = torch.from_numpy(f_np).to(dev).to(dtype)
+        x = torch.empty_like(f)
+        ws = torch.empty(P.workspace_bytes(f.shape, kern, dtype), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def one_step():
+        return P.power_iterate(f, kern, iters=iters, x=x, ws=ws, stream=stream)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        _, res = one_step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, res = one_step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    value = Nvox * iters / (dt / args.steps)
+
+    # dominant kernel alone, HIP events on its own stream
+    log("timing the step kernel")
+    z = torch.empty_like(f)
+    xs = x.clone()
+    kern_ms = P.time_step(f, xs, kern, z=z, reps=args.kernel_reps, ws=ws, stream=stream)
+    bytes_per_voxel = 3 * elem
+    flops_per_voxel = 2 * (2 * (2 * kern.r_s + 1) + (2 * kern.r_t + 1)) + 6
+    hbm_gbs = bytes_per_voxel * Nvox / (kern_ms * 1e-3) / 1e9
+    tflops = flops_per_voxel * Nvox / (kern_ms * 1e-3) / 1e12
+
+    out = {
+        "metric": "voxel-iters/s @64x480x854 (%HBM roofline); wall-time to 1e-4, warm vs plain",
+        "value": value,
+        "unit": "voxel-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"single clip {T}x{H}x{W}, {c['nblobs']} moving Gaussian blobs + U[0,0.1] noise (seed "
+                        f"{c['seed']}), sigma_s={c['sigma_s']} sigma_t={c['sigma_t']} r_s={c['r_s']} r_t={c['r_t']}, "
+                        f"{iters} iterations from the uniform start, {args.dtype} storage",
+            "voxels": Nvox,
+            "iters": iters,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": tflops,
+            "peak": VALU_FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": tflops / VALU_FP32_PEAK_TFLOPS,
+            "traffic": None,
+            "kernel": "fwd_step_kernel",
+            "kernel_ms": kern_ms,
+            "flop_per_voxel": flops_per_voxel,
+            "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
+                    "bytes_per_voxel": bytes_per_voxel},
+        },
+        "result": {"residual": res["residual"], "lambda": res["lambda_"], "iters": res["iters"]},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(f_np, kern, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,142 @@
+/*
+ * stpi: space-time power iteration on MI355X (gfx950).
+ *
+ * C ABI of the library libstpi.so. The library computes the principal
+ * eigenvector of the pixel-level space-time affinity matrix
+ *
+ *     A = diag(f) G diag(f),
+ *     G_ij = exp(-dt^2/(2 sigma_t^2) - (dy^2 + dx^2)/(2 sigma_s^2))
+ *            for |dt| <= r_t, |dy| <= r_s, |dx| <= r_s, both voxels inside
+ *            the T x H x W volume (zero padding), 0 otherwise,
+ *
+ * by matrix-free power iteration x <- A x / ||A x||_2. This is the paper's
+ * Gaussian affinity in its first-order form (Sec. 3, Eq. 2) with alpha = 0 and
+ * the unary feature taken as f; the neighbourhood sum of Eq. 4 is evaluated as
+ * the first 3D convolution term of Eq. 7, split into three 1D passes (the
+ * separable filter of Sec. 4.3), followed by the global L2 normalisation of
+ * Eq. 8. The kernel is not normalised: G_ii = 1.
+ *
+ * Conventions for every entry point:
+ *  - Volumes are dense row-major [T][H][W] (W fastest) arrays in DEVICE
+ *    memory, element type given by stpi_problem.dtype. Batched inputs are
+ *    one flat device buffer addressed by per-clip element offsets.
+ *  - The caller owns every buffer and the stream; the library allocates
+ *    nothing on the hot path. `stream` is a hipStream_t passed as void*
+ *    (NULL = the default stream). Calls are asynchronous on that stream
+ *    unless stated otherwise.
+ *  - Arguments are validated on the host before any launch; on error
+ *    nothing is written and a status code is returned. The message of the
+ *    last error on the calling thread is available from stpi_last_error().
+ *  - f must be finite and >= 0 for Perron semantics (not checked on the
+ *    hot path).
+ */
+#ifndef STPI_H
+#define STPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define STPI_OK 0
+#define STPI_EINVAL 1        /* bad argument (checked before any launch)          */
+#define STPI_EUNSUPPORTED 2  /* valid but outside the compiled kernel set         */
+#define STPI_EZERO_NORM 3    /* A x = 0 (e.g. f == 0); x keeps the last iterate   */
+#define STPI_ENONFINITE 4    /* a NaN or Inf appeared in a norm                    */
+#define STPI_EHIP 5          /* HIP runtime error; see stpi_last_error()          */
+#define STPI_EWORKSPACE 6    /* workspace missing or too small                    */
+
+/* Radius limits of the compiled kernels. */
+#define STPI_MAX_RS 16
+#define STPI_MAX_RT 8
+
+/* ---- element types ------------------------------------------------------- */
+#define STPI_F32 0   /* float storage, float arithmetic                          */
+#define STPI_BF16 1  /* bfloat16 storage (RNE on store), float arithmetic        */
+#define STPI_F64 2   /* double storage and arithmetic (gradient checks)          */
+
+/* One clip and its filter. T, H, W >= 1; sigma_s, sigma_t > 0;
+ * 0 <= r_s <= STPI_MAX_RS; 0 <= r_t <= STPI_MAX_RT. */
+typedef struct stpi_problem {
+    int32_t T, H, W;
+    float sigma_s, sigma_t;
+    int32_t r_s, r_t;
+    int32_t dtype;
+} stpi_problem;
+
+/* Outcome of an iteration (host memory). residual is ||x_k - x_{k-1}||_2
+ * between the last two unit iterates; lambda = ||A x_{k-1}|| (tends to the
+ * principal eigenvalue); rayleigh = <x_{k-1}, A x_{k-1}>. flags: bit 0 zero
+ * norm, bit 1 non-finite. Not converging is not an error (converged = 0). */
+typedef struct stpi_result {
+    int32_t iters;
+    int32_t converged;
+    uint32_t flags;
+    int32_t status;
+    double residual;
+    double lambda;
+    double rayleigh;
+} stpi_result;
+
+/* Message for a status code; never NULL. */
+const char *stpi_status_string(int status);
+/* Message of the last error on the calling thread ("" if none). */
+const char *stpi_last_error(void);
+/* Library version string. */
+const char *stpi_version(void);
+
+/* Bytes of device workspace stpi_iterate / stpi_step need for `p` (includes
+ * one volume-sized ping-pong buffer, block partials and the iteration state).
+ * Returns 0 if `p` is invalid. */
+size_t stpi_workspace_bytes(const stpi_problem *p);
+
+/* One application of A (Eq. 4 / Eq. 7 first term), unnormalised:
+ *   z = f .* G * (f .* (x * x_scale)),
+ *   d_sums[0] = sum z^2,  d_sums[1] = sum z .* x * x_scale   (device doubles).
+ * f, x, z: device volumes of p->dtype; z must not alias f or x. d_sums: two
+ * device doubles. ws: workspace of stpi_workspace_bytes(p). */
+int stpi_step(const stpi_problem *p, const void *f, const void *x, double x_scale, void *z,
+              double *d_sums, void *ws, size_t ws_bytes, void *stream);
+
+/* Power iteration (Eq. 4 + Eq. 8, outer loop of Alg. 1).
+ * x (device, in/out): with init = 1 it is overwritten by the uniform start
+ * 1/sqrt(N); with init = 0 it holds the caller's start (normalised first,
+ * must not be zero). On return x holds the last unit iterate.
+ * tol > 0: stop at the first k with ||x_k - x_{k-1}|| < tol, or after
+ * max_iters applications; tol <= 0: exactly max_iters applications.
+ * The iteration runs on the device without host round trips; the call
+ * synchronises `stream` once at the end and fills *out (host). */
+int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int max_iters, double tol,
+                 void *ws, size_t ws_bytes, stpi_result *out, void *stream);
+
+/* ---- kernel variants ------------------------------------------------------
+ * Each storage type has a list of compiled step kernels (radii RS >= r_s,
+ * RT >= r_t, tile TH x TW, NTHR threads, RY rows per y-pass item). By default
+ * the library picks the cheapest eligible one (or the autotuned one). */
+
+/* Number of compiled variants for dtype (0 for an unknown dtype). */
+int stpi_variant_count(int dtype);
+/* info[0..5] = RS, RT, TH, TW, NTHR, RY of variant `index`; STPI_EINVAL if out of range. */
+int stpi_variant_info(int dtype, int index, int32_t info[6]);
+/* Force variant `index` for every later call in the process (-1: automatic
+ * choice). A forced variant whose radii are too small makes calls fail with
+ * STPI_EUNSUPPORTED. Not thread-safe against concurrent launches. */
+int stpi_set_variant(int index);
+
+/* Average duration in milliseconds of the step kernel alone (no reduction
+ * epilogue launch), measured with HIP events recorded on `stream` around
+ * `reps` back-to-back launches of variant `variant` (-1: the variant
+ * stpi_step would use) in single-step mode z = A x. f, x, z are device volumes
+ * as for stpi_step; ws as for stpi_step. Synchronises `stream`. Used by the
+ * benchmark and the autotuner. */
+int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z, void *ws, size_t ws_bytes,
+                   int variant, int reps, void *stream, double *avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STPI_H */

@@ -1,0 +1,7 @@
+"""MI355X-native space-time power iteration (spectral video segmentation hot path).
+
+The compute path is the HIP library libstpi.so (C ABI in include/stpi.h);
+this package only marshals torch tensors (device memory) and streams into it.
+"""
+from .api import Kernel, power_iterate, problem_for, step, time_step, workspace_bytes  # noqa: F401
+from ._native import StpiError  # noqa: F401

@@ -1,0 +1,89 @@
+"""ctypes binding of libstpi.so (argument marshalling only).
+
+The library is the only compute path: if it is missing this module raises at
+import time instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstpi.so")
+
+STPI_OK = 0
+STPI_EINVAL = 1
+STPI_EUNSUPPORTED = 2
+STPI_EZERO_NORM = 3
+STPI_ENONFINITE = 4
+STPI_EHIP = 5
+STPI_EWORKSPACE = 6
+
+STPI_F32 = 0
+STPI_BF16 = 1
+STPI_F64 = 2
+STPI_MAX_RS = 16
+STPI_MAX_RT = 8
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("sigma_s", ctypes.c_float), ("sigma_t", ctypes.c_float),
+                ("r_s", ctypes.c_int32), ("r_t", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("status", ctypes.c_int32), ("residual", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("rayleigh", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, converged=bool(self.converged), flags=self.flags, status=self.status,
+                    residual=self.residual, lambda_=self.lambda_, rayleigh=self.rayleigh)
+
+
+# (name, restype, argtypes); pointers to device memory and streams are void*.
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_PP = ctypes.POINTER(Problem)
+_RP = ctypes.POINTER(Result)
+PROTOTYPES = [
+    ("stpi_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("stpi_last_error", ctypes.c_char_p, []),
+    ("stpi_version", ctypes.c_char_p, []),
+    ("stpi_workspace_bytes", _sz, [_PP]),
+    ("stpi_step", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_iterate", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _sz, _RP, _vp]),
+    ("stpi_variant_count", ctypes.c_int, [ctypes.c_int]),
+    ("stpi_variant_info", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
+    ("stpi_set_variant", ctypes.c_int, [ctypes.c_int]),
+    ("stpi_time_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _sz, ctypes.c_int, ctypes.c_int, _vp,
+                                      ctypes.POINTER(ctypes.c_double)]),
+]
+
+
+class StpiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"stpi error {status}: {message}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libstpi.so not found at {path}: build it with "
+                          f"`python -c 'import __graft_entry__ as g; g.build()'` or paper_2212_08058_amd/build.py")
+    lib = ctypes.CDLL(path)
+    for name, res, args in PROTOTYPES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load()
+
+
+def check(status: int) -> None:
+    if status != STPI_OK:
+        msg = lib.stpi_last_error().decode() or lib.stpi_status_string(status).decode()
+        raise StpiError(status, msg)

@@ -1,0 +1,137 @@
+"""Python entry points over the C ABI: same names and arguments as the C calls."""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _native as N
+
+
+@dataclass(frozen=True)
+class Kernel:
+    """Truncated space-time Gaussian filter: sigmas (pixels, frames) and box radii."""
+    sigma_s: float
+    sigma_t: float
+    r_s: int
+    r_t: int
+
+
+_DTYPES = {torch.float32: N.STPI_F32, torch.bfloat16: N.STPI_BF16, torch.float64: N.STPI_F64}
+
+
+def _dtype_code(dt: torch.dtype) -> int:
+    if dt not in _DTYPES:
+        raise TypeError(f"unsupported dtype {dt}; use float32, bfloat16 or float64")
+    return _DTYPES[dt]
+
+
+def problem_for(shape, k: Kernel, dtype: torch.dtype) -> N.Problem:
+    T, H, W = (int(s) for s in shape)
+    return N.Problem(T, H, W, float(k.sigma_s), float(k.sigma_t), int(k.r_s), int(k.r_t), _dtype_code(dtype))
+
+
+def _check_volume(name: str, t: torch.Tensor, shape=None, dtype=None) -> None:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous [T][H][W]")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def workspace_bytes(shape, k: Kernel, dtype: torch.dtype = torch.float32) -> int:
+    p = problem_for(shape, k, dtype)
+    n = N.lib.stpi_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        N.check(N.STPI_EINVAL)
+    return int(n)
+
+
+def _workspace(shape, k, dtype, device, ws):
+    need = workspace_bytes(shape, k, dtype)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+    elif ws.numel() * ws.element_size() < need:
+        raise ValueError(f"workspace too small: {ws.numel()} < {need} bytes")
+    return ws
+
+
+def step(f: torch.Tensor, x: torch.Tensor, k: Kernel, x_scale: float = 1.0, z: torch.Tensor | None = None,
+         ws: torch.Tensor | None = None, stream=None):
+    """One unnormalised application z = f * G * (f * x * x_scale) (stpi_step).
+
+    Returns (z, sums) with sums a device float64 tensor (sum z^2, sum z x x_scale).
+    """
+    _check_volume("f", f)
+    _check_volume("x", x, f.shape, f.dtype)
+    if z is None:
+        z = torch.empty_like(f)
+    _check_volume("z", z, f.shape, f.dtype)
+    sums = torch.empty(2, dtype=torch.float64, device=f.device)
+    ws = _workspace(f.shape, k, f.dtype, f.device, ws)
+    p = problem_for(f.shape, k, f.dtype)
+    N.check(N.lib.stpi_step(ctypes.byref(p), f.data_ptr(), x.data_ptr(), float(x_scale), z.data_ptr(),
+                            sums.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return z, sums
+
+
+def power_iterate(f: torch.Tensor, k: Kernel, iters: int | None = None, tol: float | None = None,
+                  max_iters: int = 1000, x0: torch.Tensor | None = None, x: torch.Tensor | None = None,
+                  ws: torch.Tensor | None = None, stream=None, check: bool = True):
+    """Power iteration x <- A x / ||A x|| (stpi_iterate).
+
+    iters: exact number of applications; otherwise stop when
+    ||x_k - x_{k-1}|| < tol or after max_iters. x0 (optional) is the start
+    vector (uniform 1/sqrt(N) otherwise). Returns (x, result dict).
+    """
+    _check_volume("f", f)
+    if iters is not None:
+        n_iter, t = int(iters), 0.0
+    else:
+        if tol is None or not tol > 0:
+            raise ValueError("give iters, or tol > 0")
+        n_iter, t = int(max_iters), float(tol)
+    if x is None:
+        x = torch.empty_like(f)
+    _check_volume("x", x, f.shape, f.dtype)
+    init = 1
+    if x0 is not None:
+        _check_volume("x0", x0, f.shape, f.dtype)
+        if x0.data_ptr() != x.data_ptr():
+            x.copy_(x0)
+        init = 0
+    ws = _workspace(f.shape, k, f.dtype, f.device, ws)
+    p = problem_for(f.shape, k, f.dtype)
+    res = N.Result()
+    rc = N.lib.stpi_iterate(ctypes.byref(p), f.data_ptr(), x.data_ptr(), init, n_iter, t, ws.data_ptr(),
+                            ws.numel(), ctypes.byref(res), _stream_ptr(stream))
+    if check:
+        N.check(rc)
+    out = res.as_dict()
+    out["rc"] = rc
+    return x, out
+
+
+def time_step(f: torch.Tensor, x: torch.Tensor, k: Kernel, z: torch.Tensor | None = None, reps: int = 20,
+              variant: int = -1, ws: torch.Tensor | None = None, stream=None) -> float:
+    """Average step-kernel duration in ms over `reps` launches (stpi_time_step, HIP events)."""
+    _check_volume("f", f)
+    _check_volume("x", x, f.shape, f.dtype)
+    if z is None:
+        z = torch.empty_like(f)
+    ws = _workspace(f.shape, k, f.dtype, f.device, ws)
+    p = problem_for(f.shape, k, f.dtype)
+    ms = ctypes.c_double()
+    N.check(N.lib.stpi_time_step(ctypes.byref(p), f.data_ptr(), x.data_ptr(), z.data_ptr(), ws.data_ptr(),
+                                 ws.numel(), int(variant), int(reps), _stream_ptr(stream), ctypes.byref(ms)))
+    return ms.value

@@ -1,0 +1,82 @@
+// Shared device-side types for the stpi kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace stpi {
+
+// bfloat16 storage: the upper 16 bits of an IEEE binary32 value.
+struct bf16 {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ float ld(const float *p) { return *p; }
+__device__ __forceinline__ double ld(const double *p) { return *p; }
+__device__ __forceinline__ float ld(const bf16 *p) {
+    return __uint_as_float(((uint32_t)p->bits) << 16);
+}
+
+// Round-to-nearest-even float -> bfloat16 (NaN stays NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ void st(float *p, float v) { *p = v; }
+__device__ __forceinline__ void st(double *p, double v) { *p = v; }
+__device__ __forceinline__ void st(bf16 *p, float v) { p->bits = f32_to_bf16_bits(v); }
+
+// The value a store of v would leave in memory, read back in compute precision.
+__device__ __forceinline__ float stored_value(const float *, float v) { return v; }
+__device__ __forceinline__ double stored_value(const double *, double v) { return v; }
+__device__ __forceinline__ float stored_value(const bf16 *, float v) {
+    return __uint_as_float(((uint32_t)f32_to_bf16_bits(v)) << 16);
+}
+
+// Compute type for a storage type.
+template <class ST> struct Compute { using type = float; };
+template <> struct Compute<double> { using type = double; };
+
+// Iteration state kept in device memory so that a whole iteration chain runs
+// without host round trips. The stored iterate is unnormalised; the unit
+// iterate is scale * stored.
+struct DevState {
+    double scale;      // 1 / ||stored iterate||
+    double residual;   // ||x_k - x_{k-1}|| of the last step
+    double lambda;     // ||A x_{k-1}||
+    double rayleigh;   // <x_{k-1}, A x_{k-1}>
+    double tol;        // <= 0: run a fixed number of steps
+    int32_t iters;     // applications of A done
+    int32_t done;      // 1: converged or stopped, further steps are no-ops
+    int32_t cur;       // 0: iterate lives in buffer 0 (the caller's x), 1: in buffer 1
+    uint32_t flags;    // bit 0 zero norm, bit 1 non-finite
+    int32_t max_iters;
+    int32_t converged;
+};
+
+constexpr uint32_t FLAG_ZERO = 1u;
+constexpr uint32_t FLAG_NONFINITE = 2u;
+
+// Sum of a double over a workgroup (fixed shuffle/LDS tree: deterministic).
+template <int NTHR>
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    constexpr int NW = NTHR / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) s += lds[i];
+    }
+    return s;  // valid in thread 0 only
+}
+
+}  // namespace stpi

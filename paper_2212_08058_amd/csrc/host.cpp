@@ -1,0 +1,442 @@
+// Host side of libstpi: argument validation, filter taps, kernel selection,
+// workspace layout and the C ABI declared in include/stpi.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/stpi.h"
+#include "dtype_ops.hpp"
+#include "host_internal.hpp"
+
+namespace stpi {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    return fail(STPI_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+const DtypeOps *ops_for(int dtype) {
+    switch (dtype) {
+        case STPI_F32: return dtype_ops_f32();
+        case STPI_BF16: return dtype_ops_bf16();
+        case STPI_F64: return dtype_ops_f64();
+        default: return nullptr;
+    }
+}
+
+int validate_problem(const stpi_problem *p) {
+    if (!p) return fail(STPI_EINVAL, "problem is NULL");
+    if (p->T < 1 || p->H < 1 || p->W < 1)
+        return fail(STPI_EINVAL, "volume must be at least 1x1x1 (got %dx%dx%d)", p->T, p->H, p->W);
+    if (!(p->sigma_s > 0.0f) || !(p->sigma_t > 0.0f) || !std::isfinite(p->sigma_s) || !std::isfinite(p->sigma_t))
+        return fail(STPI_EINVAL, "sigmas must be finite and > 0");
+    if (p->r_s < 0 || p->r_t < 0) return fail(STPI_EINVAL, "radii must be >= 0");
+    if (p->r_s > STPI_MAX_RS || p->r_t > STPI_MAX_RT)
+        return fail(STPI_EUNSUPPORTED, "radii (%d, %d) exceed the compiled maximum (%d, %d)", p->r_s, p->r_t,
+                    STPI_MAX_RS, STPI_MAX_RT);
+    if (!ops_for(p->dtype)) return fail(STPI_EINVAL, "unknown dtype %d", p->dtype);
+    if ((int64_t)p->H * p->W > (int64_t)1 << 30)
+        return fail(STPI_EUNSUPPORTED, "frame of %d x %d voxels is too large", p->H, p->W);
+    return STPI_OK;
+}
+
+// Taps exp(-d^2 / (2 sigma^2)) for |d| <= r, centred at index 16 (space) / 8
+// (time), zero beyond the radius. The centre tap is 1 (unnormalised kernel).
+void make_taps(const stpi_problem *p, double *gs, double *gt) {
+    for (int i = 0; i < 2 * 16 + 1; ++i) gs[i] = 0.0;
+    for (int i = 0; i < 2 * 8 + 1; ++i) gt[i] = 0.0;
+    const double ss = (double)p->sigma_s, stt = (double)p->sigma_t;
+    for (int d = -p->r_s; d <= p->r_s; ++d) gs[d + 16] = std::exp(-(double)(d * d) / (2.0 * ss * ss));
+    for (int d = -p->r_t; d <= p->r_t; ++d) gt[d + 8] = std::exp(-(double)(d * d) / (2.0 * stt * stt));
+}
+
+static double variant_cost(const Variant &v, const stpi_problem *p) {
+    // Taps per voxel plus the y-pass over the x-halo, on the padded tile grid.
+    const double gx = std::ceil((double)p->W / v.TW), gy = std::ceil((double)p->H / v.TH);
+    const double cover = gx * v.TW * gy * v.TH / ((double)p->W * p->H);
+    const double taps = (2.0 * v.RS + 1) * (1.0 + 2.0 * v.RS / v.TW) + (2.0 * v.RS + 1) + (2.0 * v.RT + 1);
+    return taps * cover;
+}
+
+const Variant *choose_variant(const stpi_problem *p, int forced_index) {
+    const DtypeOps *ops = ops_for(p->dtype);
+    if (forced_index >= 0) {
+        if (forced_index >= ops->nvariants) return nullptr;
+        const Variant &v = ops->variants[forced_index];
+        if (v.RS < p->r_s || v.RT < p->r_t) return nullptr;
+        return &v;
+    }
+    int tuned = tuned_variant(p);
+    if (tuned >= 0 && tuned < ops->nvariants) {
+        const Variant &v = ops->variants[tuned];
+        if (v.RS >= p->r_s && v.RT >= p->r_t) return &v;
+    }
+    const Variant *best = nullptr;
+    double best_cost = 1e300;
+    for (int i = 0; i < ops->nvariants; ++i) {
+        const Variant &v = ops->variants[i];
+        if (v.RS < p->r_s || v.RT < p->r_t) continue;
+        const double c = variant_cost(v, p);
+        if (c < best_cost) {
+            best_cost = c;
+            best = &v;
+        }
+    }
+    return best;
+}
+
+int grid_blocks(const Variant &v, const stpi_problem *p) {
+    return ((p->W + v.TW - 1) / v.TW) * ((p->H + v.TH - 1) / v.TH);
+}
+
+// Workspace: [state 256 B][partials][ping-pong volume]. The partials area
+// holds the largest grid any compiled variant can use for this frame size.
+size_t partials_capacity(const stpi_problem *p) {
+    const DtypeOps *ops = ops_for(p->dtype);
+    size_t cap = (size_t)NORM_BLOCKS_HOST;
+    for (int i = 0; i < ops->nvariants; ++i) {
+        const size_t g = (size_t)grid_blocks(ops->variants[i], p);
+        if (g > cap) cap = g;
+    }
+    return cap;
+}
+
+WsLayout layout_for(const stpi_problem *p) {
+    WsLayout L;
+    const DtypeOps *ops = ops_for(p->dtype);
+    const size_t N = (size_t)p->T * p->H * p->W;
+    L.state_off = 0;
+    L.partials_off = 256;
+    L.partials_cap = partials_capacity(p);
+    size_t off = L.partials_off + L.partials_cap * 2 * sizeof(double);
+    off = (off + 255) & ~(size_t)255;
+    L.buf_off = off;
+    L.total = off + ((N * ops->elem + 255) & ~(size_t)255);
+    return L;
+}
+
+static int g_forced_variant = -1;
+
+// Captured iteration chains, keyed by every argument that shapes the launch
+// sequence. Replaying a graph removes the per-launch host overhead of the
+// 2 * max_iters + 3 kernels.
+struct GraphKey {
+    stpi_problem p;
+    const void *f;
+    void *x, *ws;
+    int init, max_iters;
+    double tol;
+    const Variant *v;
+    hipStream_t s;
+    bool operator==(const GraphKey &o) const {
+        return std::memcmp(&p, &o.p, sizeof(p)) == 0 && f == o.f && x == o.x && ws == o.ws && init == o.init &&
+               max_iters == o.max_iters && tol == o.tol && v == o.v && s == o.s;
+    }
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    unsigned long long last_use;
+};
+static std::mutex g_graph_mu;
+static std::vector<GraphEntry> g_graphs;
+static unsigned long long g_graph_clock = 0;
+constexpr size_t GRAPH_CACHE_MAX = 16;
+
+static bool graphs_enabled() {
+    const char *e = std::getenv("STPI_NO_GRAPH");
+    return !(e && e[0] == '1');
+}
+
+int forced_variant() { return g_forced_variant; }
+void set_forced_variant(int v) { g_forced_variant = v; }
+int tuned_variant(const stpi_problem *) { return -1; }
+
+}  // namespace stpi
+
+using namespace stpi;
+
+extern "C" {
+
+const char *stpi_status_string(int status) {
+    switch (status) {
+        case STPI_OK: return "ok";
+        case STPI_EINVAL: return "invalid argument";
+        case STPI_EUNSUPPORTED: return "unsupported problem";
+        case STPI_EZERO_NORM: return "zero norm (A x = 0)";
+        case STPI_ENONFINITE: return "non-finite value";
+        case STPI_EHIP: return "HIP runtime error";
+        case STPI_EWORKSPACE: return "workspace missing or too small";
+        default: return "unknown status";
+    }
+}
+
+const char *stpi_last_error(void) { return g_last_error.c_str(); }
+
+const char *stpi_version(void) { return "stpi 0.1 gfx950"; }
+
+size_t stpi_workspace_bytes(const stpi_problem *p) {
+    if (validate_problem(p) != STPI_OK) return 0;
+    return layout_for(p).total;
+}
+
+int stpi_step(const stpi_problem *p, const void *f, const void *x, double x_scale, void *z, double *d_sums,
+              void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    if (!f || !x || !z || !d_sums) return fail(STPI_EINVAL, "NULL buffer");
+    if (z == f || z == x) return fail(STPI_EINVAL, "z must not alias f or x");
+    if (!std::isfinite(x_scale)) return fail(STPI_EINVAL, "x_scale must be finite");
+    const WsLayout L = layout_for(p);
+    if (!ws || ws_bytes < L.total) return fail(STPI_EWORKSPACE, "workspace needs %zu bytes", L.total);
+    const Variant *v = choose_variant(p, forced_variant());
+    if (!v) return fail(STPI_EUNSUPPORTED, "no compiled kernel for radii (%d, %d)", p->r_s, p->r_t);
+    hipStream_t s = (hipStream_t)stream;
+    FwdLaunch FL;
+    std::memset(&FL, 0, sizeof(FL));
+    FL.f = f;
+    FL.buf0 = const_cast<void *>(x);
+    FL.buf1 = z;
+    FL.state = nullptr;
+    FL.x_scale = x_scale;
+    FL.partials = (double *)((char *)ws + L.partials_off);
+    FL.T = p->T;
+    FL.H = p->H;
+    FL.W = p->W;
+    make_taps(p, FL.gs, FL.gt);
+    hipError_t e = v->launch(FL, s);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+    e = launch_step_sums(FL.partials, grid_blocks(*v, p), x_scale, d_sums, s);
+    if (e != hipSuccess) return hip_fail(e, "step sums launch");
+    return STPI_OK;
+}
+
+int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int max_iters, double tol, void *ws,
+                 size_t ws_bytes, stpi_result *out, void *stream) {
+    clear_error();
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    if (!f || !x || !out) return fail(STPI_EINVAL, "NULL buffer or result");
+    if (f == x) return fail(STPI_EINVAL, "x must not alias f");
+    if (max_iters < 0) return fail(STPI_EINVAL, "max_iters must be >= 0");
+    if (init != 0 && init != 1) return fail(STPI_EINVAL, "init must be 0 (use x) or 1 (uniform)");
+    if (!std::isfinite(tol)) return fail(STPI_EINVAL, "tol must be finite");
+    const WsLayout L = layout_for(p);
+    if (!ws || ws_bytes < L.total) return fail(STPI_EWORKSPACE, "workspace needs %zu bytes", L.total);
+    const Variant *v = choose_variant(p, forced_variant());
+    if (!v) return fail(STPI_EUNSUPPORTED, "no compiled kernel for radii (%d, %d)", p->r_s, p->r_t);
+    std::memset(out, 0, sizeof(*out));
+    hipStream_t s = (hipStream_t)stream;
+    const DtypeOps *ops = ops_for(p->dtype);
+    const size_t N = (size_t)p->T * p->H * p->W;
+    DevState *state = (DevState *)((char *)ws + L.state_off);
+    double *partials = (double *)((char *)ws + L.partials_off);
+    void *buf1 = (char *)ws + L.buf_off;
+
+    if (s != nullptr && graphs_enabled()) {
+        GraphKey key;
+        std::memset(&key, 0, sizeof(key));
+        key.p = *p;
+        key.f = f;
+        key.x = x;
+        key.ws = ws;
+        key.init = init;
+        key.max_iters = max_iters;
+        key.tol = tol;
+        key.v = v;
+        key.s = s;
+        hipGraphExec_t exec = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            for (auto &g : g_graphs)
+                if (g.key == key) {
+                    exec = g.exec;
+                    g.last_use = ++g_graph_clock;
+                    break;
+                }
+        }
+        hipError_t e;
+        if (!exec) {
+            if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(e, "begin capture");
+            rc = enqueue_iteration(p, ops, v, f, x, buf1, state, partials, init, max_iters, tol, s);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(s, &graph);
+            if (rc) {
+                if (graph) hipGraphDestroy(graph);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "end capture");
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            if (g_graphs.size() >= GRAPH_CACHE_MAX) {
+                size_t old = 0;
+                for (size_t i = 1; i < g_graphs.size(); ++i)
+                    if (g_graphs[i].last_use < g_graphs[old].last_use) old = i;
+                hipGraphExecDestroy(g_graphs[old].exec);
+                g_graphs.erase(g_graphs.begin() + old);
+            }
+            g_graphs.push_back(GraphEntry{key, exec, ++g_graph_clock});
+        }
+        if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+    } else {
+        rc = enqueue_iteration(p, ops, v, f, x, buf1, state, partials, init, max_iters, tol, s);
+        if (rc) return rc;
+    }
+
+    DevState hs;
+    hipError_t e = hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "state readback");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    out->iters = hs.iters;
+    out->converged = hs.converged;
+    out->flags = hs.flags;
+    out->residual = hs.residual;
+    out->lambda = hs.lambda;
+    out->rayleigh = hs.rayleigh;
+    out->status = STPI_OK;
+    if (hs.flags & FLAG_NONFINITE) out->status = STPI_ENONFINITE;
+    else if (hs.flags & FLAG_ZERO) out->status = STPI_EZERO_NORM;
+    (void)N;
+    if (out->status != STPI_OK)
+        return fail(out->status, "iteration stopped after %d steps: %s", hs.iters, stpi_status_string(out->status));
+    return STPI_OK;
+}
+
+int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z, void *ws, size_t ws_bytes,
+                   int variant, int reps, void *stream, double *avg_ms) {
+    clear_error();
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    if (!f || !x || !z || !avg_ms) return fail(STPI_EINVAL, "NULL buffer");
+    if (reps < 1) return fail(STPI_EINVAL, "reps must be >= 1");
+    const WsLayout L = layout_for(p);
+    if (!ws || ws_bytes < L.total) return fail(STPI_EWORKSPACE, "workspace needs %zu bytes", L.total);
+    const Variant *v = choose_variant(p, variant >= 0 ? variant : forced_variant());
+    if (!v) return fail(STPI_EUNSUPPORTED, "no eligible kernel variant");
+    hipStream_t s = (hipStream_t)stream;
+    FwdLaunch FL;
+    std::memset(&FL, 0, sizeof(FL));
+    FL.f = f;
+    FL.buf0 = const_cast<void *>(x);
+    FL.buf1 = z;
+    FL.x_scale = 1.0;
+    FL.partials = (double *)((char *)ws + L.partials_off);
+    FL.T = p->T;
+    FL.H = p->H;
+    FL.W = p->W;
+    make_taps(p, FL.gs, FL.gt);
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event create");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(e, "event create");
+    }
+    e = hipEventRecord(e0, s);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = v->launch(FL, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "timed launches");
+    *avg_ms = (double)ms / reps;
+    return STPI_OK;
+}
+
+int stpi_variant_count(int dtype) {
+    const DtypeOps *ops = ops_for(dtype);
+    return ops ? ops->nvariants : 0;
+}
+
+int stpi_variant_info(int dtype, int index, int32_t info[6]) {
+    clear_error();
+    const DtypeOps *ops = ops_for(dtype);
+    if (!ops || !info || index < 0 || index >= ops->nvariants)
+        return fail(STPI_EINVAL, "no variant %d for dtype %d", index, dtype);
+    const Variant &v = ops->variants[index];
+    info[0] = v.RS;
+    info[1] = v.RT;
+    info[2] = v.TH;
+    info[3] = v.TW;
+    info[4] = v.NTHR;
+    info[5] = v.RY;
+    return STPI_OK;
+}
+
+int stpi_set_variant(int index) {
+    clear_error();
+    if (index < -1) return fail(STPI_EINVAL, "variant index must be >= -1");
+    set_forced_variant(index);
+    return STPI_OK;
+}
+
+}  // extern "C"
+
+namespace stpi {
+
+// Enqueues start vector, max_iters (step, finalise) pairs and the final
+// normalisation. No host synchronisation.
+int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
+                      void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,
+                      hipStream_t s) {
+    const size_t N = (size_t)p->T * p->H * p->W;
+    hipError_t e;
+    if (init == 1) {
+        if ((e = ops->fill_ones(x, N, s)) != hipSuccess) return hip_fail(e, "fill");
+        if ((e = launch_state_init(state, 1.0 / std::sqrt((double)N), tol, max_iters, s)) != hipSuccess)
+            return hip_fail(e, "init");
+    } else {
+        if ((e = launch_state_init(state, 1.0, tol, max_iters, s)) != hipSuccess) return hip_fail(e, "init");
+        if ((e = ops->sumsq(x, N, partials, s)) != hipSuccess) return hip_fail(e, "norm");
+        if ((e = launch_state_from_norm(partials, NORM_BLOCKS_HOST, state, s)) != hipSuccess)
+            return hip_fail(e, "init norm");
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init");
+    FwdLaunch FL;
+    std::memset(&FL, 0, sizeof(FL));
+    FL.f = f;
+    FL.buf0 = x;
+    FL.buf1 = buf1;
+    FL.state = state;
+    FL.partials = partials;
+    FL.T = p->T;
+    FL.H = p->H;
+    FL.W = p->W;
+    make_taps(p, FL.gs, FL.gt);
+    const int nb = grid_blocks(*v, p);
+    for (int k = 0; k < max_iters; ++k) {
+        if ((e = v->launch(FL, s)) != hipSuccess) return hip_fail(e, "step kernel launch");
+        if ((e = launch_finalize(partials, nb, state, s)) != hipSuccess) return hip_fail(e, "finalize launch");
+    }
+    if ((e = ops->normalize(x, buf1, N, state, s)) != hipSuccess) return hip_fail(e, "normalize");
+    return STPI_OK;
+}
+
+}  // namespace stpi

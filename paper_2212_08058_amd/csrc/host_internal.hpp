@@ -1,0 +1,43 @@
+// Declarations shared by the host-side translation units of libstpi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstddef>
+
+#include "../../include/stpi.h"
+#include "common.hpp"
+#include "dtype_ops.hpp"
+
+namespace stpi {
+
+constexpr int NORM_BLOCKS_HOST = 512;  // grid of the sum-of-squares pass (matches NORM_BLOCKS)
+
+struct WsLayout {
+    size_t state_off, partials_off, partials_cap, buf_off, total;
+};
+
+int fail(int status, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *where);
+void clear_error();
+const DtypeOps *ops_for(int dtype);
+int validate_problem(const stpi_problem *p);
+void make_taps(const stpi_problem *p, double *gs, double *gt);
+const Variant *choose_variant(const stpi_problem *p, int forced_index);
+int grid_blocks(const Variant &v, const stpi_problem *p);
+WsLayout layout_for(const stpi_problem *p);
+int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
+                      void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,
+                      hipStream_t s);
+
+// Variant selection overrides (autotuner and tests).
+int forced_variant();
+int tuned_variant(const stpi_problem *p);
+
+hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, hipStream_t st);
+hipError_t launch_state_from_norm(const double *partials, int n, DevState *s, hipStream_t st);
+hipError_t launch_finalize(const double *partials, int n, DevState *s, hipStream_t st);
+hipError_t launch_step_sums(const double *partials, int n, double x_scale, double *d_sums, hipStream_t st);
+
+}  // namespace stpi

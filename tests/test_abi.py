@@ -1,0 +1,73 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad arguments on the host before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stpi.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stpi_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2212_08058_amd import _native
+    return _native
+
+
+def test_every_declared_symbol_is_exported(native):
+    syms = declared_symbols()
+    assert len(syms) >= 6
+    for s in syms:
+        assert hasattr(native.lib, s), s
+    # and the binding prototypes cover the header
+    bound = {name for name, _, _ in native.PROTOTYPES}
+    assert set(syms) <= bound, set(syms) - bound
+
+
+def test_status_strings(native):
+    for code in range(7):
+        assert native.lib.stpi_status_string(code)
+    assert native.lib.stpi_status_string(99) == b"unknown status"
+
+
+def _prob(native, **kw):
+    d = dict(T=8, H=64, W=112, sigma_s=2.0, sigma_t=1.0, r_s=4, r_t=2, dtype=0)
+    d.update(kw)
+    return native.Problem(d["T"], d["H"], d["W"], d["sigma_s"], d["sigma_t"], d["r_s"], d["r_t"], d["dtype"])
+
+
+def test_workspace_bytes_and_validation(native):
+    ws = native.lib.stpi_workspace_bytes(ctypes.byref(_prob(native)))
+    assert ws >= 8 * 64 * 112 * 4
+    bf = native.lib.stpi_workspace_bytes(ctypes.byref(_prob(native, dtype=1)))
+    assert bf < ws
+    for bad in (dict(T=0), dict(W=-1), dict(sigma_s=0.0), dict(sigma_t=float("nan")), dict(r_s=-1),
+                dict(r_s=17), dict(r_t=9), dict(dtype=7)):
+        assert native.lib.stpi_workspace_bytes(ctypes.byref(_prob(native, **bad))) == 0, bad
+
+
+def test_invalid_calls_fail_before_any_launch(native):
+    p = _prob(native)
+    res = native.Result()
+    # NULL buffers
+    assert native.lib.stpi_step(ctypes.byref(p), None, None, 1.0, None, None, None, 0, None) == native.STPI_EINVAL
+    assert b"NULL" in native.lib.stpi_last_error()
+    rc = native.lib.stpi_iterate(ctypes.byref(p), 16, 32, 1, 10, 0.0, None, 0, ctypes.byref(res), None)
+    assert rc == native.STPI_EWORKSPACE
+    rc = native.lib.stpi_iterate(ctypes.byref(p), 16, 16, 1, 10, 0.0, 64, 1 << 30, ctypes.byref(res), None)
+    assert rc == native.STPI_EINVAL   # x aliases f
+    rc = native.lib.stpi_iterate(ctypes.byref(p), 16, 32, 2, 10, 0.0, 64, 1 << 30, ctypes.byref(res), None)
+    assert rc == native.STPI_EINVAL   # bad init
+    rc = native.lib.stpi_iterate(ctypes.byref(p), 16, 32, 1, -1, 0.0, 64, 1 << 30, ctypes.byref(res), None)
+    assert rc == native.STPI_EINVAL   # negative count
+    big = _prob(native, r_s=20)
+    rc = native.lib.stpi_iterate(ctypes.byref(big), 16, 32, 1, 1, 0.0, 64, 1 << 30, ctypes.byref(res), None)
+    assert rc == native.STPI_EUNSUPPORTED
