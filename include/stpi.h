@@ -114,13 +114,14 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
 
 /* ---- kernel variants ------------------------------------------------------
  * Each storage type has a list of compiled step kernels (radii RS >= r_s,
- * RT >= r_t, tile TH x TW, NTHR threads, RY rows per y-pass item). By default
+ * RT >= r_t, tile TH x TW, NTHR threads, RY rows per y-pass item, QX outputs
+ * per x-pass item). By default
  * the library picks the cheapest eligible one (or the autotuned one). */
 
 /* Number of compiled variants for dtype (0 for an unknown dtype). */
 int stpi_variant_count(int dtype);
-/* info[0..5] = RS, RT, TH, TW, NTHR, RY of variant `index`; STPI_EINVAL if out of range. */
-int stpi_variant_info(int dtype, int index, int32_t info[6]);
+/* info[0..7] = RS, RT, TH, TW, NTHR, RY, QX, OCC (min waves per SIMD) of variant `index`; STPI_EINVAL if out of range. */
+int stpi_variant_info(int dtype, int index, int32_t info[8]);
 /* Force variant `index` for every later call in the process (-1: automatic
  * choice). A forced variant whose radii are too small makes calls fail with
  * STPI_EUNSUPPORTED. Not thread-safe against concurrent launches. */
@@ -134,6 +135,76 @@ int stpi_set_variant(int index);
  * benchmark and the autotuner. */
 int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z, void *ws, size_t ws_bytes,
                    int variant, int reps, void *stream, double *avg_ms);
+
+/* ---- differentiation path ---------------------------------------------------
+ * The gradient of a loss through the whole normalised iteration ("propagating
+ * the gradient of the loss through the full spectral algorithm", Sec. 1 and
+ * Sec. 3.4), so that per-channel combination weights can be learned end to
+ * end. Iterates live on a tape unnormalised: x_k = z_k / norm_k, with norm_k
+ * a device double. All scalars (norms, inner products, loss) stay in device
+ * memory so the whole forward and backward run without host round trips.
+ * Storage types with adjoint kernels: STPI_F32, STPI_F64. */
+
+#define STPI_MAX_CHANNELS 64
+/* Device workspace the auxiliary reductions (dot, combine_bwd, bce) need. */
+#define STPI_AUX_WS_BYTES (512 * 1024)
+
+/* x0 <- 1 (every voxel), *norm0 <- sqrt(T H W): the uniform unit start
+ * 1/sqrt(N) on the tape (Sec. 4, uniform initialisation). */
+int stpi_train_init(const stpi_problem *p, void *x0, double *norm0, void *stream);
+
+/* One tape step (Eq. 4 + Eq. 8 without the division):
+ *   x = z_in / *norm_in, z_out = f .* G * (f .* x), v_out = G * (f .* x)
+ *   (v_out may be NULL), *norm_out = ||z_out||.
+ * z_out and v_out must not alias the inputs. ws: stpi_workspace_bytes(p). */
+int stpi_train_step(const stpi_problem *p, const void *f, const void *z_in, const double *norm_in, void *z_out,
+                    void *v_out, double *norm_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of tape step k. Inputs: f; z_k, *norm_k (x_k = z_k / norm_k);
+ * z_k1, *norm_k1 (x_{k+1}); v_k = G (f .* x_k) saved by the forward step;
+ * g_k1 = dL/dx_{k+1}; *d_k1 = <x_{k+1}, g_k1>. Outputs:
+ *   g_k = f .* G (f .* g_z),  g_z = (g_k1 - x_{k+1} d_k1) / norm_k1,
+ *   g_f += v_k .* g_z + x_k .* G (f .* g_z)     (accumulated in place),
+ *   *d_k = <x_k, g_k>  (the d of step k - 1).
+ * g_k must not alias another argument. ws: stpi_workspace_bytes(p). */
+int stpi_adjoint_step(const stpi_problem *p, const void *f, const void *z_k, const double *norm_k, const void *z_k1,
+                      const double *norm_k1, const void *v_k, const void *g_k1, const double *d_k1, void *g_k,
+                      void *g_f, double *d_k, void *ws, size_t ws_bytes, void *stream);
+
+/* x = z / *norm over n elements (x may alias z). */
+int stpi_normalize(int64_t n, int dtype, const void *z, const double *norm, void *x, void *stream);
+
+/* *out = <a, b> / (a_norm ? *a_norm : 1) over n elements (double sums of exact
+ * double products). ws: STPI_AUX_WS_BYTES. */
+int stpi_dot(int64_t n, int dtype, const void *a, const double *a_norm, const void *b, double *out, void *ws,
+             size_t ws_bytes, void *stream);
+
+/* Multi-channel combination (the learnable channel weighting of Eq. 9, in the
+ * convex form f = sum_c softmax(w)_c fc_c): fc is [C][n], w holds C double
+ * logits in device memory, f is [n]. 1 <= C <= STPI_MAX_CHANNELS. */
+int stpi_combine_fwd(int C, int64_t n, int dtype, const void *fc, const double *w, void *f, void *stream);
+
+/* g_w[c] (device doubles) = dL/dw_c given g_f = dL/df:
+ * g_a_c = <g_f, fc_c>, g_w = softmax(w) .* (g_a - <softmax(w), g_a>).
+ * ws: STPI_AUX_WS_BYTES. */
+int stpi_combine_bwd(int C, int64_t n, int dtype, const void *fc, const double *w, const void *g_f, double *g_w,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Binary cross-entropy of the soft segmentation against a ground-truth mask:
+ * y = clip(x / max(x), 1e-7, 1 - 1e-7), *loss = mean(-(gt log y + (1 - gt) log(1 - y))),
+ * g_x = dL/dx (clipped entries pass no gradient; the max-normalisation term goes
+ * to the first maximal element). gt: n bytes, 0 or nonzero. ws: STPI_AUX_WS_BYTES. */
+int stpi_bce(int64_t n, int dtype, const void *x, const uint8_t *gt, double *loss, void *g_x, void *ws,
+             size_t ws_bytes, void *stream);
+
+/* AdamW (Eq. 13, decoupled weight decay, with AMSGrad when amsgrad != 0) on n
+ * parameters of dtype STPI_F32 or STPI_F64 in device memory (w, g, m, v, vmax
+ * all of that type), step >= 1 (1-based, for the bias corrections):
+ * w <- w (1 - lr wd); m <- b1 m + (1 - b1) g; v <- b2 v + (1 - b2) g^2;
+ * vmax <- max(vmax, v); w <- w - lr (m / (1 - b1^step)) / (sqrt(vmax / (1 - b2^step)) + eps).
+ * vmax may be NULL when amsgrad == 0. */
+int stpi_adamw(int64_t n, int dtype, void *w, const void *g, void *m, void *v, void *vmax, int step, double lr,
+               double beta1, double beta2, double eps, double weight_decay, int amsgrad, void *stream);
 
 #ifdef __cplusplus
 }

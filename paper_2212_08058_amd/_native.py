@@ -59,7 +59,22 @@ PROTOTYPES = [
     ("stpi_set_variant", ctypes.c_int, [ctypes.c_int]),
     ("stpi_time_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _sz, ctypes.c_int, ctypes.c_int, _vp,
                                       ctypes.POINTER(ctypes.c_double)]),
+    ("stpi_train_init", ctypes.c_int, [_PP, _vp, _vp, _vp]),
+    ("stpi_train_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_adjoint_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_normalize", ctypes.c_int, [ctypes.c_int64, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    ("stpi_dot", ctypes.c_int, [ctypes.c_int64, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_combine_fwd", ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    ("stpi_combine_bwd", ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _sz,
+                                        _vp]),
+    ("stpi_bce", ctypes.c_int, [ctypes.c_int64, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_adamw", ctypes.c_int, [ctypes.c_int64, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, _vp]),
 ]
+
+AUX_WS_BYTES = 512 * 1024
+MAX_CHANNELS = 64
 
 
 class StpiError(RuntimeError):

@@ -1,4 +1,5 @@
 // Non-template kernels of the iteration chain and their host-side launchers.
+#include "aux.hpp"
 #include "chain.hpp"
 #include "host_internal.hpp"
 
@@ -81,6 +82,125 @@ __global__ void step_sums_kernel(const double *partials, int n, double x_scale, 
         d_sums[0] = p2;
         d_sums[1] = x_scale * p1;
     }
+}
+
+// g_a_c = sum of partials; dL/dw = a (g_a - <a, g_a>)  (softmax Jacobian)
+__global__ void combine_bwd_finalize(int C, int nblocks, const double *partials, const double *w, double *gw) {
+    __shared__ double ga[MAX_CHANNELS];
+    __shared__ double red[AUX_THREADS / 64];
+    for (int c = 0; c < C; ++c) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += AUX_THREADS) s += partials[(size_t)b * C + c];
+        const double t = block_sum<AUX_THREADS>(s, red);
+        if (threadIdx.x == 0) ga[c] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a[MAX_CHANNELS];
+        softmax_c(w, C, a);
+        double dot = 0.0;
+        for (int c = 0; c < C; ++c) dot += a[c] * ga[c];
+        for (int c = 0; c < C; ++c) gw[c] = a[c] * (ga[c] - dot);
+    }
+}
+
+// scalars[0] = max, scalars[1] = its first index
+__global__ void max_finalize(int nblocks, const double *partials, double *scalars) {
+    if (threadIdx.x != 0) return;
+    double bv = -1e300, bi = 1e300;
+    for (int b = 0; b < nblocks; ++b) {
+        const double v = partials[2 * b], i = partials[2 * b + 1];
+        if (v > bv || (v == bv && i < bi)) {
+            bv = v;
+            bi = i;
+        }
+    }
+    scalars[0] = bv;
+    scalars[1] = bi;
+}
+
+// out = (sum_b partials[2b]) / (a_norm ? *a_norm : 1)
+__global__ void dot_finalize(const double *partials, int n, const double *a_norm, double *out) {
+    double s0, s1;
+    sum_pairs(partials, n, s0, s1);
+    if (threadIdx.x == 0) *out = a_norm ? s0 / *a_norm : s0;
+}
+
+// out = sqrt(sum_b partials[2b + 1])  (norm of a step's output)
+__global__ void norm_finalize(const double *partials, int n, double *out) {
+    double s0, s1;
+    sum_pairs(partials, n, s0, s1);
+    if (threadIdx.x == 0) *out = sqrt(s1);
+}
+
+// out = sum_b partials[2b]  (the adjoint's <x_k, g_k>)
+__global__ void sum0_finalize(const double *partials, int n, double *out) {
+    double s0, s1;
+    sum_pairs(partials, n, s0, s1);
+    if (threadIdx.x == 0) *out = s0;
+}
+
+hipError_t launch_combine_bwd_finalize(int C, int nblocks, const double *partials, const double *w, double *gw,
+                                       hipStream_t st) {
+    hipLaunchKernelGGL(combine_bwd_finalize, dim3(1), dim3(AUX_THREADS), 0, st, C, nblocks, partials, w, gw);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_finalize(int nblocks, const double *partials, double *scalars, hipStream_t st) {
+    hipLaunchKernelGGL(max_finalize, dim3(1), dim3(64), 0, st, nblocks, partials, scalars);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_finalize(const double *partials, int n, const double *a_norm, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(dot_finalize, dim3(1), dim3(CHAIN_THREADS), 0, st, partials, n, a_norm, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_finalize(const double *partials, int n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(norm_finalize, dim3(1), dim3(CHAIN_THREADS), 0, st, partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum0_finalize(const double *partials, int n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(sum0_finalize, dim3(1), dim3(CHAIN_THREADS), 0, st, partials, n, out);
+    return hipGetLastError();
+}
+
+// AdamW with decoupled weight decay and optional AMSGrad on float master
+// weights (Eq. 13): w <- w (1 - lr wd); m, v moment updates; vmax = max(vmax, v);
+// w <- w - lr (m / bc1) / (sqrt(vmax / bc2) + eps).
+template <class T>
+__global__ void adamw_kernel(int64_t n, T *w, const T *g, T *m, T *v, T *vmax, T lr, T beta1, T beta2, T eps, T wd,
+                             T bc1, T bc2, int amsgrad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T gi = g[i];
+        T wi = w[i] * (T(1) - lr * wd);
+        const T mi = beta1 * m[i] + (T(1) - beta1) * gi;
+        const T vi = beta2 * v[i] + (T(1) - beta2) * gi * gi;
+        T vh = vi;
+        if (amsgrad) {
+            vh = vmax[i] > vi ? vmax[i] : vi;
+            vmax[i] = vh;
+        }
+        wi -= lr * (mi / bc1) / (sqrt(vh / bc2) + eps);
+        m[i] = mi;
+        v[i] = vi;
+        w[i] = wi;
+    }
+}
+
+hipError_t launch_adamw(int dtype, int64_t n, void *w, const void *g, void *m, void *v, void *vmax, double lr,
+                        double beta1, double beta2, double eps, double wd, double bc1, double bc2, int amsgrad,
+                        hipStream_t st) {
+    const int blocks = (int)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    if (dtype == STPI_F64)
+        hipLaunchKernelGGL(adamw_kernel<double>, dim3(blocks), dim3(256), 0, st, n, (double *)w, (const double *)g,
+                           (double *)m, (double *)v, (double *)vmax, lr, beta1, beta2, eps, wd, bc1, bc2, amsgrad);
+    else
+        hipLaunchKernelGGL(adamw_kernel<float>, dim3(blocks), dim3(256), 0, st, n, (float *)w, (const float *)g,
+                           (float *)m, (float *)v, (float *)vmax, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                           (float)wd, (float)bc1, (float)bc2, amsgrad);
+    return hipGetLastError();
 }
 
 hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, hipStream_t st) {

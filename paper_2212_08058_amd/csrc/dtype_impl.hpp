@@ -1,8 +1,9 @@
 // Instantiates the kernel set for one storage type. Included once per type by
 // kernels_<type>.hip with STPI_ST (storage type), STPI_NAME (suffix) and
-// STPI_VARIANTS(X) (the compiled (RS, RT, TH, TW, NTHR, RY) list) defined.
+// STPI_VARIANTS(X) (the compiled (RS, RT, TH, TW, NTHR, RY, QX, OCC) list) defined.
 #pragma once
 
+#include "aux.hpp"
 #include "chain.hpp"
 #include "dtype_ops.hpp"
 
@@ -26,13 +27,68 @@ hipError_t normalize_impl(void *x, const void *buf1, size_t n, const DevState *s
     return hipGetLastError();
 }
 
-#define STPI_VARIANT_ENTRY(RS, RT, TH, TW, NTHR, RY) \
-    {RS, RT, TH, TW, NTHR, RY, &launch_fwd<ST_, RS, RT, TH, TW, NTHR, RY>},
+#define STPI_VARIANT_ENTRY(RS, RT, TH, TW, NTHR, RY, QX, OCC) \
+    {RS, RT, TH, TW, NTHR, RY, QX, OCC, &launch_fwd<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC>},
 
 const Variant kVariants[] = {STPI_VARIANTS(STPI_VARIANT_ENTRY)};
 
-const DtypeOps kOps = {sizeof(ST_), kVariants, (int)(sizeof(kVariants) / sizeof(kVariants[0])),
-                       &fill_ones_impl, &sumsq_impl, &normalize_impl};
+#ifdef STPI_ADJ_VARIANTS
+#define STPI_ADJ_ENTRY(RS, RT, TH, TW, NTHR, RY, QX) \
+    {RS, RT, TH, TW, NTHR, RY, QX, &launch_adj<ST_, RS, RT, TH, TW, NTHR, RY, QX>},
+const AdjVariant kAdj[] = {STPI_ADJ_VARIANTS(STPI_ADJ_ENTRY)};
+constexpr int kNAdj = (int)(sizeof(kAdj) / sizeof(kAdj[0]));
+#else
+const AdjVariant *const kAdj = nullptr;
+constexpr int kNAdj = 0;
+#endif
+
+hipError_t combine_fwd_impl(int C, size_t n, const void *fc, const double *w, void *f, hipStream_t s) {
+    hipLaunchKernelGGL(combine_fwd_kernel<ST_>, dim3(1024), dim3(AUX_THREADS), 0, s, C, n, (const ST_ *)fc, w,
+                       (ST_ *)f);
+    return hipGetLastError();
+}
+hipError_t combine_bwd_impl(int C, size_t n, const void *fc, const void *gf, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(combine_bwd_kernel<ST_>, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, C, n, (const ST_ *)fc,
+                       (const ST_ *)gf, partials);
+    return hipGetLastError();
+}
+hipError_t scale_impl(size_t n, const void *z, const double *norm, void *x, hipStream_t s) {
+    hipLaunchKernelGGL(scale_by_norm_kernel<ST_>, dim3(1024), dim3(AUX_THREADS), 0, s, n, (const ST_ *)z, norm,
+                       (ST_ *)x);
+    return hipGetLastError();
+}
+hipError_t dot_impl(size_t n, const void *a, const void *b, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(dot_kernel<ST_>, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, n, (const ST_ *)a,
+                       (const ST_ *)b, partials);
+    return hipGetLastError();
+}
+hipError_t train_init_impl(size_t n, void *x, double *norm, hipStream_t s) {
+    hipLaunchKernelGGL(train_init_kernel<ST_>, dim3(1024), dim3(AUX_THREADS), 0, s, n, (ST_ *)x, norm);
+    return hipGetLastError();
+}
+hipError_t max_impl(size_t n, const void *x, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(max_kernel<ST_>, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, n, (const ST_ *)x, partials);
+    return hipGetLastError();
+}
+hipError_t bce_impl(size_t n, const void *x, const uint8_t *gt, const double *scalars, void *gx, double *partials,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(bce_kernel<ST_>, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, n, (const ST_ *)x, gt, scalars,
+                       (ST_ *)gx, partials);
+    return hipGetLastError();
+}
+hipError_t bce_fin_impl(size_t n, int nblocks, const double *partials, const double *scalars, void *gx,
+                        double *loss, hipStream_t s) {
+    hipLaunchKernelGGL(bce_finalize<ST_>, dim3(1), dim3(CHAIN_THREADS), 0, s, n, nblocks, partials, scalars,
+                       (ST_ *)gx, loss);
+    return hipGetLastError();
+}
+
+const DtypeOps kOps = {sizeof(ST_),       kVariants,        (int)(sizeof(kVariants) / sizeof(kVariants[0])),
+                       &fill_ones_impl,   &sumsq_impl,      &normalize_impl,
+                       kAdj,              kNAdj,            &combine_fwd_impl,
+                       &combine_bwd_impl, &scale_impl,      &dot_impl,
+                       &train_init_impl,  &max_impl,        &bce_impl,
+                       &bce_fin_impl};
 
 }  // namespace
 

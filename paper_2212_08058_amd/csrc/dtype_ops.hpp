@@ -1,6 +1,7 @@
 // Per-storage-type entry points of the kernel set (one translation unit per type).
 #pragma once
 
+#include "adjoint.hpp"
 #include "forward.hpp"
 
 namespace stpi {
@@ -12,6 +13,19 @@ struct DtypeOps {
     hipError_t (*fill_ones)(void *x, size_t n, hipStream_t);
     hipError_t (*sumsq)(const void *x, size_t n, double *partials, hipStream_t);
     hipError_t (*normalize)(void *x, const void *buf1, size_t n, const DevState *s, hipStream_t);
+    // differentiation path (null where a storage type does not provide it)
+    const AdjVariant *adj_variants;
+    int nadj;
+    hipError_t (*combine_fwd)(int C, size_t n, const void *fc, const double *w, void *f, hipStream_t);
+    hipError_t (*combine_bwd)(int C, size_t n, const void *fc, const void *gf, double *partials, hipStream_t);
+    hipError_t (*scale_by_norm)(size_t n, const void *z, const double *norm, void *x, hipStream_t);
+    hipError_t (*dot)(size_t n, const void *a, const void *b, double *partials, hipStream_t);
+    hipError_t (*train_init)(size_t n, void *x, double *norm, hipStream_t);
+    hipError_t (*maxarg)(size_t n, const void *x, double *partials, hipStream_t);
+    hipError_t (*bce)(size_t n, const void *x, const uint8_t *gt, const double *scalars, void *gx, double *partials,
+                      hipStream_t);
+    hipError_t (*bce_finalize)(size_t n, int nblocks, const double *partials, const double *scalars, void *gx,
+                               double *loss, hipStream_t);
 };
 
 const DtypeOps *dtype_ops_f32();

@@ -12,6 +12,8 @@ struct FwdLaunch {
     void *buf1;          // z (iterate mode: ping-pong buffer 1)
     DevState *state;     // null: single step with x_scale, src = buf0, dst = buf1
     double x_scale;
+    const double *norm_in;  // single step: if set, x_scale = 1 / *norm_in (read on the device)
+    void *vout;             // if set, also store v = G (f x) (x unit) for the adjoint
     double *partials;    // [gridblocks][2] doubles
     int T, H, W;
     double gs[2 * 16 + 1];
@@ -20,7 +22,7 @@ struct FwdLaunch {
 
 // One variant of the step kernel: compiled radii and tile.
 struct Variant {
-    int RS, RT, TH, TW, NTHR, RY;
+    int RS, RT, TH, TW, NTHR, RY, QX, OCC;
     hipError_t (*launch)(const FwdLaunch &, hipStream_t);
 };
 
@@ -33,6 +35,8 @@ struct FwdArgs {
     const DevState *state;
     double *partials;
     double x_scale;
+    const double *norm_in;
+    ST *vout;
     int T, H, W;
     Taps<CT> taps;
 };
@@ -44,27 +48,105 @@ struct FwdArgs {
 template <class ST>
 struct FwdOp {
     using CT = typename Compute<ST>::type;
+    using IO = BufIO<ST>;
+    static constexpr uint32_t ESZ = IO::SZ;
     const ST *f;
     const ST *src;
     ST *dst;
+    ST *vout;         // optional: v = s * acc = G (f x_unit)
     CT scale;
-    __device__ __forceinline__ CT load_u(size_t i) const { return ld(f + i) * ld(src + i); }
-    __device__ __forceinline__ void emit(size_t i, CT acc, double &p1, double &p2) const {
-        const CT z = scale * (ld(f + i) * acc);
-        st(dst + i, z);
-        const double zs = (double)stored_value(dst, z);
-        p2 = fma(zs, zs, p2);
-        p1 = fma(zs, (double)ld(src + i), p1);
+    size_t plane;     // elements per frame
+    uint32_t pbytes;  // bytes per frame
+
+    template <int NPF>
+    struct Raw {
+        CT f[NPF], x[NPF];
+    };
+    template <int NPF>
+    __device__ __forceinline__ void fetch(int t, const uint32_t (&off)[NPF], Raw<NPF> &raw) const {
+        const auto rf = make_rsrc(f + (size_t)t * plane, pbytes);
+        const auto rx = make_rsrc(src + (size_t)t * plane, pbytes);
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) {
+            raw.f[k] = IO::load(rf, off[k]);
+            raw.x[k] = IO::load(rx, off[k]);
+        }
+    }
+    template <int NPF>
+    __device__ __forceinline__ CT input(const Raw<NPF> &raw, int k) const {
+        return raw.f[k] * raw.x[k];
+    }
+    template <int IPT, int QX>
+    struct OutRaw {
+        CT f[IPT][QX], x[IPT][QX];
+    };
+    // Epilogue operands. A group of QX = 4 outputs that lies wholly inside its
+    // row moves with one 4-wide access; groups cut by the right edge of the
+    // frame fall back to single elements with per-element out-of-range offsets.
+    template <int IPT, int QX>
+    __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw) const {
+        const auto rf = make_rsrc(f + (size_t)t * plane, pbytes);
+        const auto rx = make_rsrc(src + (size_t)t * plane, pbytes);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            if constexpr (QX == 4) {
+                if (off[i][3] != OOB) {
+                    IO::load4(rf, off[i][0], raw.f[i]);
+                    IO::load4(rx, off[i][0], raw.x[i]);
+                    continue;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                raw.f[i][q] = IO::load(rf, off[i][q]);
+                raw.x[i][q] = IO::load(rx, off[i][q]);
+            }
+        }
+    }
+    template <int IPT, int QX>
+    __device__ __forceinline__ void emit_frame(int t, const CT (&acc)[IPT][QX], const OutRaw<IPT, QX> &raw,
+                                               const uint32_t (&off)[IPT][QX], double &d1, double &d2) const {
+        const auto rz = make_rsrc(dst + (size_t)t * plane, pbytes);
+        if (vout) {
+            const auto rv = make_rsrc(vout + (size_t)t * plane, pbytes);
+#pragma unroll
+            for (int i = 0; i < IPT; ++i)
+#pragma unroll
+                for (int q = 0; q < QX; ++q) IO::store(rv, off[i][q], scale * acc[i][q]);
+        }
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            CT z[QX];
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                z[q] = scale * (raw.f[i][q] * acc[i][q]);
+                const double zs = (double)IO::rounded(z[q]);
+                d2 = fma(zs, zs, d2);
+                d1 = fma(zs, (double)raw.x[i][q], d1);
+            }
+            if constexpr (QX == 4) {
+                if (off[i][3] != OOB) {
+                    IO::store4(rz, off[i][0], z);
+                    continue;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < QX; ++q) IO::store(rz, off[i][q], z[q]);
+        }
     }
 };
 
-template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY>
-__global__ __launch_bounds__(NTHR) void fwd_step_kernel(FwdArgs<ST> a) {
+// OCC: minimum waves per SIMD the register allocation must allow (1 = no limit).
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC>
+__global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     using CT = typename Compute<ST>::type;
-    using G = Geometry<RS, RT, TH, TW, NTHR, RY>;
-    __shared__ CT lds[2 * TH * G::LW];
+    using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    __shared__ CT lds[G::LDS_ELEMS];
     __shared__ double red[NTHR / 64];
 
+    const int nbx = (a.W + TW - 1) / TW, nby = (a.H + TH - 1) / TH;
+    const int tile = xcd_tile(blockIdx.x, nbx * nby);
+    if (tile < 0) return;
     FwdOp<ST> op;
     op.f = a.f;
     if (a.state) {
@@ -76,21 +158,23 @@ __global__ __launch_bounds__(NTHR) void fwd_step_kernel(FwdArgs<ST> a) {
     } else {
         op.src = a.buf0;
         op.dst = a.buf1;
-        op.scale = (CT)a.x_scale;
+        op.scale = a.norm_in ? (CT)(1.0 / *a.norm_in) : (CT)a.x_scale;
     }
+    op.vout = a.vout;
+    op.plane = (size_t)a.H * a.W;
+    op.pbytes = (uint32_t)(op.plane * sizeof(ST));
     double d1 = 0.0, d2 = 0.0;
-    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
-    stencil_tile<CT, RS, RT, TH, TW, NTHR, RY>(op, a.taps, a.T, a.H, a.W, x0, y0, lds, d1, d2);
+    const int x0 = (tile % nbx) * TW, y0 = (tile / nbx) * TH;
+    stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, a.H, a.W, x0, y0, lds, d1, d2);
     const double s1 = block_sum<NTHR>(d1, red);
     const double s2 = block_sum<NTHR>(d2, red);
     if (threadIdx.x == 0) {
-        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        a.partials[2 * b] = s1;
-        a.partials[2 * b + 1] = s2;
+        a.partials[2 * tile] = s1;
+        a.partials[2 * tile + 1] = s2;
     }
 }
 
-template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY>
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC>
 hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     using CT = typename Compute<ST>::type;
     FwdArgs<ST> a;
@@ -100,6 +184,8 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     a.state = L.state;
     a.partials = L.partials;
     a.x_scale = L.x_scale;
+    a.norm_in = L.norm_in;
+    a.vout = (ST *)L.vout;
     a.T = L.T;
     a.H = L.H;
     a.W = L.W;
@@ -109,8 +195,10 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     for (int i = 0; i < 2 * 8 + 1; ++i) a.taps.gt[i] = CT(0);
     for (int d = -RS; d <= RS; ++d) a.taps.gs[d + RS] = (CT)L.gs[d + 16];
     for (int d = -RT; d <= RT; ++d) a.taps.gt[d + RT] = (CT)L.gt[d + 8];
-    dim3 grid((L.W + TW - 1) / TW, (L.H + TH - 1) / TH);
-    hipLaunchKernelGGL((fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY>), grid, dim3(NTHR), 0, stream, a);
+    const int ntiles = ((L.W + TW - 1) / TW) * ((L.H + TH - 1) / TH);
+    const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+    hipLaunchKernelGGL((fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC>), dim3(per * NUM_XCD), dim3(NTHR), 0,
+                       stream, a);
     return hipGetLastError();
 }
 

@@ -118,6 +118,11 @@ size_t partials_capacity(const stpi_problem *p) {
         const size_t g = (size_t)grid_blocks(ops->variants[i], p);
         if (g > cap) cap = g;
     }
+    for (int i = 0; i < ops->nadj; ++i) {
+        const AdjVariant &v = ops->adj_variants[i];
+        const size_t g = (size_t)(((p->W + v.TW - 1) / v.TW) * ((p->H + v.TH - 1) / v.TH));
+        if (g > cap) cap = g;
+    }
     return cap;
 }
 
@@ -284,19 +289,19 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(s, &graph);
             if (rc) {
-                if (graph) hipGraphDestroy(graph);
+                if (graph) (void)hipGraphDestroy(graph);
                 return rc;
             }
             if (e != hipSuccess) return hip_fail(e, "end capture");
             e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return hip_fail(e, "graph instantiate");
             std::lock_guard<std::mutex> lk(g_graph_mu);
             if (g_graphs.size() >= GRAPH_CACHE_MAX) {
                 size_t old = 0;
                 for (size_t i = 1; i < g_graphs.size(); ++i)
                     if (g_graphs[i].last_use < g_graphs[old].last_use) old = i;
-                hipGraphExecDestroy(g_graphs[old].exec);
+                (void)hipGraphExecDestroy(g_graphs[old].exec);
                 g_graphs.erase(g_graphs.begin() + old);
             }
             g_graphs.push_back(GraphEntry{key, exec, ++g_graph_clock});
@@ -354,7 +359,7 @@ int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z,
     hipError_t e;
     if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event create");
     if ((e = hipEventCreate(&e1)) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return hip_fail(e, "event create");
     }
     e = hipEventRecord(e0, s);
@@ -363,8 +368,8 @@ int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z,
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "timed launches");
     *avg_ms = (double)ms / reps;
     return STPI_OK;
@@ -375,7 +380,7 @@ int stpi_variant_count(int dtype) {
     return ops ? ops->nvariants : 0;
 }
 
-int stpi_variant_info(int dtype, int index, int32_t info[6]) {
+int stpi_variant_info(int dtype, int index, int32_t info[8]) {
     clear_error();
     const DtypeOps *ops = ops_for(dtype);
     if (!ops || !info || index < 0 || index >= ops->nvariants)
@@ -387,6 +392,8 @@ int stpi_variant_info(int dtype, int index, int32_t info[6]) {
     info[3] = v.TW;
     info[4] = v.NTHR;
     info[5] = v.RY;
+    info[6] = v.QX;
+    info[7] = v.OCC;
     return STPI_OK;
 }
 

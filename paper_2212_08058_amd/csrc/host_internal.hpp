@@ -39,5 +39,14 @@ hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iter
 hipError_t launch_state_from_norm(const double *partials, int n, DevState *s, hipStream_t st);
 hipError_t launch_finalize(const double *partials, int n, DevState *s, hipStream_t st);
 hipError_t launch_step_sums(const double *partials, int n, double x_scale, double *d_sums, hipStream_t st);
+hipError_t launch_combine_bwd_finalize(int C, int nblocks, const double *partials, const double *w, double *gw,
+                                       hipStream_t st);
+hipError_t launch_max_finalize(int nblocks, const double *partials, double *scalars, hipStream_t st);
+hipError_t launch_dot_finalize(const double *partials, int n, const double *a_norm, double *out, hipStream_t st);
+hipError_t launch_norm_finalize(const double *partials, int n, double *out, hipStream_t st);
+hipError_t launch_sum0_finalize(const double *partials, int n, double *out, hipStream_t st);
+hipError_t launch_adamw(int dtype, int64_t n, void *w, const void *g, void *m, void *v, void *vmax, double lr,
+                        double beta1, double beta2, double eps, double wd, double bc1, double bc2, int amsgrad,
+                        hipStream_t st);
 
 }  // namespace stpi

@@ -2,68 +2,249 @@
 //
 // One workgroup owns a TH x TW output tile of every frame and streams along
 // the time axis. For each input frame it
-//   1. y-pass: each work item owns one halo-extended column strip, loads the
-//      RY + 2RS input values it needs straight from global memory (coalesced
-//      across the wavefront along x), forms the pass input u with the
-//      operation's prologue (e.g. u = f * x), and writes the RY vertically
-//      filtered values to LDS;
-//   2. x-pass: each thread owns IPT groups of QX consecutive outputs of one
-//      row and filters horizontally from a 16-byte aligned LDS window;
-//   3. t-pass: scatters the 2D-filtered values into 2RT+1 rotating register
-//      accumulators (one per output frame the input frame contributes to).
+//   0. (one frame ahead) loads the halo-extended (TH+2RS) x (TW+2RS) input
+//      tile with raw buffer loads into registers; out-of-volume offsets fall
+//      outside the buffer range and read as 0, which is exactly the zero
+//      padding of the operator;
+//   1. forms the pass input u with the operation's prologue (u = f * x for
+//      the forward step) and stores it to LDS;
+//   2. y-pass: each work item filters RY rows of one halo column from LDS and
+//      writes them to a second LDS tile;
+//   3. x-pass: each thread filters QX consecutive outputs of a row;
+//   4. t-pass: scatters those values into 2RT+1 rotating register
+//      accumulators, one per output frame the input frame contributes to.
 // When the accumulator of frame t - RT is complete it goes through the
-// operation's epilogue (e.g. z = s * f * acc, store, reduction partials).
+// operation's epilogue (z = s * f * acc for the forward step, the store and
+// the reduction partials).
 //
-// The y-halo is consumed by the y-pass itself, so the only redundant work is
-// the y-pass over the 2RS halo columns of the x-pass. Zero padding is exact:
-// out-of-volume inputs contribute 0 and the time stream runs RT frames past
-// the end. Every frame is updated (no edge frames are left out).
+// Only the small t-scatter/epilogue is specialised per ring position (a
+// switch over t mod (2RT+1)), so the code stays compact. Tiles are handed to
+// workgroups so that each XCD (workgroups are dealt round-robin over the 8
+// XCDs) owns a contiguous band of tile rows: the y-halo rows that adjacent
+// tiles share are then read through the same L2.
 #pragma once
 
 #include "common.hpp"
 
 namespace stpi {
 
-constexpr int QX = 4;  // consecutive x outputs per thread item (one 16-byte LDS chunk)
+constexpr int NUM_XCD = 8;
+constexpr uint32_t OOB = 0xFFFFFFF0u;  // byte offset that lies outside every buffer
 
 template <class CT>
 struct Taps {
-    CT gs[2 * 16 + 1];  // spatial taps g(-r_s..r_s), zero beyond the radius
-    CT gt[2 * 8 + 1];   // temporal taps g(-r_t..r_t)
+    CT gs[2 * 16 + 1];  // spatial taps g(-RS..RS) of the compiled radius, zero beyond r_s
+    CT gt[2 * 8 + 1];   // temporal taps g(-RT..RT)
+};
+
+// Raw buffer resource over `bytes` bytes at `base`; loads beyond the range
+// return 0 and stores beyond it are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <class ST>
+struct BufIO;
+
+template <>
+struct BufIO<float> {
+    static constexpr uint32_t SZ = 4;
+    __device__ static __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+    }
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, boff, 0, 0);
+    }
+    __device__ static __forceinline__ float rounded(float v) { return v; }
+    // four consecutive elements (offset need only be element-aligned)
+    __device__ static __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, uint32_t boff, float (&v)[4]) {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = __uint_as_float(t[e]);
+    }
+    __device__ static __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, uint32_t boff, const float (&v)[4]) {
+        using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+        V4 t;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = __float_as_uint(v[e]);
+        __builtin_amdgcn_raw_buffer_store_b128(t, r, boff, 0, 0);
+    }
+};
+
+template <>
+struct BufIO<bf16> {
+    static constexpr uint32_t SZ = 2;
+    __device__ static __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+        return __uint_as_float(((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, boff, 0, 0)) << 16);
+    }
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_bits(v), r, boff, 0, 0);
+    }
+    __device__ static __forceinline__ float rounded(float v) {
+        return __uint_as_float(((uint32_t)f32_to_bf16_bits(v)) << 16);
+    }
+    __device__ static __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, uint32_t boff, float (&v)[4]) {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0);
+        v[0] = __uint_as_float(t[0] << 16);
+        v[1] = __uint_as_float(t[0] & 0xffff0000u);
+        v[2] = __uint_as_float(t[1] << 16);
+        v[3] = __uint_as_float(t[1] & 0xffff0000u);
+    }
+    __device__ static __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, uint32_t boff, const float (&v)[4]) {
+        using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        V2 t;
+        t[0] = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
+        t[1] = (uint32_t)f32_to_bf16_bits(v[2]) | ((uint32_t)f32_to_bf16_bits(v[3]) << 16);
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, boff, 0, 0);
+    }
+};
+
+template <>
+struct BufIO<double> {
+    static constexpr uint32_t SZ = 8;
+    __device__ static __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+    }
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t boff, double v) {
+        using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, boff, 0, 0);
+    }
+    __device__ static __forceinline__ double rounded(double v) { return v; }
+    __device__ static __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, uint32_t boff, double (&v)[4]) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = load(r, boff + 8 * e);
+    }
+    __device__ static __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, uint32_t boff, const double (&v)[4]) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) store(r, boff + 8 * e, v[e]);
+    }
+};
+
+// 16-byte vector of LDS elements.
+template <class CT>
+struct LdsVec {
+    static constexpr int N = 16 / (int)sizeof(CT);
+    typedef CT type __attribute__((ext_vector_type(16 / sizeof(CT))));
 };
 
 // Tile geometry derived from the template parameters.
-template <int RS, int RT, int TH, int TW, int NTHR, int RY>
+template <int RS, int RT, int TH, int TW, int NTHR, int RY, int QX>
 struct Geometry {
-    static constexpr int RSA = (RS + 3) & ~3;      // LDS halo, rounded for 16-byte alignment
-    static constexpr int NC = TW + 2 * RS;         // columns the y-pass produces
-    static constexpr int LW = TW + 2 * RSA;        // LDS row length
-    static constexpr int NRG = TH / RY;            // row groups per column in the y-pass
-    static constexpr int NYI = NC * NRG;           // y-pass work items
-    static constexpr int NQ = TW / QX;             // x groups per row
-    static constexpr int NXI = TH * NQ;            // x-pass work items
-    static constexpr int IPT = NXI / NTHR;         // x-pass items per thread
-    static constexpr int NTS = 2 * RT + 1;         // temporal accumulator ring
+    static constexpr int RSA = (RS + 3) & ~3;           // LDS halo of the y-pass output, 16-byte aligned
+    static constexpr int NC = TW + 2 * RS;              // columns of the input tile
+    static constexpr int NR = TH + 2 * RS;              // rows of the input tile
+    static constexpr int NU = NR * NC;                  // input tile elements
+    static constexpr int NPF = (NU + NTHR - 1) / NTHR;  // prefetched elements per thread
+    static constexpr int LW = TW + 2 * RSA;             // row length of the y-pass output tile
+    static constexpr int NRG = TH / RY;                 // row groups per column in the y-pass
+    static constexpr int NYI = NC * NRG;                // y-pass work items
+    static constexpr int NQ = TW / QX;                  // x groups per row
+    static constexpr int NXI = TH * NQ;                 // x-pass work items
+    static constexpr int IPT = (NXI + NTHR - 1) / NTHR; // x-pass items per thread
+    static constexpr int NTS = 2 * RT + 1;              // temporal accumulator ring
+    static constexpr int NUP = (NU + 3) & ~3;           // Y starts 16-byte aligned
+    static constexpr int LDS_ELEMS = NUP + TH * LW;
     static_assert(TH % RY == 0, "RY must divide TH");
     static_assert(TW % QX == 0, "QX must divide TW");
-    static_assert(NXI % NTHR == 0, "x-pass items must be a multiple of the workgroup size");
     static_assert(NTHR % 64 == 0, "whole wavefronts");
 };
 
-// Streams one tile through all frames. Op provides
-//   CT   load_u(size_t idx)                       pass input at a voxel
-//   void emit(size_t idx, CT acc, double &p1, double &p2)
-//                                                 epilogue at an output voxel,
-//                                                 adding to the per-thread sums
-// d1, d2 (double).
-template <class CT, int RS, int RT, int TH, int TW, int NTHR, int RY, class Op>
-__device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, int T, int H, int W,
-                                             int x0, int y0, CT *lds, double &d1, double &d2) {
-    using G = Geometry<RS, RT, TH, TW, NTHR, RY>;
-    constexpr int RSA = G::RSA, NC = G::NC, LW = G::LW, NYI = G::NYI, NQ = G::NQ;
-    constexpr int IPT = G::IPT, NTS = G::NTS;
+// Maps a workgroup to its tile so that each XCD owns a contiguous band of
+// tiles (row-major tile order). Returns -1 for workgroups past the last tile.
+__device__ __forceinline__ int xcd_tile(int block, int ntiles) {
+    const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+    const int t = (block % NUM_XCD) * per + block / NUM_XCD;
+    return t < ntiles ? t : -1;
+}
+
+// Adds g * v into ring slot SLOT (compile-time index, so the ring stays in
+// registers).
+template <int SLOT, class CT, int NTS, int IPT, int QX>
+__device__ __forceinline__ void ring_fma(CT (&acc)[NTS][IPT][QX], const CT (&v)[IPT][QX], CT g) {
+#pragma unroll
+    for (int i = 0; i < IPT; ++i)
+#pragma unroll
+        for (int q = 0; q < QX; ++q) acc[SLOT][i][q] = fma(g, v[i][q], acc[SLOT][i][q]);
+}
+
+// Input frame at ring position J feeds output frames tin - dt, dt in [-RT, RT].
+template <int J, int DT, int RT, class CT, int IPT, int QX>
+__device__ __forceinline__ void ring_scatter(CT (&acc)[2 * RT + 1][IPT][QX], const CT (&v)[IPT][QX],
+                                             const Taps<CT> &tp) {
+    if constexpr (DT <= RT) {
+        constexpr int NTS = 2 * RT + 1;
+        ring_fma<((J - DT) % NTS + NTS) % NTS>(acc, v, tp.gt[DT + RT]);
+        ring_scatter<J, DT + 1, RT>(acc, v, tp);
+    }
+}
+
+// t-scatter of one input frame at ring position J, then the epilogue of the
+// output frame tin - RT (or, before the clip starts, only clearing its slot:
+// it collected contributions to a frame that does not exist).
+template <int J, class CT, int RT, int IPT, int QX, class Op, class ORaw>
+__device__ __forceinline__ void ring_step(CT (&acc)[2 * RT + 1][IPT][QX], const CT (&v)[IPT][QX],
+                                          const Taps<CT> &tp, bool scatter, int tin, const Op &op,
+                                          const uint32_t (&ooff)[IPT][QX], const ORaw &oraw, double &d1,
+                                          double &d2) {
+    constexpr int NTS = 2 * RT + 1;
+    if (scatter) ring_scatter<J, -RT, RT>(acc, v, tp);
+    constexpr int es = ((J - RT) % NTS + NTS) % NTS;
+    if (tin >= RT) op.emit_frame(tin - RT, acc[es], oraw, ooff, d1, d2);
+#pragma unroll
+    for (int i = 0; i < IPT; ++i)
+#pragma unroll
+        for (int q = 0; q < QX; ++q) acc[es][i][q] = CT(0);
+}
+
+// Streams one tile through all frames. Op (forward step or adjoint step)
+// provides, with ESZ its element size in bytes:
+//   template <int NPF> struct Raw                 raw prefetched operands
+//   template <int NPF> void fetch(int t, const uint32_t (&boff)[NPF], Raw<NPF> &raw)
+//       issue the loads of frame t at in-frame byte offsets (OOB offsets give 0)
+//   template <int NPF> CT input(const Raw<NPF> &raw, int k)
+//       pass input u of prefetched element k (e.g. f * x)
+//   template <int IPT, int QX> struct OutRaw      operands the epilogue reads
+//   template <int IPT, int QX> void fetch_out(int t, const uint32_t (&boff)[IPT][QX],
+//       OutRaw<IPT, QX> &raw)  issue the epilogue's loads of output frame t early
+//   template <int IPT, int QX> void emit_frame(int t, const CT (&acc)[IPT][QX],
+//       const OutRaw<IPT, QX> &raw, const uint32_t (&boff)[IPT][QX], double &d1, double &d2)
+//       epilogue of output frame t (OOB offsets are dropped stores, zero sums)
+template <class CT, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, class Op>
+__device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, int T, int H, int W, int x0,
+                                             int y0, CT *lds, double &d1, double &d2) {
+    using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    constexpr int NC = G::NC, NU = G::NU, NPF = G::NPF, LW = G::LW, RSA = G::RSA;
+    constexpr int NYI = G::NYI, NQ = G::NQ, NXI = G::NXI, IPT = G::IPT, NTS = G::NTS;
+    constexpr uint32_t ESZ = Op::ESZ;
     const int tid = threadIdx.x;
-    const size_t plane = (size_t)H * W;
+    CT *U = lds;       // [NR][NC] pass input
+    CT *Y = lds + G::NUP;  // [TH][LW] y-filtered, 16-byte aligned rows
+
+    // In-frame byte offsets of the input elements this thread stages.
+    uint32_t poff[NPF];
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+        const int e = tid + k * NTHR;
+        const int r = e / NC, c = e % NC;
+        const int gy = y0 - RS + r, gx = x0 - RS + c;
+        const bool ok = e < NU && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+        poff[k] = ok ? (uint32_t)(gy * W + gx) * ESZ : OOB;
+    }
+    // Output voxels owned by this thread in the x-pass and epilogue.
+    uint32_t ooff[IPT][QX];
+    int orow[IPT], ocol[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int item = tid + i * NTHR;
+        const bool live = item < NXI;
+        orow[i] = live ? item / NQ : 0;
+        ocol[i] = live ? (item % NQ) * QX : 0;
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int gy = y0 + orow[i], gx = x0 + ocol[i] + q;
+            ooff[i][q] = (live && gy < H && gx < W) ? (uint32_t)(gy * W + gx) * ESZ : OOB;
+        }
+    }
 
     CT acc[NTS][IPT][QX];
 #pragma unroll
@@ -73,94 +254,84 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
 #pragma unroll
             for (int q = 0; q < QX; ++q) acc[s][i][q] = CT(0);
 
-    // Output positions owned by this thread in the x-pass / epilogue.
-    int orow[IPT], ocol[IPT];
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const int item = tid + i * NTHR;
-        orow[i] = item / NQ;
-        ocol[i] = (item % NQ) * QX;
-    }
+    typename Op::template Raw<NPF> pf;
+    op.template fetch<NPF>(0, poff, pf);
 
+    typename Op::template OutRaw<IPT, QX> oraw;
     const int tend = T + RT;
-    for (int tb = 0; tb < tend; tb += NTS) {
+    for (int tin = 0; tin < tend; ++tin) {
+        CT v[IPT][QX];
+        const bool live = tin < T;
+        // the epilogue's operands load while this frame is filtered
+        if (tin >= RT) op.template fetch_out<IPT, QX>(tin - RT, ooff, oraw);
+        if (live) {
+            // stage this frame's prefetched input, then prefetch the next one
 #pragma unroll
-        for (int j = 0; j < NTS; ++j) {
-            const int tin = tb + j;
-            if (tin >= tend) break;
-            if (tin < T) {
-                CT *buf = lds + (tin & 1) * (TH * LW);
-                const size_t foff = (size_t)tin * plane;
-                // ---- y-pass: global -> registers -> LDS
-                for (int it = tid; it < NYI; it += NTHR) {
-                    const int c = it % NC;
-                    const int g = it / NC;
-                    const int gx = x0 - RS + c;
-                    const bool colok = (unsigned)gx < (unsigned)W;
-                    const int ybase = y0 + g * RY - RS;
-                    CT u[RY + 2 * RS];
+            for (int k = 0; k < NPF; ++k) {
+                const int e = tid + k * NTHR;
+                if (NU % NTHR == 0 || k < NPF - 1 || e < NU) U[e] = op.template input<NPF>(pf, k);
+            }
+            if (tin + 1 < T) op.template fetch<NPF>(tin + 1, poff, pf);
+            __syncthreads();
+            // y-pass
+            for (int it = tid; it < NYI; it += NTHR) {
+                const int c = it % NC;
+                const int g = it / NC;
+                const CT *col = U + (g * RY) * NC + c;
+                CT u[RY + 2 * RS];
 #pragma unroll
-                    for (int k = 0; k < RY + 2 * RS; ++k) {
-                        const int gy = ybase + k;
-                        CT v = CT(0);
-                        if (colok && (unsigned)gy < (unsigned)H) v = op.load_u(foff + (size_t)gy * W + gx);
-                        u[k] = v;
-                    }
-                    CT *dstp = buf + (g * RY) * LW + c + (RSA - RS);
+                for (int k = 0; k < RY + 2 * RS; ++k) u[k] = col[k * NC];
+                CT *dstp = Y + (g * RY) * LW + c + (RSA - RS);
 #pragma unroll
-                    for (int r = 0; r < RY; ++r) {
-                        CT s = CT(0);
+                for (int r = 0; r < RY; ++r) {
+                    CT s = CT(0);
 #pragma unroll
-                        for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], u[r + d], s);
-                        dstp[r * LW] = s;
-                    }
-                }
-                __syncthreads();
-                // ---- x-pass: LDS -> registers, then t-scatter into the ring
-#pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    const CT *rowp = buf + orow[i] * LW + ocol[i];
-                    CT w[QX + 2 * RSA];
-#pragma unroll
-                    for (int k = 0; k < QX + 2 * RSA; ++k) w[k] = rowp[k];
-#pragma unroll
-                    for (int q = 0; q < QX; ++q) {
-                        CT s = CT(0);
-#pragma unroll
-                        for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], w[q + d + RSA - RS], s);
-                        // input frame tin feeds output frames tin - dt, dt in [-RT, RT]
-#pragma unroll
-                        for (int dt = -RT; dt <= RT; ++dt) {
-                            const int slot = ((j - dt) % NTS + NTS) % NTS;
-                            acc[slot][i][q] = fma(tp.gt[dt + RT], s, acc[slot][i][q]);
-                        }
-                    }
+                    for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], u[r + d], s);
+                    dstp[r * LW] = s;
                 }
             }
-            // ---- epilogue for the completed output frame tin - RT. For tin < RT
-            // that frame lies before the clip: its slot only collected
-            // contributions to a non-existent output and is cleared for reuse.
-            if (tin < RT) {
-                const int slot = ((j - RT) % NTS + NTS) % NTS;
+            __syncthreads();
+            // x-pass
 #pragma unroll
-                for (int i = 0; i < IPT; ++i)
+            for (int i = 0; i < IPT; ++i) {
+                // 16-byte LDS reads: rows of Y and the window start are aligned
+                using V4 = LdsVec<CT>;
+                constexpr int NV = (QX + 2 * RSA) / V4::N;
+                const typename V4::type *rowp = reinterpret_cast<const typename V4::type *>(
+                    __builtin_assume_aligned(Y + orow[i] * LW + ocol[i], 16));
+                CT w[QX + 2 * RSA];
 #pragma unroll
-                    for (int q = 0; q < QX; ++q) acc[slot][i][q] = CT(0);
-            } else {
-                const int tout = tin - RT;
-                const int slot = ((j - RT) % NTS + NTS) % NTS;
-                const size_t foff = (size_t)tout * plane;
+                for (int k = 0; k < NV; ++k) {
+                    const typename V4::type t = rowp[k];
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    const int gy = y0 + orow[i];
+                    for (int e = 0; e < V4::N; ++e) w[k * V4::N + e] = t[e];
+                }
 #pragma unroll
-                    for (int q = 0; q < QX; ++q) {
-                        const int gx = x0 + ocol[i] + q;
-                        if (gy < H && gx < W) op.emit(foff + (size_t)gy * W + gx, acc[slot][i][q], d1, d2);
-                        acc[slot][i][q] = CT(0);
-                    }
+                for (int q = 0; q < QX; ++q) {
+                    CT s = CT(0);
+#pragma unroll
+                    for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], w[q + d + RSA - RS], s);
+                    v[i][q] = s;
                 }
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < IPT; ++i)
+#pragma unroll
+                for (int q = 0; q < QX; ++q) v[i][q] = CT(0);
+        }
+        // ring position of this frame; a switch (not a call chain) keeps the
+        // accumulators in registers
+        switch (tin % NTS) {
+#define STPI_RING_CASE(J)                                                                           \
+    case J:                                                                                         \
+        if constexpr (J < NTS) ring_step<J, CT, RT, IPT, QX>(acc, v, tp, live, tin, op, ooff, oraw, d1, d2); \
+        break;
+            STPI_RING_CASE(0) STPI_RING_CASE(1) STPI_RING_CASE(2) STPI_RING_CASE(3) STPI_RING_CASE(4)
+            STPI_RING_CASE(5) STPI_RING_CASE(6) STPI_RING_CASE(7) STPI_RING_CASE(8) STPI_RING_CASE(9)
+            STPI_RING_CASE(10) STPI_RING_CASE(11) STPI_RING_CASE(12) STPI_RING_CASE(13) STPI_RING_CASE(14)
+            STPI_RING_CASE(15) STPI_RING_CASE(16)
+#undef STPI_RING_CASE
         }
     }
 }

@@ -1,0 +1,236 @@
+"""GPU parity of the differentiation path (channel combination, tape steps,
+adjoint steps, BCE, AdamW) against the FP64 oracle, plus finite differences
+and torch.autograd.gradcheck in FP64."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import Kernel as OK
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2212_08058_amd as P
+    from paper_2212_08058_amd import learn
+    return P, learn
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def okf(k):
+    return OK(float(np.float32(k.sigma_s)), float(np.float32(k.sigma_t)), k.r_s, k.r_t)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV).to(dtype)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-6), (torch.float64, 1e-14)])
+def test_combine_forward_backward(P, dtype, tol):
+    _, learn = P
+    from paper_2212_08058_amd import _native as N
+    rng = np.random.default_rng(0)
+    C, shape = 8, (3, 37, 41)
+    fc = rng.uniform(0, 1, (C,) + shape)
+    w = rng.standard_normal(C)
+    f = learn.combine(dev(fc, dtype), dev(w, torch.float64))
+    assert rel(f.double().cpu().numpy(), oracle.combine(fc, w)) < tol
+    gf = rng.standard_normal(shape)
+    gw = torch.empty(C, dtype=torch.float64, device=DEV)
+    aux = torch.empty(N.AUX_WS_BYTES, dtype=torch.uint8, device=DEV)
+    wd = dev(w, torch.float64)
+    fcd, gfd = dev(fc, dtype), dev(gf, dtype)
+    N.check(N.lib.stpi_combine_bwd(C, gfd.numel(), 0 if dtype == torch.float32 else 2, fcd.data_ptr(), wd.data_ptr(),
+                                   gfd.data_ptr(), gw.data_ptr(), aux.data_ptr(), aux.numel(), None))
+    ref = oracle.combine_bwd(fcd.double().cpu().numpy(), w, gfd.double().cpu().numpy())
+    assert rel(gw.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_bce(P, dtype):
+    _, learn = P
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0.0, 1.0, (4, 30, 33))
+    x[0, 0, 0] = 0.0
+    gt = rng.uniform(size=x.shape) < 0.3
+    xd = dev(x, dtype).requires_grad_(True)
+    loss = learn.bce(xd, torch.from_numpy(gt).to(DEV))
+    loss.backward()
+    xs = xd.detach().double().cpu().numpy()
+    lref, gref = oracle.bce(xs, gt)
+    assert abs(float(loss) - lref) < (1e-6 if dtype == torch.float32 else 1e-13) * abs(lref)
+    assert rel(xd.grad.double().cpu().numpy(), gref) < (1e-6 if dtype == torch.float32 else 1e-13)
+
+
+def _tape_reference(f, k, iters):
+    return oracle.forward_train(f, k, iters)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.float64, 1e-12)])
+def test_train_steps_and_adjoint_step(P, dtype, tol):
+    Pm, learn = P
+    from paper_2212_08058_amd import _native as N
+    import ctypes
+    rng = np.random.default_rng(2)
+    shape = (5, 33, 70)
+    kern = Pm.Kernel(2.0, 1.0, 4, 2)
+    k = okf(kern)
+    f = rng.uniform(0.05, 1.0, shape)
+    fd = dev(f, dtype)
+    fref = fd.double().cpu().numpy()
+    tape = oracle.forward_train(fref, k, 3)
+    p = Pm.problem_for(shape, kern, dtype)
+    ws = torch.empty(Pm.workspace_bytes(shape, kern, dtype), dtype=torch.uint8, device=DEV)
+    norms = torch.empty(4, dtype=torch.float64, device=DEV)
+    zs = [torch.empty(shape, dtype=dtype, device=DEV) for _ in range(4)]
+    vs = [torch.empty(shape, dtype=dtype, device=DEV) for _ in range(3)]
+    N.check(N.lib.stpi_train_init(ctypes.byref(p), zs[0].data_ptr(), norms.data_ptr(), None))
+    for j in range(3):
+        N.check(N.lib.stpi_train_step(ctypes.byref(p), fd.data_ptr(), zs[j].data_ptr(), norms[j:].data_ptr(),
+                                      zs[j + 1].data_ptr(), vs[j].data_ptr(), norms[j + 1:].data_ptr(),
+                                      ws.data_ptr(), ws.numel(), None))
+    nrm = norms.cpu().numpy()
+    for j in range(3):
+        x = zs[j + 1].double().cpu().numpy() / nrm[j + 1]
+        assert rel(x, tape["xs"][j + 1]) < tol
+        assert rel(vs[j].double().cpu().numpy(), tape["vs"][j]) < tol
+        assert abs(nrm[j + 1] - tape["ns"][j]) < tol * tape["ns"][j]
+    # one adjoint step (the last) against the oracle's reverse mode on a linear functional
+    g = rng.standard_normal(shape)
+    gd = dev(g, dtype)
+    d = torch.empty(2, dtype=torch.float64, device=DEV)
+    aux = torch.empty(N.AUX_WS_BYTES, dtype=torch.uint8, device=DEV)
+    N.check(N.lib.stpi_dot(gd.numel(), 0 if dtype == torch.float32 else 2, zs[3].data_ptr(), norms[3:].data_ptr(),
+                           gd.data_ptr(), d[1:].data_ptr(), aux.data_ptr(), aux.numel(), None))
+    gk = torch.empty_like(gd)
+    gf = torch.zeros_like(gd)
+    N.check(N.lib.stpi_adjoint_step(ctypes.byref(p), fd.data_ptr(), zs[2].data_ptr(), norms[2:].data_ptr(),
+                                    zs[3].data_ptr(), norms[3:].data_ptr(), vs[2].data_ptr(), gd.data_ptr(),
+                                    d[1:].data_ptr(), gk.data_ptr(), gf.data_ptr(), d[0:].data_ptr(), ws.data_ptr(),
+                                    ws.numel(), None))
+    # oracle: one reversed step
+    x1, x0, n1, v = tape["xs"][3], tape["xs"][2], tape["ns"][2], tape["vs"][2]
+    gdn = gd.double().cpu().numpy()
+    g_z = (gdn - x1 * float(np.sum(x1 * gdn))) / n1
+    g_u = oracle.apply(np.ones(shape), fref * g_z, k)
+    gf_ref = v * g_z + x0 * g_u
+    gk_ref = fref * g_u
+    assert rel(gk.double().cpu().numpy(), gk_ref) < (1e-4 if dtype == torch.float32 else 1e-11)
+    assert rel(gf.double().cpu().numpy(), gf_ref) < (1e-4 if dtype == torch.float32 else 1e-11)
+    dd = d.cpu().numpy()
+    assert abs(dd[0] - float(np.sum(x0 * gk.double().cpu().numpy()))) < 1e-6 * max(1.0, abs(dd[0]))
+
+
+def _end_to_end(P, fc, w, gt, kern, iters, ckpt, dtype):
+    Pm, learn = P
+    fcd = dev(fc, dtype)
+    wd = dev(w, torch.float64).requires_grad_(True)
+    x = learn.spectral_iterate(fcd, wd, kern, iters, ckpt)
+    loss = learn.bce(x, torch.from_numpy(gt).to(DEV))
+    loss.backward()
+    return float(loss), wd.grad.cpu().numpy(), x
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-4), (torch.float64, 1e-10)])
+def test_end_to_end_gradient_matches_oracle(P, dtype, tol):
+    Pm, _ = P
+    rng = np.random.default_rng(3)
+    C, shape = 8, (6, 40, 52)
+    fc, gt = synth.channel_stack(C, *shape, seed=7)
+    fc = fc.astype(np.float64)
+    w = rng.standard_normal(C) * 0.3
+    kern = Pm.Kernel(2.0, 1.0, 4, 2)
+    loss, gw, x = _end_to_end(P, fc, w, gt, kern, 15, 5, dtype)
+    fcr = dev(fc, dtype).double().cpu().numpy()
+    lref, gref, tape = oracle.loss_and_grad(fcr, w, gt, okf(kern), 15)
+    print(f"{dtype}: loss {loss:.10f} vs {lref:.10f}; grad rel err {rel(gw, gref):.3e}")
+    assert abs(loss - lref) < tol * abs(lref)
+    assert rel(gw, gref) < tol
+    assert rel(x.detach().double().cpu().numpy(), tape["xs"][-1]) < (1e-5 if dtype == torch.float32 else 1e-12)
+
+
+def test_checkpointing_matches_full_tape(P):
+    Pm, _ = P
+    rng = np.random.default_rng(4)
+    fc, gt = synth.channel_stack(4, 5, 24, 30, seed=9)
+    w = rng.standard_normal(4)
+    kern = Pm.Kernel(1.5, 1.0, 2, 1)
+    _, g5, _ = _end_to_end(P, fc.astype(np.float64), w, gt, kern, 12, 5, torch.float64)
+    _, g12, _ = _end_to_end(P, fc.astype(np.float64), w, gt, kern, 12, 12, torch.float64)
+    _, g1, _ = _end_to_end(P, fc.astype(np.float64), w, gt, kern, 12, 1, torch.float64)
+    assert np.array_equal(g5, g12) and np.array_equal(g1, g12)
+
+
+def test_gradcheck_fp64(P):
+    """torch.autograd.gradcheck of the full iteration (4x16x16, C = 8, FP64)."""
+    Pm, learn = P
+    rng = np.random.default_rng(5)
+    fc = torch.from_numpy(rng.uniform(0.05, 1.0, (8, 4, 16, 16))).to(DEV)
+    w = torch.from_numpy(rng.standard_normal(8) * 0.5).to(DEV).requires_grad_(True)
+    c = torch.from_numpy(rng.standard_normal((4, 16, 16))).to(DEV)
+    kern = Pm.Kernel(1.5, 1.0, 2, 1)
+
+    def fn(wv):
+        x = learn.spectral_iterate(fc, wv, kern, 6, 2)
+        return (x * c).sum()
+
+    assert torch.autograd.gradcheck(fn, (w,), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_adamw_matches_oracle(P):
+    _, learn = P
+    rng = np.random.default_rng(6)
+    w0 = rng.standard_normal(37)
+    for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
+        wd = dev(w0, dtype)
+        opt = learn.AdamW([wd], lr=3e-3, weight_decay=0.05)
+        w, m, v, vm = w0.copy(), np.zeros(37), np.zeros(37), np.zeros(37)
+        for step in range(1, 6):
+            g = rng.standard_normal(37)
+            opt.step([dev(g, dtype)])
+            w, m, v, vm = oracle.adamw_step(w, dev(g, dtype).double().cpu().numpy(), m, v, vm, step, lr=3e-3,
+                                            weight_decay=0.05)
+        assert rel(wd.double().cpu().numpy(), w) < tol
+
+
+def test_channel_training_full_size(P):
+    """The channel-combination workload (C = 8, 32x240x432, 15 iterations
+    checkpointed every 5, BCE): the FP32 gradient matches the FP64 oracle, and a
+    few AdamW steps lower the loss while moving weight to the cleaner channels."""
+    Pm, learn = P
+    c = synth.CONFIGS["channels"]
+    fc, gt = synth.channel_stack(c["C"], c["T"], c["H"], c["W"], seed=c["seed"])
+    kern = Pm.Kernel(c["sigma_s"], c["sigma_t"], c["r_s"], c["r_t"])
+    w0 = np.zeros(c["C"])
+    loss, gw, _ = _end_to_end(P, fc.astype(np.float64), w0, gt, kern, c["iters"], c["ckpt"], torch.float32)
+    lref, gref, _ = oracle.loss_and_grad(fc.astype(np.float64), w0, gt, okf(kern), c["iters"])
+    print(f"full-size channel gradient: loss {loss:.8f} vs {lref:.8f}, rel err {rel(gw, gref):.3e}")
+    assert abs(loss - lref) < 1e-4 * lref
+    assert rel(gw, gref) < 1e-3
+    fcd = dev(fc)
+    gtd = torch.from_numpy(gt).to(DEV)
+    w = torch.zeros(c["C"], dtype=torch.float64, device=DEV, requires_grad=True)
+    opt = learn.AdamW([w], lr=0.1, weight_decay=0.0)
+    losses = []
+    for _ in range(6):
+        w.grad = None
+        x = learn.spectral_iterate(fcd, w, kern, c["iters"], c["ckpt"])
+        L = learn.bce(x, gtd)
+        L.backward()
+        losses.append(float(L))
+        opt.step()
+    a = torch.softmax(w.detach(), 0).cpu().numpy()
+    print("losses", losses, "softmax weights", a)
+    assert losses[-1] < losses[0]
+    assert a[:3].sum() > 3.0 / 8.0
