@@ -136,6 +136,56 @@ int stpi_set_variant(int index);
 int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z, void *ws, size_t ws_bytes,
                    int variant, int reps, void *stream, double *avg_ms);
 
+/* ---- batched clips --------------------------------------------------------
+ * Many clips of different length and frame size iterated together, all with
+ * the same filter. Their volumes sit in flat device buffers at per-clip
+ * element offsets (non-overlapping; 256-byte aligned offsets are best). Each
+ * iteration is one persistent launch whose workgroups pull tiles from a work
+ * list (longest clips first); every clip keeps its own state, stops on its own
+ * (tolerance or cap) and is skipped afterwards. The whole chain of max_iters
+ * iterations is captured once per (buffers, stream) as a HIP graph and
+ * replayed with a single graph launch. */
+
+typedef struct stpi_clip {
+    int64_t offset;  /* element offset of the clip in the flat buffers */
+    int32_t T, H, W;
+    int32_t reserved;
+} stpi_clip;
+
+typedef struct stpi_plan stpi_plan;
+
+/* Builds a plan: validates the clips, picks the step kernel variant (the
+ * autotuned one for the frame size carrying the most voxels, else the
+ * cheapest eligible one), orders the tile list and uploads the clip and tile
+ * tables (the only device allocations, made here, not on the hot path).
+ * *out receives the plan (owned by the caller, free with stpi_plan_destroy). */
+int stpi_batch_plan(const stpi_clip *clips, int nclips, float sigma_s, float sigma_t, int r_s, int r_t, int dtype,
+                    stpi_plan **out);
+/* Device workspace stpi_batch_iterate needs (0 for NULL). */
+size_t stpi_batch_workspace_bytes(const stpi_plan *plan);
+/* info[0..9] = nclips, ntiles, persistent grid size, RS, RT, TH, TW, NTHR, RY, QX. */
+int stpi_batch_info(const stpi_plan *plan, int32_t info[10]);
+/* Power iteration of every clip (as stpi_iterate, per clip): x_flat is in/out,
+ * init = 1 overwrites each clip with the uniform start, init = 0 uses x_flat.
+ * Stops each clip at its first residual < tol (tol > 0) or after max_iters.
+ * per_clip: host array of nclips results. Synchronises `stream` once. Calls
+ * with a NULL stream run without graph capture. */
+int stpi_batch_iterate(stpi_plan *plan, const void *f_flat, void *x_flat, int init, int max_iters, double tol,
+                       void *ws, size_t ws_bytes, stpi_result *per_clip, void *stream);
+void stpi_plan_destroy(stpi_plan *plan);
+
+/* ---- autotuner -------------------------------------------------------------
+ * stpi_autotune times every compiled variant eligible for `p` (reps launches
+ * each, HIP events, on temporary device buffers it allocates and frees),
+ * records the fastest for (device arch, dtype, r_s, r_t, H, W), and writes the
+ * whole table to cache_path (if not NULL). Later calls for that key use the
+ * recorded variant. Synchronises the device. */
+int stpi_autotune(const stpi_problem *p, const char *cache_path, int reps, int32_t *best_variant, double *best_ms);
+/* Merges a table written by stpi_autotune into the process's table. */
+int stpi_autotune_load(const char *path);
+/* Forgets every recorded choice. */
+void stpi_autotune_clear(void);
+
 /* ---- differentiation path ---------------------------------------------------
  * The gradient of a loss through the whole normalised iteration ("propagating
  * the gradient of the loss through the full spectral algorithm", Sec. 1 and
@@ -205,6 +255,34 @@ int stpi_bce(int64_t n, int dtype, const void *x, const uint8_t *gt, double *los
  * vmax may be NULL when amsgrad == 0. */
 int stpi_adamw(int64_t n, int dtype, void *w, const void *g, void *m, void *v, void *vmax, int step, double lr,
                double beta1, double beta2, double eps, double weight_decay, int amsgrad, void *stream);
+
+/* ---- learned warm start ------------------------------------------------------
+ * A small 3D convolutional network predicts the start vector of the iteration
+ * from f (the paper's own warm start is the previous sub-window's solution,
+ * Sec. 4.4; here a network trained on eigenvectors of the plain method plays
+ * that role). Four 'same' 3x3x3 convolutions with zero padding and bias,
+ * 1 -> 16 -> 16 -> 16 -> 1 channels, ReLU between layers; bfloat16 weights and
+ * activations, FP32 accumulation; the 16 -> 16 layers run on the matrix cores.
+ * Parameters are FP32 masters (stpi_net_param_count() floats, PyTorch conv3d
+ * order [Cout][Cin][3][3][3] per layer: w1 b1 w2 b2 w3 b3 w4 b4); kernels read
+ * a prepared bfloat16 copy (stpi_net_prep_bytes() bytes) made by
+ * stpi_net_prepare. f and y are FP32 [T][H][W] volumes; ws holds the
+ * activations kept for the backward pass (stpi_net_workspace_bytes). */
+int stpi_net_param_count(void);
+size_t stpi_net_prep_bytes(void);
+size_t stpi_net_workspace_bytes(const stpi_problem *p);
+/* prep <- bfloat16 operand layouts of master (device). */
+int stpi_net_prepare(const float *master, void *prep, void *stream);
+/* y = net(f); the activations stay in ws for stpi_net_backward. */
+int stpi_net_forward(const stpi_problem *p, const float *f, const void *prep, float *y, void *ws, size_t ws_bytes,
+                     void *stream);
+/* After stpi_net_forward with the same ws: *loss = mean((y - x_star sqrt(N))^2)
+ * (x_star: the target unit eigenvector) and grad (same layout as the masters,
+ * overwritten) = dloss/dparameters. */
+int stpi_net_backward(const stpi_problem *p, const float *f, const void *prep, const float *y, const float *x_star,
+                      double *loss, float *grad, void *ws, size_t ws_bytes, void *stream);
+/* x0 = max(y, 0) + eps (the iteration normalises its start vector). */
+int stpi_net_warm_start(int64_t n, const float *y, float eps, float *x0, void *stream);
 
 #ifdef __cplusplus
 }

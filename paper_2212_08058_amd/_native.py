@@ -32,6 +32,11 @@ class Problem(ctypes.Structure):
                 ("r_s", ctypes.c_int32), ("r_t", ctypes.c_int32), ("dtype", ctypes.c_int32)]
 
 
+class Clip(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("T", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("status", ctypes.c_int32), ("residual", ctypes.c_double), ("lambda_", ctypes.c_double),
@@ -59,6 +64,24 @@ PROTOTYPES = [
     ("stpi_set_variant", ctypes.c_int, [ctypes.c_int]),
     ("stpi_time_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _sz, ctypes.c_int, ctypes.c_int, _vp,
                                       ctypes.POINTER(ctypes.c_double)]),
+    ("stpi_batch_plan", ctypes.c_int, [ctypes.POINTER(Clip), ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("stpi_batch_workspace_bytes", _sz, [_vp]),
+    ("stpi_batch_info", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    ("stpi_batch_iterate", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _sz,
+                                          _RP, _vp]),
+    ("stpi_plan_destroy", None, [_vp]),
+    ("stpi_autotune", ctypes.c_int, [_PP, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_double)]),
+    ("stpi_autotune_load", ctypes.c_int, [ctypes.c_char_p]),
+    ("stpi_autotune_clear", None, []),
+    ("stpi_net_param_count", ctypes.c_int, []),
+    ("stpi_net_prep_bytes", _sz, []),
+    ("stpi_net_workspace_bytes", _sz, [_PP]),
+    ("stpi_net_prepare", ctypes.c_int, [_vp, _vp, _vp]),
+    ("stpi_net_forward", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_net_backward", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_net_warm_start", ctypes.c_int, [ctypes.c_int64, _vp, ctypes.c_float, _vp, _vp]),
     ("stpi_train_init", ctypes.c_int, [_PP, _vp, _vp, _vp]),
     ("stpi_train_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("stpi_adjoint_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),

@@ -1,0 +1,225 @@
+// Batched power iteration over many clips of different length and frame size.
+//
+// All clips share one filter. Their volumes live in one flat buffer at
+// per-clip element offsets. One iteration is one launch of a persistent grid
+// (about as many workgroups as fit on the chip at once): each workgroup takes
+// tiles from a global work counter until the list is exhausted, so the
+// longest clips (listed first) start first and short ones fill the gaps. A
+// tile of a clip that has converged is skipped. After the step, one
+// workgroup per clip reduces that clip's tile partials and updates its own
+// iteration state (scale, residual, stopping), exactly as the single-clip
+// chain does. No workgroup ever waits for another, so the grid always drains.
+#pragma once
+
+#include "chain.hpp"
+#include "forward.hpp"
+
+namespace stpi {
+
+struct ClipDesc {
+    int64_t offset;    // element offset of the clip in the flat buffers
+    int32_t T, H, W;
+    int32_t tile_begin;  // first entry of the clip in the tile list
+    int32_t tile_end;
+    int32_t pad;
+};
+
+struct TileDesc {
+    int32_t clip;
+    int32_t x0, y0;
+    int32_t pad;
+};
+
+// Counters shared by the launches of one batched iteration chain.
+struct BatchCtl {
+    uint32_t next_tile;   // work counter of the running step (reset by the finalisation)
+    uint32_t done_clips;  // clips that stopped (converged, capped or failed)
+    uint32_t pad[2];
+};
+
+template <class ST>
+struct BatchArgs {
+    using CT = typename Compute<ST>::type;
+    const ST *f;
+    ST *buf0;
+    ST *buf1;
+    DevState *states;
+    const ClipDesc *clips;
+    const TileDesc *tiles;
+    BatchCtl *ctl;
+    double *partials;  // [ntiles][2]
+    int ntiles, nclips;
+    Taps<CT> taps;
+};
+
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX>
+__global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
+    using CT = typename Compute<ST>::type;
+    using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    __shared__ CT lds[G::LDS_ELEMS];
+    __shared__ double red[NTHR / 64];
+    __shared__ int s_tile;
+    if (a.ctl->done_clips >= (uint32_t)a.nclips) return;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&a.ctl->next_tile, 1u);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t >= a.ntiles) break;
+        const TileDesc td = a.tiles[t];
+        const ClipDesc cd = a.clips[td.clip];
+        const DevState *st_ = a.states + td.clip;
+        double d1 = 0.0, d2 = 0.0;
+        if (!st_->done) {
+            const int cur = st_->cur;
+            FwdOp<ST> op;
+            op.f = a.f + cd.offset;
+            op.src = (cur ? a.buf1 : a.buf0) + cd.offset;
+            op.dst = (cur ? a.buf0 : a.buf1) + cd.offset;
+            op.vout = nullptr;
+            op.scale = (CT)st_->scale;
+            op.plane = (size_t)cd.H * cd.W;
+            op.pbytes = (uint32_t)(op.plane * sizeof(ST));
+            stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, cd.T, cd.H, cd.W, td.x0, td.y0, lds, d1, d2);
+        }
+        const double s1 = block_sum<NTHR>(d1, red);
+        const double s2 = block_sum<NTHR>(d2, red);
+        if (threadIdx.x == 0) {
+            a.partials[2 * (size_t)t] = s1;
+            a.partials[2 * (size_t)t + 1] = s2;
+        }
+    }
+}
+
+// One workgroup per clip: the clip's step finalisation (see finalize_kernel).
+__device__ __forceinline__ void finalize_state(DevState *s, double p1, double p2, BatchCtl *ctl) {
+    const double scale = s->scale;
+    const double nz = sqrt(p2);
+    bool stop = false;
+    if (!isfinite(nz) || !isfinite(p1)) {
+        s->flags |= FLAG_NONFINITE;
+        stop = true;
+    } else if (nz == 0.0) {
+        s->flags |= FLAG_ZERO;
+        stop = true;
+    } else {
+        const double c = scale * p1 / nz;
+        s->rayleigh = scale * p1;
+        s->lambda = nz;
+        s->residual = sqrt(fmax(0.0, 2.0 - 2.0 * c));
+        s->scale = 1.0 / nz;
+        s->cur ^= 1;
+        s->iters += 1;
+        if (s->tol > 0.0 && s->residual < s->tol) {
+            s->converged = 1;
+            stop = true;
+        }
+        if (s->iters >= s->max_iters) stop = true;
+    }
+    if (stop) {
+        s->done = 1;
+        atomicAdd(&ctl->done_clips, 1u);
+    }
+}
+
+}  // namespace stpi
+
+namespace stpi {
+
+// Per-storage-type pieces of the batched chain (instantiated in kernels_<type>.hip).
+
+struct BatchLaunch {
+    const void *f;
+    void *buf0, *buf1;
+    DevState *states;
+    const ClipDesc *clips;
+    const TileDesc *tiles;
+    BatchCtl *ctl;
+    double *partials;
+    int ntiles, nclips, grid;
+    double gs[2 * 16 + 1];
+    double gt[2 * 8 + 1];
+};
+
+struct BatchVariant {
+    int RS, RT, TH, TW, NTHR, RY, QX;
+    hipError_t (*launch)(const BatchLaunch &, hipStream_t);
+    int (*blocks_per_cu)();
+};
+
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX>
+hipError_t launch_batch(const BatchLaunch &L, hipStream_t stream) {
+    using CT = typename Compute<ST>::type;
+    BatchArgs<ST> a;
+    a.f = (const ST *)L.f;
+    a.buf0 = (ST *)L.buf0;
+    a.buf1 = (ST *)L.buf1;
+    a.states = L.states;
+    a.clips = L.clips;
+    a.tiles = L.tiles;
+    a.ctl = L.ctl;
+    a.partials = L.partials;
+    a.ntiles = L.ntiles;
+    a.nclips = L.nclips;
+    for (int i = 0; i < 2 * 16 + 1; ++i) a.taps.gs[i] = CT(0);
+    for (int i = 0; i < 2 * 8 + 1; ++i) a.taps.gt[i] = CT(0);
+    for (int d = -RS; d <= RS; ++d) a.taps.gs[d + RS] = (CT)L.gs[d + 16];
+    for (int d = -RT; d <= RT; ++d) a.taps.gt[d + RT] = (CT)L.gt[d + 8];
+    hipLaunchKernelGGL((batch_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX>), dim3(L.grid), dim3(NTHR), 0, stream,
+                       a);
+    return hipGetLastError();
+}
+
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX>
+int batch_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX>, NTHR,
+                                                     0) != hipSuccess)
+        n = 1;
+    return n > 0 ? n : 1;
+}
+
+constexpr int BATCH_NORM_BLOCKS = 64;  // workgroups per clip in the per-clip reductions
+
+// x[clip] <- 1 (uniform start, scale set by the init kernel)
+template <class ST>
+__global__ void batch_fill_ones_kernel(ST *x, const ClipDesc *clips) {
+    using CT = typename Compute<ST>::type;
+    const ClipDesc cd = clips[blockIdx.y];
+    const size_t n = (size_t)cd.T * cd.H * cd.W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(x + cd.offset + i, CT(1));
+}
+
+// partials[(clip * BATCH_NORM_BLOCKS + b) * 2] = sum of squares of the clip's x
+template <class ST>
+__global__ void batch_sumsq_kernel(const ST *x, const ClipDesc *clips, double *partials) {
+    __shared__ double red[256 / 64];
+    const ClipDesc cd = clips[blockIdx.y];
+    const size_t n = (size_t)cd.T * cd.H * cd.W;
+    double a = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const double v = (double)ld(x + cd.offset + i);
+        a += v * v;
+    }
+    const double s = block_sum<256>(a, red);
+    if (threadIdx.x == 0) {
+        partials[2 * ((size_t)blockIdx.y * BATCH_NORM_BLOCKS + blockIdx.x)] = s;
+        partials[2 * ((size_t)blockIdx.y * BATCH_NORM_BLOCKS + blockIdx.x) + 1] = 0.0;
+    }
+}
+
+// x[clip] <- scale_clip * (current iterate of the clip)
+template <class ST>
+__global__ void batch_normalize_kernel(ST *x, const ST *buf1, const ClipDesc *clips, const DevState *states) {
+    using CT = typename Compute<ST>::type;
+    const ClipDesc cd = clips[blockIdx.y];
+    const DevState *s = states + blockIdx.y;
+    const ST *src = (s->cur ? buf1 : x) + cd.offset;
+    const CT scale = (CT)s->scale;
+    const size_t n = (size_t)cd.T * cd.H * cd.W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(x + cd.offset + i, scale * ld(src + i));
+}
+
+}  // namespace stpi

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "aux.hpp"
+#include "batch.hpp"
 #include "chain.hpp"
 #include "dtype_ops.hpp"
 
@@ -83,12 +84,40 @@ hipError_t bce_fin_impl(size_t n, int nblocks, const double *partials, const dou
     return hipGetLastError();
 }
 
+#ifdef STPI_BATCH_VARIANTS
+#define STPI_BATCH_ENTRY(RS, RT, TH, TW, NTHR, RY, QX)                                \
+    {RS, RT, TH, TW, NTHR, RY, QX, &launch_batch<ST_, RS, RT, TH, TW, NTHR, RY, QX>, \
+     &batch_blocks_per_cu<ST_, RS, RT, TH, TW, NTHR, RY, QX>},
+const BatchVariant kBatch[] = {STPI_BATCH_VARIANTS(STPI_BATCH_ENTRY)};
+constexpr int kNBatch = (int)(sizeof(kBatch) / sizeof(kBatch[0]));
+#else
+const BatchVariant *const kBatch = nullptr;
+constexpr int kNBatch = 0;
+#endif
+
+hipError_t batch_fill_impl(void *x, const ClipDesc *clips, int nclips, hipStream_t s) {
+    hipLaunchKernelGGL(batch_fill_ones_kernel<ST_>, dim3(BATCH_NORM_BLOCKS, nclips), dim3(256), 0, s, (ST_ *)x, clips);
+    return hipGetLastError();
+}
+hipError_t batch_sumsq_impl(const void *x, const ClipDesc *clips, int nclips, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(batch_sumsq_kernel<ST_>, dim3(BATCH_NORM_BLOCKS, nclips), dim3(256), 0, s, (const ST_ *)x,
+                       clips, partials);
+    return hipGetLastError();
+}
+hipError_t batch_normalize_impl(void *x, const void *buf1, const ClipDesc *clips, const DevState *states, int nclips,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(batch_normalize_kernel<ST_>, dim3(BATCH_NORM_BLOCKS, nclips), dim3(256), 0, s, (ST_ *)x,
+                       (const ST_ *)buf1, clips, states);
+    return hipGetLastError();
+}
+
 const DtypeOps kOps = {sizeof(ST_),       kVariants,        (int)(sizeof(kVariants) / sizeof(kVariants[0])),
                        &fill_ones_impl,   &sumsq_impl,      &normalize_impl,
                        kAdj,              kNAdj,            &combine_fwd_impl,
                        &combine_bwd_impl, &scale_impl,      &dot_impl,
                        &train_init_impl,  &max_impl,        &bce_impl,
-                       &bce_fin_impl};
+                       &bce_fin_impl,     kBatch,           kNBatch,
+                       &batch_fill_impl,  &batch_sumsq_impl, &batch_normalize_impl};
 
 }  // namespace
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "adjoint.hpp"
+#include "batch.hpp"
 #include "forward.hpp"
 
 namespace stpi {
@@ -26,6 +27,13 @@ struct DtypeOps {
                       hipStream_t);
     hipError_t (*bce_finalize)(size_t n, int nblocks, const double *partials, const double *scalars, void *gx,
                                double *loss, hipStream_t);
+    // batched chain
+    const BatchVariant *batch_variants;
+    int nbatch;
+    hipError_t (*batch_fill)(void *x, const ClipDesc *clips, int nclips, hipStream_t);
+    hipError_t (*batch_sumsq)(const void *x, const ClipDesc *clips, int nclips, double *partials, hipStream_t);
+    hipError_t (*batch_normalize)(void *x, const void *buf1, const ClipDesc *clips, const DevState *states,
+                                  int nclips, hipStream_t);
 };
 
 const DtypeOps *dtype_ops_f32();

@@ -175,7 +175,6 @@ static bool graphs_enabled() {
 
 int forced_variant() { return g_forced_variant; }
 void set_forced_variant(int v) { g_forced_variant = v; }
-int tuned_variant(const stpi_problem *) { return -1; }
 
 }  // namespace stpi
 

@@ -1,0 +1,317 @@
+// C ABI of the batched path: plans, the batched iteration chain and its graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "../../include/stpi.h"
+#include "host_internal.hpp"
+
+struct stpi_plan {
+    stpi_problem proto;  // sigmas, radii, dtype (T, H, W unused)
+    int nclips = 0, ntiles = 0, grid = 0;
+    const stpi::BatchVariant *v = nullptr;
+    stpi::ClipDesc *d_clips = nullptr;
+    stpi::TileDesc *d_tiles = nullptr;
+    std::vector<stpi::ClipDesc> clips;  // host copy, in the caller's order
+    int64_t extent = 0;                 // elements the flat buffers must hold
+    size_t ws_state_off = 0, ws_partials_off = 0, ws_buf_off = 0, ws_total = 0;
+    // captured chains: (f, x, ws, init, max_iters, tol, stream) -> graph
+    struct G {
+        const void *f;
+        void *x, *ws;
+        int init, max_iters;
+        double tol;
+        hipStream_t s;
+        hipGraphExec_t exec;
+    };
+    std::vector<G> graphs;
+};
+
+namespace stpi {
+
+static const BatchVariant *choose_batch_variant(const stpi_problem *proto, const std::vector<ClipDesc> &clips) {
+    const DtypeOps *ops = ops_for(proto->dtype);
+    // Prefer the variant the autotuner picked for the frame size carrying the
+    // most voxels; otherwise the cheapest eligible one by the tap-count model.
+    std::vector<std::pair<int64_t, std::pair<int, int>>> by_shape;
+    for (const auto &c : clips) {
+        bool found = false;
+        for (auto &e : by_shape)
+            if (e.second.first == c.H && e.second.second == c.W) {
+                e.first += (int64_t)c.T * c.H * c.W;
+                found = true;
+            }
+        if (!found) by_shape.push_back({(int64_t)c.T * c.H * c.W, {c.H, c.W}});
+    }
+    std::sort(by_shape.begin(), by_shape.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    if (!by_shape.empty()) {
+        stpi_problem q = *proto;
+        q.T = 64;
+        q.H = by_shape[0].second.first;
+        q.W = by_shape[0].second.second;
+        const int tv = tuned_variant(&q);
+        if (tv >= 0 && tv < ops->nvariants) {
+            const Variant &fv = ops->variants[tv];
+            for (int i = 0; i < ops->nbatch; ++i) {
+                const BatchVariant &b = ops->batch_variants[i];
+                if (b.RS == fv.RS && b.RT == fv.RT && b.TH == fv.TH && b.TW == fv.TW && b.NTHR == fv.NTHR &&
+                    b.RY == fv.RY && b.QX == fv.QX)
+                    return &b;
+            }
+        }
+    }
+    const BatchVariant *best = nullptr;
+    double best_cost = 1e300;
+    for (int i = 0; i < ops->nbatch; ++i) {
+        const BatchVariant &b = ops->batch_variants[i];
+        if (b.RS < proto->r_s || b.RT < proto->r_t) continue;
+        double cost = 0.0;
+        for (const auto &c : clips) {
+            const double gx = std::ceil((double)c.W / b.TW), gy = std::ceil((double)c.H / b.TH);
+            const double taps = (2.0 * b.RS + 1) * (1.0 + 2.0 * b.RS / b.TW) + (2.0 * b.RS + 1) + (2.0 * b.RT + 1);
+            cost += gx * gy * b.TW * b.TH * (double)c.T * taps;
+        }
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = &b;
+        }
+    }
+    return best;
+}
+
+static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int init, int max_iters, double tol,
+                         hipStream_t s) {
+    const DtypeOps *ops = ops_for(P->proto.dtype);
+    char *w = (char *)ws;
+    BatchCtl *ctl = (BatchCtl *)w;
+    DevState *states = (DevState *)(w + P->ws_state_off);
+    double *partials = (double *)(w + P->ws_partials_off);
+    void *buf1 = w + P->ws_buf_off;
+    hipError_t e;
+    if ((e = launch_batch_init(states, P->d_clips, P->nclips, tol, max_iters, init, ctl, s)) != hipSuccess)
+        return hip_fail(e, "batch init");
+    if (init == 1) {
+        if ((e = ops->batch_fill(x, P->d_clips, P->nclips, s)) != hipSuccess) return hip_fail(e, "batch fill");
+    } else {
+        if ((e = ops->batch_sumsq(x, P->d_clips, P->nclips, partials, s)) != hipSuccess)
+            return hip_fail(e, "batch norm");
+        if ((e = launch_batch_state_from_norm(partials, states, P->nclips, ctl, s)) != hipSuccess)
+            return hip_fail(e, "batch norm finalize");
+    }
+    BatchLaunch BL;
+    std::memset(&BL, 0, sizeof(BL));
+    BL.f = f;
+    BL.buf0 = x;
+    BL.buf1 = buf1;
+    BL.states = states;
+    BL.clips = P->d_clips;
+    BL.tiles = P->d_tiles;
+    BL.ctl = ctl;
+    BL.partials = partials;
+    BL.ntiles = P->ntiles;
+    BL.nclips = P->nclips;
+    BL.grid = P->grid;
+    make_taps(&P->proto, BL.gs, BL.gt);
+    for (int k = 0; k < max_iters; ++k) {
+        if ((e = P->v->launch(BL, s)) != hipSuccess) return hip_fail(e, "batch step");
+        if ((e = launch_batch_finalize(partials, P->d_clips, states, P->nclips, ctl, s)) != hipSuccess)
+            return hip_fail(e, "batch finalize");
+    }
+    if ((e = ops->batch_normalize(x, buf1, P->d_clips, states, P->nclips, s)) != hipSuccess)
+        return hip_fail(e, "batch normalize");
+    return STPI_OK;
+}
+
+}  // namespace stpi
+
+using namespace stpi;
+
+extern "C" {
+
+int stpi_batch_plan(const stpi_clip *clips, int nclips, float sigma_s, float sigma_t, int r_s, int r_t, int dtype,
+                    stpi_plan **out) {
+    clear_error();
+    if (!clips || nclips < 1 || !out) return fail(STPI_EINVAL, "need at least one clip and an output pointer");
+    *out = nullptr;
+    stpi_problem proto;
+    proto.T = proto.H = proto.W = 1;
+    proto.sigma_s = sigma_s;
+    proto.sigma_t = sigma_t;
+    proto.r_s = r_s;
+    proto.r_t = r_t;
+    proto.dtype = dtype;
+    int rc = validate_problem(&proto);
+    if (rc) return rc;
+    std::vector<ClipDesc> cds(nclips);
+    int64_t extent = 0;
+    for (int i = 0; i < nclips; ++i) {
+        stpi_problem q = proto;
+        q.T = clips[i].T;
+        q.H = clips[i].H;
+        q.W = clips[i].W;
+        if ((rc = validate_problem(&q))) return fail(rc, "clip %d: %s", i, stpi_last_error());
+        if (clips[i].offset < 0) return fail(STPI_EINVAL, "clip %d: negative offset", i);
+        cds[i].offset = clips[i].offset;
+        cds[i].T = clips[i].T;
+        cds[i].H = clips[i].H;
+        cds[i].W = clips[i].W;
+        extent = std::max(extent, clips[i].offset + (int64_t)clips[i].T * clips[i].H * clips[i].W);
+    }
+    // clips must not overlap
+    std::vector<int> order(nclips);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return cds[a].offset < cds[b].offset; });
+    for (int i = 1; i < nclips; ++i) {
+        const ClipDesc &p = cds[order[i - 1]];
+        if (p.offset + (int64_t)p.T * p.H * p.W > cds[order[i]].offset)
+            return fail(STPI_EINVAL, "clips %d and %d overlap", order[i - 1], order[i]);
+    }
+    const BatchVariant *v = choose_batch_variant(&proto, cds);
+    if (!v) return fail(STPI_EUNSUPPORTED, "no batched kernel for dtype %d, radii (%d, %d)", dtype, r_s, r_t);
+    // tile list: longest clips first, each clip's tiles contiguous, row-major
+    std::vector<int> by_len(nclips);
+    std::iota(by_len.begin(), by_len.end(), 0);
+    std::stable_sort(by_len.begin(), by_len.end(), [&](int a, int b) {
+        const int64_t wa = (int64_t)cds[a].T * ((cds[a].H + v->TH - 1) / v->TH) * ((cds[a].W + v->TW - 1) / v->TW);
+        const int64_t wb = (int64_t)cds[b].T * ((cds[b].H + v->TH - 1) / v->TH) * ((cds[b].W + v->TW - 1) / v->TW);
+        return cds[a].T > cds[b].T || (cds[a].T == cds[b].T && wa > wb);
+    });
+    std::vector<TileDesc> tiles;
+    for (int c : by_len) {
+        cds[c].tile_begin = (int)tiles.size();
+        const int nbx = (cds[c].W + v->TW - 1) / v->TW, nby = (cds[c].H + v->TH - 1) / v->TH;
+        for (int ty = 0; ty < nby; ++ty)
+            for (int tx = 0; tx < nbx; ++tx) tiles.push_back(TileDesc{c, tx * v->TW, ty * v->TH, 0});
+        cds[c].tile_end = (int)tiles.size();
+    }
+    stpi_plan *P = new stpi_plan();
+    P->proto = proto;
+    P->nclips = nclips;
+    P->ntiles = (int)tiles.size();
+    P->v = v;
+    P->clips = cds;
+    P->extent = extent;
+    int dev = 0, cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        cus = prop.multiProcessorCount;
+    P->grid = cus * v->blocks_per_cu();
+    hipError_t e = hipMalloc((void **)&P->d_clips, sizeof(ClipDesc) * nclips);
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_tiles, sizeof(TileDesc) * tiles.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(P->d_clips, cds.data(), sizeof(ClipDesc) * nclips, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(P->d_tiles, tiles.data(), sizeof(TileDesc) * tiles.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        stpi_plan_destroy(P);
+        return hip_fail(e, "plan tables");
+    }
+    const size_t elem = ops_for(dtype)->elem;
+    P->ws_state_off = 256;
+    size_t off = P->ws_state_off + ((sizeof(DevState) * nclips + 255) & ~(size_t)255);
+    P->ws_partials_off = off;
+    const size_t npart = std::max((size_t)P->ntiles, (size_t)nclips * BATCH_NORM_BLOCKS);
+    off += ((npart * 2 * sizeof(double) + 255) & ~(size_t)255);
+    P->ws_buf_off = off;
+    P->ws_total = off + (((size_t)extent * elem + 255) & ~(size_t)255);
+    *out = P;
+    return STPI_OK;
+}
+
+size_t stpi_batch_workspace_bytes(const stpi_plan *plan) { return plan ? plan->ws_total : 0; }
+
+int stpi_batch_info(const stpi_plan *plan, int32_t info[10]) {
+    clear_error();
+    if (!plan || !info) return fail(STPI_EINVAL, "NULL plan or info");
+    const BatchVariant *v = plan->v;
+    info[0] = plan->nclips;
+    info[1] = plan->ntiles;
+    info[2] = plan->grid;
+    info[3] = v->RS;
+    info[4] = v->RT;
+    info[5] = v->TH;
+    info[6] = v->TW;
+    info[7] = v->NTHR;
+    info[8] = v->RY;
+    info[9] = v->QX;
+    return STPI_OK;
+}
+
+int stpi_batch_iterate(stpi_plan *plan, const void *f, void *x, int init, int max_iters, double tol, void *ws,
+                       size_t ws_bytes, stpi_result *per_clip, void *stream) {
+    clear_error();
+    if (!plan || !f || !x || !per_clip) return fail(STPI_EINVAL, "NULL plan, buffer or result");
+    if (f == x) return fail(STPI_EINVAL, "x must not alias f");
+    if (max_iters < 0) return fail(STPI_EINVAL, "max_iters must be >= 0");
+    if (init != 0 && init != 1) return fail(STPI_EINVAL, "init must be 0 (use x) or 1 (uniform)");
+    if (!std::isfinite(tol)) return fail(STPI_EINVAL, "tol must be finite");
+    if (!ws || ws_bytes < plan->ws_total)
+        return fail(STPI_EWORKSPACE, "batch workspace needs %zu bytes", plan->ws_total);
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if (s != nullptr) {
+        hipGraphExec_t exec = nullptr;
+        for (auto &g : plan->graphs)
+            if (g.f == f && g.x == x && g.ws == ws && g.init == init && g.max_iters == max_iters && g.tol == tol &&
+                g.s == s)
+                exec = g.exec;
+        hipError_t e;
+        if (!exec) {
+            if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(e, "begin capture");
+            rc = enqueue_batch(plan, f, x, ws, init, max_iters, tol, s);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(s, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "end capture");
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            if (plan->graphs.size() >= 8) {
+                (void)hipGraphExecDestroy(plan->graphs.front().exec);
+                plan->graphs.erase(plan->graphs.begin());
+            }
+            plan->graphs.push_back({f, x, ws, init, max_iters, tol, s, exec});
+        }
+        if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+    } else {
+        rc = enqueue_batch(plan, f, x, ws, init, max_iters, tol, s);
+        if (rc) return rc;
+    }
+    std::vector<DevState> hs(plan->nclips);
+    hipError_t e = hipMemcpyAsync(hs.data(), (char *)ws + plan->ws_state_off, sizeof(DevState) * plan->nclips,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "batch readback");
+    int worst = STPI_OK;
+    for (int i = 0; i < plan->nclips; ++i) {
+        stpi_result &r = per_clip[i];
+        r.iters = hs[i].iters;
+        r.converged = hs[i].converged;
+        r.flags = hs[i].flags;
+        r.residual = hs[i].residual;
+        r.lambda = hs[i].lambda;
+        r.rayleigh = hs[i].rayleigh;
+        r.status = (hs[i].flags & FLAG_NONFINITE) ? STPI_ENONFINITE : (hs[i].flags & FLAG_ZERO) ? STPI_EZERO_NORM : 0;
+        if (r.status && !worst) worst = r.status;
+    }
+    if (worst) return fail(worst, "at least one clip stopped with: %s", stpi_status_string(worst));
+    return STPI_OK;
+}
+
+void stpi_plan_destroy(stpi_plan *plan) {
+    if (!plan) return;
+    for (auto &g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (plan->d_clips) (void)hipFree(plan->d_clips);
+    if (plan->d_tiles) (void)hipFree(plan->d_tiles);
+    delete plan;
+}
+
+}  // extern "C"

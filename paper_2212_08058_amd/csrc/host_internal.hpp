@@ -8,6 +8,7 @@
 
 #include "../../include/stpi.h"
 #include "common.hpp"
+#include "batch.hpp"
 #include "dtype_ops.hpp"
 
 namespace stpi {
@@ -45,6 +46,12 @@ hipError_t launch_max_finalize(int nblocks, const double *partials, double *scal
 hipError_t launch_dot_finalize(const double *partials, int n, const double *a_norm, double *out, hipStream_t st);
 hipError_t launch_norm_finalize(const double *partials, int n, double *out, hipStream_t st);
 hipError_t launch_sum0_finalize(const double *partials, int n, double *out, hipStream_t st);
+hipError_t launch_batch_init(DevState *states, const ClipDesc *clips, int nclips, double tol, int max_iters,
+                             int uniform, BatchCtl *ctl, hipStream_t st);
+hipError_t launch_batch_state_from_norm(const double *partials, DevState *states, int nclips, BatchCtl *ctl,
+                                        hipStream_t st);
+hipError_t launch_batch_finalize(const double *partials, const ClipDesc *clips, DevState *states, int nclips,
+                                 BatchCtl *ctl, hipStream_t st);
 hipError_t launch_adamw(int dtype, int64_t n, void *w, const void *g, void *m, void *v, void *vmax, double lr,
                         double beta1, double beta2, double eps, double wd, double bc1, double bc2, int amsgrad,
                         hipStream_t st);

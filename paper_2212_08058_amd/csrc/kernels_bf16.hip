@@ -19,4 +19,8 @@
     X(15, 5, 8, 64, 128, 8, 4, 1)      \
     X(15, 5, 16, 128, 512, 8, 4, 1)    \
     X(16, 8, 16, 64, 256, 8, 4, 1)
+#define STPI_BATCH_VARIANTS(X)       \
+    X(8, 3, 16, 64, 256, 8, 4)   \
+    X(8, 3, 8, 64, 128, 8, 4)    \
+    X(16, 8, 16, 64, 256, 8, 4)
 #include "dtype_impl.hpp"

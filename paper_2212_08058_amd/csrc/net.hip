@@ -1,0 +1,469 @@
+// Warm-start network: four 'same' 3x3x3 convolutions (1 -> 16 -> 16 -> 16 -> 1
+// channels, zero padding, bias, ReLU between layers) mapping the feature
+// volume f to a start vector for the power iteration.
+//
+// Weights and activations are bfloat16, accumulation is FP32. Hidden
+// activations are stored channels-last ([voxel][16], 32 bytes per voxel).
+// The two 16 -> 16 layers, and their input gradients, run as implicit GEMMs on
+// the matrix cores (v_mfma_f32_16x16x16_bf16): per wavefront a 16-channel x
+// 16-voxel output block accumulates 27 taps of (16 out x 16 in) weights times
+// (16 in x 16 voxels) inputs. The 1 -> 16 and 16 -> 1 layers and the weight
+// gradients are VALU kernels (their shapes fit the matrix cores badly).
+//
+// Parameter layout (FP32 masters, PyTorch conv3d order [Cout][Cin][3][3][3]):
+//   w1[16][1][27] b1[16] w2[16][16][27] b2[16] w3[16][16][27] b3[16] w4[1][16][27] b4[1]
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/stpi.h"
+#include "common.hpp"
+#include "host_internal.hpp"
+
+namespace stpi {
+
+namespace net {
+
+constexpr int C = 16;
+constexpr int NT = 27;
+constexpr int OFF_W1 = 0, OFF_B1 = 432, OFF_W2 = 448, OFF_B2 = 448 + 6912, OFF_W3 = OFF_B2 + 16,
+              OFF_B3 = OFF_W3 + 6912, OFF_W4 = OFF_B3 + 16, OFF_B4 = OFF_W4 + 432, NPARAM = OFF_B4 + 1;
+static_assert(NPARAM == 14737, "parameter count");
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Prepared weights (device): rounded FP32 copies for the VALU layers and the
+// per-lane MFMA operand blocks of the 16 -> 16 layers, forward and transposed/
+// flipped (input gradient).
+struct Prep {
+    float w1[C][NT];       // [co][tap]
+    float b1[C];
+    bf16x4 a2[NT][64];     // forward A operand of layer 2: lane l -> W2[co=l%16][ci=4(l/16)+j][tap]
+    bf16x4 a2d[NT][64];    // input-gradient A operand:     lane l -> W2[co=4(l/16)+j][ci=l%16][26-tap]
+    float b2[C];
+    bf16x4 a3[NT][64];
+    bf16x4 a3d[NT][64];
+    float b3[C];
+    float w4[C][NT];       // [ci][tap]
+    float b4;
+};
+
+__device__ __forceinline__ float bfr(float v) { return __uint_as_float(((uint32_t)f32_to_bf16_bits(v)) << 16); }
+__device__ __forceinline__ short bfbits(float v) { return (short)f32_to_bf16_bits(v); }
+__device__ __forceinline__ float bf2f(short b) { return __uint_as_float(((uint32_t)(uint16_t)b) << 16); }
+
+__global__ void prepare_kernel(const float *m, Prep *p) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nth = gridDim.x * blockDim.x;
+    for (int i = tid; i < C * NT; i += nth) {
+        const int co = i / NT, tap = i % NT;
+        p->w1[co][tap] = bfr(m[OFF_W1 + i]);
+        p->w4[co][tap] = bfr(m[OFF_W4 + i]);  // w4[0][ci=co][tap]
+    }
+    for (int i = tid; i < NT * 64; i += nth) {
+        const int tap = i / 64, l = i % 64;
+        bf16x4 f2, d2, f3, d3;
+        for (int j = 0; j < 4; ++j) {
+            const int co = l % 16, ci = 4 * (l / 16) + j;          // forward
+            f2[j] = bfbits(m[OFF_W2 + (co * C + ci) * NT + tap]);
+            f3[j] = bfbits(m[OFF_W3 + (co * C + ci) * NT + tap]);
+            const int co2 = 4 * (l / 16) + j, ci2 = l % 16;        // transposed, flipped
+            d2[j] = bfbits(m[OFF_W2 + (co2 * C + ci2) * NT + (NT - 1 - tap)]);
+            d3[j] = bfbits(m[OFF_W3 + (co2 * C + ci2) * NT + (NT - 1 - tap)]);
+        }
+        p->a2[tap][l] = f2;
+        p->a2d[tap][l] = d2;
+        p->a3[tap][l] = f3;
+        p->a3d[tap][l] = d3;
+    }
+    if (tid < C) {
+        p->b1[tid] = m[OFF_B1 + tid];
+        p->b2[tid] = m[OFF_B2 + tid];
+        p->b3[tid] = m[OFF_B3 + tid];
+    }
+    if (tid == 0) p->b4 = m[OFF_B4];
+}
+
+struct Dims {
+    int T, H, W;
+};
+
+__device__ __forceinline__ bool inside(const Dims &d, int t, int y, int x) {
+    return (unsigned)t < (unsigned)d.T && (unsigned)y < (unsigned)d.H && (unsigned)x < (unsigned)d.W;
+}
+
+// Layer 1 (1 -> 16), ReLU. f is FP32 and enters rounded to bfloat16.
+__global__ __launch_bounds__(256) void conv_in_kernel(Dims d, const float *f, const Prep *p, short *act) {
+    __shared__ float w[C][NT];
+    __shared__ float b[C];
+    for (int i = threadIdx.x; i < C * NT; i += blockDim.x) w[i / NT][i % NT] = p->w1[i / NT][i % NT];
+    if (threadIdx.x < C) b[threadIdx.x] = p->b1[threadIdx.x];
+    __syncthreads();
+    const size_t V = (size_t)d.T * d.H * d.W;
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H), t = (int)(v / ((size_t)d.W * d.H));
+        float in[NT];
+#pragma unroll
+        for (int tap = 0; tap < NT; ++tap) {
+            const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
+            in[tap] = inside(d, tt, yy, xx) ? bfr(f[((size_t)tt * d.H + yy) * d.W + xx]) : 0.0f;
+        }
+        short o[C];
+#pragma unroll
+        for (int co = 0; co < C; ++co) {
+            float s = b[co];
+#pragma unroll
+            for (int tap = 0; tap < NT; ++tap) s = fmaf(w[co][tap], in[tap], s);
+            o[co] = bfbits(fmaxf(s, 0.0f));
+        }
+        bf16x4 *dst = reinterpret_cast<bf16x4 *>(act + v * C);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = bf16x4{o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]};
+    }
+}
+
+// 16 -> 16 convolution on the matrix cores. mode 0: out = relu(conv + bias);
+// mode 1 (input gradient of a ReLU layer): out = conv(g, flipped W^T) masked
+// by mask > 0. One wavefront per 16 consecutive voxels of a row.
+template <int MODE>
+__global__ __launch_bounds__(256) void conv16_kernel(Dims d, const short *in, const bf16x4 (*A)[64],
+                                                     const float *bias, const short *mask, short *out) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int gx = (d.W + 15) / 16;
+    const int ngroups = d.T * d.H * gx;
+    const int nwaves = gridDim.x * (blockDim.x / 64);
+    const int n = lane % 16, kq = lane / 16;  // voxel column of B, channel quad
+    bf16x4 a[NT];
+#pragma unroll
+    for (int tap = 0; tap < NT; ++tap) a[tap] = A[tap][lane];
+    for (int g = wave; g < ngroups; g += nwaves) {
+        const int xg = g % gx, y = (g / gx) % d.H, t = g / (gx * d.H);
+        const int x = xg * 16 + n;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < NT; ++tap) {
+            const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
+            bf16x4 bv = {0, 0, 0, 0};
+            if (inside(d, tt, yy, xx))
+                bv = *reinterpret_cast<const bf16x4 *>(in + ((((size_t)tt * d.H + yy) * d.W + xx) * C + 4 * kq));
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[tap], bv, acc, 0, 0, 0);
+        }
+        // lane holds out[co = 4 kq + j][voxel n]
+        if (x < d.W) {
+            const size_t v = ((size_t)t * d.H + y) * d.W + x;
+            bf16x4 o;
+            if (MODE == 0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o[j] = bfbits(fmaxf(acc[j] + bias[4 * kq + j], 0.0f));
+            } else {
+                const bf16x4 mk = *reinterpret_cast<const bf16x4 *>(mask + v * C + 4 * kq);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o[j] = bf2f(mk[j]) > 0.0f ? bfbits(acc[j]) : (short)0;
+            }
+            *reinterpret_cast<bf16x4 *>(out + v * C + 4 * kq) = o;
+        }
+    }
+}
+
+// Layer 4 (16 -> 1), no activation: y = b4 + sum w4 * act3.
+__global__ __launch_bounds__(256) void conv_out_kernel(Dims d, const short *act, const Prep *p, float *y) {
+    __shared__ float w[C][NT];
+    for (int i = threadIdx.x; i < C * NT; i += blockDim.x) w[i / NT][i % NT] = p->w4[i / NT][i % NT];
+    __syncthreads();
+    const float b4 = p->b4;
+    const size_t V = (size_t)d.T * d.H * d.W;
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(v % d.W), yy0 = (int)((v / d.W) % d.H), t = (int)(v / ((size_t)d.W * d.H));
+        float s = b4;
+        for (int tap = 0; tap < NT; ++tap) {
+            const int tt = t + tap / 9 - 1, yy = yy0 + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
+            if (!inside(d, tt, yy, xx)) continue;
+            const bf16x4 *src = reinterpret_cast<const bf16x4 *>(act + (((size_t)tt * d.H + yy) * d.W + xx) * C);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bf16x4 a = src[q];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) s = fmaf(w[4 * q + j][tap], bf2f(a[j]), s);
+            }
+        }
+        y[v] = s;
+    }
+}
+
+// Loss MSE(y, x* sqrt(V)) and g_y = 2 (y - x* sqrt(V)) / V; partials[2b] = sum of squares.
+__global__ void mse_kernel(size_t V, const float *y, const float *xs, double scale, float *gy, double *partials) {
+    __shared__ double red[256 / 64];
+    double s = 0.0;
+    const double inv = 1.0 / (double)V;
+    for (size_t v = (size_t)blockIdx.x * 256 + threadIdx.x; v < V; v += (size_t)gridDim.x * 256) {
+        const double dlt = (double)y[v] - (double)xs[v] * scale;
+        s += dlt * dlt;
+        gy[v] = (float)(2.0 * dlt * inv);
+    }
+    const double t = block_sum<256>(s, red);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = t;
+        partials[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+__global__ void mse_finalize(int nb, size_t V, const double *partials, double *loss) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partials[2 * b];
+    *loss = s / (double)V;
+}
+
+// Input gradient of layer 4, masked by layer 3's ReLU:
+// g3[v][ci] = (act3[v][ci] > 0) * sum_tap w4[ci][tap] * g_y[v - tap]
+__global__ __launch_bounds__(256) void out_bwd_kernel(Dims d, const float *gy, const short *act3, const Prep *p, short *g3) {
+    __shared__ float w[C][NT];
+    for (int i = threadIdx.x; i < C * NT; i += blockDim.x) w[i / NT][i % NT] = p->w4[i / NT][i % NT];
+    __syncthreads();
+    const size_t V = (size_t)d.T * d.H * d.W;
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H), t = (int)(v / ((size_t)d.W * d.H));
+        float g[NT];
+#pragma unroll
+        for (int tap = 0; tap < NT; ++tap) {
+            const int tt = t - (tap / 9 - 1), yy = y - ((tap / 3) % 3 - 1), xx = x - (tap % 3 - 1);
+            g[tap] = inside(d, tt, yy, xx) ? gy[((size_t)tt * d.H + yy) * d.W + xx] : 0.0f;
+        }
+        const bf16x4 *ap = reinterpret_cast<const bf16x4 *>(act3 + v * C);
+        bf16x4 *dst = reinterpret_cast<bf16x4 *>(g3 + v * C);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bf16x4 a = ap[q];
+            bf16x4 o;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float s = 0.0f;
+#pragma unroll
+                for (int tap = 0; tap < NT; ++tap) s = fmaf(w[4 * q + j][tap], g[tap], s);
+                o[j] = bf2f(a[j]) > 0.0f ? bfbits(s) : (short)0;
+            }
+            dst[q] = o;
+        }
+    }
+}
+
+// Weight and bias gradients of one layer: dW[co][ci][tap] = sum_v g[v][co] a[v + tap][ci],
+// db[co] = sum_v g[v][co]. a: layer input (CI channels; CI = 1 reads FP32 f rounded to
+// bfloat16), g: gradient at the layer's pre-activation (CO channels; CO = 1 reads FP32
+// g_y). Threads are (ci, co, lane) triples; each workgroup covers a strided set of
+// voxels and writes its partial sums: partials[block][co][ci][tap] and [block][co][ci = CI] (bias).
+template <int CI, int CO>
+__global__ __launch_bounds__(256) void wgrad_kernel(Dims d, const void *a_, const void *g_, float *partials) {
+    constexpr int VL = 256 / (CI * CO);
+    constexpr int NP = CO * (CI * NT + 1);
+    static_assert(CI * CO * VL == 256, "thread mapping");
+    __shared__ float red[256][NT + 1];
+    const int tid = threadIdx.x;
+    const int ci = tid % CI, co = (tid / CI) % CO, vl = tid / (CI * CO);
+    float acc[NT + 1];
+#pragma unroll
+    for (int k = 0; k <= NT; ++k) acc[k] = 0.0f;
+    const size_t V = (size_t)d.T * d.H * d.W;
+    for (size_t v = (size_t)blockIdx.x * VL + vl; v < V; v += (size_t)gridDim.x * VL) {
+        const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H), t = (int)(v / ((size_t)d.W * d.H));
+        float gv;
+        if (CO == 1)
+            gv = reinterpret_cast<const float *>(g_)[v];
+        else
+            gv = bf2f(reinterpret_cast<const short *>(g_)[v * CO + co]);
+        acc[NT] += gv;
+#pragma unroll
+        for (int tap = 0; tap < NT; ++tap) {
+            const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
+            float av = 0.0f;
+            if (inside(d, tt, yy, xx)) {
+                const size_t u = ((size_t)tt * d.H + yy) * d.W + xx;
+                av = CI == 1 ? bfr(reinterpret_cast<const float *>(a_)[u])
+                             : bf2f(reinterpret_cast<const short *>(a_)[u * CI + ci]);
+            }
+            acc[tap] = fmaf(gv, av, acc[tap]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k <= NT; ++k) red[tid][k] = acc[k];
+    __syncthreads();
+    if (vl == 0) {
+        for (int l = 1; l < VL; ++l)
+#pragma unroll
+            for (int k = 0; k <= NT; ++k) acc[k] += red[tid + l * CI * CO][k];
+        float *out = partials + (size_t)blockIdx.x * NP + co * (CI * NT + 1);
+#pragma unroll
+        for (int tap = 0; tap < NT; ++tap) out[ci * NT + tap] = acc[tap];
+        if (ci == 0) out[CI * NT] = acc[NT];
+    }
+}
+
+// Sums the workgroup partials of one layer into the gradient buffer (same
+// layout as the masters): dW[co][ci][tap] at w_off, db[co] at b_off.
+template <int CI, int CO>
+__global__ void wgrad_reduce(int nblocks, const float *partials, float *grad, int w_off, int b_off) {
+    constexpr int NP = CO * (CI * NT + 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NP) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += (double)partials[(size_t)b * NP + i];
+    const int co = i / (CI * NT + 1), r = i % (CI * NT + 1);
+    if (r < CI * NT)
+        grad[w_off + co * CI * NT + r] = (float)s;
+    else
+        grad[b_off + co] = (float)s;
+}
+
+// Start vector from the net output: x0 = max(y, 0) + eps (normalised by the iteration).
+__global__ void warm_x0_kernel(size_t V, const float *y, float eps, float *x0) {
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (size_t)gridDim.x * blockDim.x)
+        x0[v] = fmaxf(y[v], 0.0f) + eps;
+}
+
+constexpr int WG_BLOCKS = 512;
+
+}  // namespace net
+
+}  // namespace stpi
+
+using namespace stpi;
+using namespace stpi::net;
+
+extern "C" {
+
+int stpi_net_param_count(void) { return NPARAM; }
+
+size_t stpi_net_prep_bytes(void) { return sizeof(Prep); }
+
+size_t stpi_net_workspace_bytes(const stpi_problem *p) {
+    if (validate_problem(p) != STPI_OK) return 0;
+    const size_t V = (size_t)p->T * p->H * p->W;
+    // 3 activation volumes + 2 gradient volumes (bf16 x 16 channels), g_y, loss partials,
+    // weight-gradient partials.
+    size_t b = 5 * ((V * C * 2 + 255) & ~(size_t)255);
+    b += (V * 4 + 255) & ~(size_t)255;
+    b += 4096 * 8;
+    b += (size_t)WG_BLOCKS * C * (C * NT + 1) * sizeof(float);
+    return b;
+}
+
+int stpi_net_prepare(const float *master, void *prep, void *stream) {
+    clear_error();
+    if (!master || !prep) return fail(STPI_EINVAL, "NULL buffer");
+    hipLaunchKernelGGL(prepare_kernel, dim3(8), dim3(256), 0, (hipStream_t)stream, master, (Prep *)prep);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? STPI_OK : hip_fail(e, "net prepare");
+}
+
+static int net_check(const stpi_problem *p, const void *ws, size_t ws_bytes) {
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    if (!ws || ws_bytes < stpi_net_workspace_bytes(p))
+        return fail(STPI_EWORKSPACE, "net workspace needs %zu bytes", stpi_net_workspace_bytes(p));
+    return STPI_OK;
+}
+
+struct NetWs {
+    short *act1, *act2, *act3, *g_a, *g_b;
+    float *gy;
+    double *lpart;
+    float *wpart;
+};
+
+static NetWs net_ws(const stpi_problem *p, void *ws) {
+    const size_t V = (size_t)p->T * p->H * p->W;
+    const size_t vb = (V * C * 2 + 255) & ~(size_t)255;
+    char *w = (char *)ws;
+    NetWs n;
+    n.act1 = (short *)w;
+    n.act2 = (short *)(w + vb);
+    n.act3 = (short *)(w + 2 * vb);
+    n.g_a = (short *)(w + 3 * vb);
+    n.g_b = (short *)(w + 4 * vb);
+    char *q = w + 5 * vb;
+    n.gy = (float *)q;
+    q += (V * 4 + 255) & ~(size_t)255;
+    n.lpart = (double *)q;
+    q += 4096 * 8;
+    n.wpart = (float *)q;
+    return n;
+}
+
+static int conv16_grid(const stpi_problem *p) {
+    const long groups = (long)p->T * p->H * ((p->W + 15) / 16);
+    const long blocks = (groups + 3) / 4;
+    return (int)(blocks < 8192 ? blocks : 8192);
+}
+
+int stpi_net_forward(const stpi_problem *p, const float *f, const void *prep, float *y, void *ws, size_t ws_bytes,
+                     void *stream) {
+    clear_error();
+    int rc = net_check(p, ws, ws_bytes);
+    if (rc) return rc;
+    if (!f || !prep || !y) return fail(STPI_EINVAL, "NULL buffer");
+    const Prep *P = (const Prep *)prep;
+    NetWs n = net_ws(p, ws);
+    hipStream_t s = (hipStream_t)stream;
+    const Dims d{p->T, p->H, p->W};
+    hipLaunchKernelGGL(conv_in_kernel, dim3(2048), dim3(256), 0, s, d, f, P, n.act1);
+    hipLaunchKernelGGL(conv16_kernel<0>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.act1, P->a2, P->b2,
+                       (const short *)nullptr, n.act2);
+    hipLaunchKernelGGL(conv16_kernel<0>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.act2, P->a3, P->b3,
+                       (const short *)nullptr, n.act3);
+    hipLaunchKernelGGL(conv_out_kernel, dim3(2048), dim3(256), 0, s, d, n.act3, P, y);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? STPI_OK : hip_fail(e, "net forward");
+}
+
+int stpi_net_backward(const stpi_problem *p, const float *f, const void *prep, const float *y, const float *x_star,
+                      double *loss, float *grad, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    int rc = net_check(p, ws, ws_bytes);
+    if (rc) return rc;
+    if (!f || !prep || !y || !x_star || !loss || !grad) return fail(STPI_EINVAL, "NULL buffer");
+    const Prep *P = (const Prep *)prep;
+    NetWs n = net_ws(p, ws);
+    hipStream_t s = (hipStream_t)stream;
+    const Dims d{p->T, p->H, p->W};
+    const size_t V = (size_t)p->T * p->H * p->W;
+    hipLaunchKernelGGL(mse_kernel, dim3(2048), dim3(256), 0, s, V, y, x_star, std::sqrt((double)V), n.gy, n.lpart);
+    hipLaunchKernelGGL(mse_finalize, dim3(1), dim3(64), 0, s, 2048, V, n.lpart, loss);
+    // layer 4
+    hipLaunchKernelGGL((wgrad_kernel<C, 1>), dim3(WG_BLOCKS), dim3(256), 0, s, d, (const void *)n.act3,
+                       (const void *)n.gy, n.wpart);
+    hipLaunchKernelGGL((wgrad_reduce<C, 1>), dim3(2), dim3(256), 0, s, WG_BLOCKS, n.wpart, grad, OFF_W4, OFF_B4);
+    hipLaunchKernelGGL(out_bwd_kernel, dim3(2048), dim3(256), 0, s, d, n.gy, n.act3, P, n.g_a);  // g at pre3
+    // layer 3
+    hipLaunchKernelGGL((wgrad_kernel<C, C>), dim3(WG_BLOCKS), dim3(256), 0, s, d, (const void *)n.act2,
+                       (const void *)n.g_a, n.wpart);
+    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s, WG_BLOCKS,
+                       n.wpart, grad, OFF_W3, OFF_B3);
+    hipLaunchKernelGGL(conv16_kernel<1>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.g_a, P->a3d,
+                       (const float *)nullptr, n.act2, n.g_b);  // g at pre2
+    // layer 2
+    hipLaunchKernelGGL((wgrad_kernel<C, C>), dim3(WG_BLOCKS), dim3(256), 0, s, d, (const void *)n.act1,
+                       (const void *)n.g_b, n.wpart);
+    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s, WG_BLOCKS,
+                       n.wpart, grad, OFF_W2, OFF_B2);
+    hipLaunchKernelGGL(conv16_kernel<1>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.g_b, P->a2d,
+                       (const float *)nullptr, n.act1, n.g_a);  // g at pre1
+    // layer 1
+    hipLaunchKernelGGL((wgrad_kernel<1, C>), dim3(WG_BLOCKS), dim3(256), 0, s, d, (const void *)f,
+                       (const void *)n.g_a, n.wpart);
+    hipLaunchKernelGGL((wgrad_reduce<1, C>), dim3(2), dim3(256), 0, s, WG_BLOCKS, n.wpart, grad, OFF_W1, OFF_B1);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? STPI_OK : hip_fail(e, "net backward");
+}
+
+int stpi_net_warm_start(int64_t n, const float *y, float eps, float *x0, void *stream) {
+    clear_error();
+    if (n < 1 || !y || !x0) return fail(STPI_EINVAL, "bad arguments");
+    hipLaunchKernelGGL(warm_x0_kernel, dim3(1024), dim3(256), 0, (hipStream_t)stream, (size_t)n, y, eps, x0);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? STPI_OK : hip_fail(e, "warm start");
+}
+
+}  // extern "C"

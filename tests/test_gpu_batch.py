@@ -1,0 +1,137 @@
+"""Batched uneven clips: parity with the FP64 oracle per clip, bitwise agreement
+with the single-clip path, per-clip stopping, and the autotuner."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import Kernel as OK
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2212_08058_amd as P
+    from paper_2212_08058_amd import batch
+    return P, batch
+
+
+def okf(k):
+    return OK(float(np.float32(k.sigma_s)), float(np.float32(k.sigma_t)), k.r_s, k.r_t)
+
+
+SHAPES = [(9, 40, 70), (3, 17, 23), (1, 64, 80), (12, 31, 33), (5, 5, 5), (7, 70, 40)]
+
+
+def _clips(shapes, seed=0):
+    return [synth.blob_clip(T, H, W, 2, seed + i)[0] for i, (T, H, W) in enumerate(shapes)]
+
+
+def test_batch_fixed_iterations_match_oracle(P):
+    Pm, B = P
+    kern = Pm.Kernel(2.0, 1.0, 4, 2)
+    fs = _clips(SHAPES)
+    plan = B.BatchPlan(SHAPES, kern)
+    print(plan.info())
+    f_flat = plan.pack([torch.from_numpy(f).to(DEV) for f in fs])
+    x_flat, res = plan.iterate(f_flat, max_iters=8, tol=0.0)
+    for f, xv, r in zip(fs, plan.views(x_flat), res):
+        xr, info = oracle.iterate(f, okf(kern), iters=8)
+        err = float(np.linalg.norm(xv.double().cpu().numpy() - xr) / np.linalg.norm(xr))
+        assert r["iters"] == 8 and err < 1e-5, (f.shape, err)
+        assert abs(r["lambda_"] - info.lambdas[-1]) < 1e-5 * info.lambdas[-1]
+
+
+def test_batch_bitwise_equals_single_clip_path(P):
+    """Same kernel variant, same tiles, same reduction order: per-clip results are identical."""
+    Pm, B = P
+    from paper_2212_08058_amd import _native as N
+    kern = Pm.Kernel(4.0, 1.5, 8, 3)
+    shapes = [(11, 60, 130), (4, 45, 70), (20, 33, 150)]
+    fs = _clips(shapes, seed=10)
+    plan = B.BatchPlan(shapes, kern)
+    info = plan.info()
+    # force the single-clip path onto the same compiled variant
+    nv = N.lib.stpi_variant_count(0)
+    idx = None
+    for i in range(nv):
+        a = (ctypes.c_int * 8)()
+        N.lib.stpi_variant_info(0, i, a)
+        if [a[k] for k in range(7)] == [info[k] for k in ("RS", "RT", "TH", "TW", "NTHR", "RY", "QX")]:
+            idx = i
+            break
+    assert idx is not None
+    s = torch.cuda.Stream()
+    f_flat = plan.pack([torch.from_numpy(f).to(DEV) for f in fs])
+    torch.cuda.synchronize()
+    x_flat, res = plan.iterate(f_flat, max_iters=60, tol=1e-4, stream=s)
+    try:
+        N.lib.stpi_set_variant(idx)
+        for f, xv, r in zip(fs, plan.views(x_flat), res):
+            xs, rs = Pm.power_iterate(torch.from_numpy(f).to(DEV), kern, tol=1e-4, max_iters=60)
+            assert torch.equal(xs, xv), f.shape
+            assert r["iters"] == rs["iters"] and r["converged"] == rs["converged"]
+            assert r["residual"] == rs["residual"] and r["lambda_"] == rs["lambda_"]
+    finally:
+        N.lib.stpi_set_variant(-1)
+
+
+def test_batch_tolerance_per_clip_and_failures(P):
+    Pm, B = P
+    kern = Pm.Kernel(2.0, 1.0, 4, 2)
+    shapes = [(6, 30, 40), (6, 30, 40), (4, 20, 20)]
+    fs = _clips(shapes, seed=20)
+    fs[2] = np.zeros_like(fs[2])  # A x = 0 for this clip only
+    plan = B.BatchPlan(shapes, kern)
+    f_flat = plan.pack([torch.from_numpy(f).to(DEV) for f in fs])
+    x_flat, res = plan.iterate(f_flat, max_iters=400, tol=1e-4, check=False)
+    for f, xv, r in list(zip(fs, plan.views(x_flat), res))[:2]:
+        xr, info = oracle.iterate(f, okf(kern), tol=1e-4, cap=400)
+        assert r["converged"] and abs(r["iters"] - info.iters) <= 2
+        cosd = 1 - float(np.sum(xv.double().cpu().numpy() * xr))
+        assert cosd < 1e-3
+    assert res[2]["status"] == 3 and not res[2]["converged"]
+    # the capped case: every clip stops at the cap
+    x_flat, res = plan.iterate(f_flat, max_iters=3, tol=1e-12, check=False)
+    assert [r["iters"] for r in res[:2]] == [3, 3]
+
+
+def test_batch_start_vectors(P):
+    Pm, B = P
+    kern = Pm.Kernel(2.0, 1.0, 4, 2)
+    shapes = [(4, 20, 30), (3, 25, 21)]
+    fs = _clips(shapes, seed=30)
+    rng = np.random.default_rng(1)
+    x0 = [rng.uniform(0.1, 1, s).astype(np.float32) * 5 for s in shapes]
+    plan = B.BatchPlan(shapes, kern)
+    f_flat = plan.pack([torch.from_numpy(f).to(DEV) for f in fs])
+    x_flat = plan.pack([torch.from_numpy(v).to(DEV) for v in x0])
+    x_flat, res = plan.iterate(f_flat, x_flat, init=0, max_iters=4, tol=0.0)
+    for f, v0, xv in zip(fs, x0, plan.views(x_flat)):
+        xr, _ = oracle.iterate(f, okf(kern), x0=v0, iters=4)
+        assert np.linalg.norm(xv.double().cpu().numpy() - xr) / np.linalg.norm(xr) < 1e-5
+
+
+def test_autotune_roundtrip(P, tmp_path):
+    Pm, B = P
+    from paper_2212_08058_amd import _native as N
+    kern = Pm.Kernel(4.0, 1.5, 8, 3)
+    path = str(tmp_path / "tune.txt")
+    v, ms = B.autotune((16, 120, 216), kern, cache_path=path, reps=3)
+    assert v >= 0 and ms > 0
+    text = open(path).read()
+    assert "gfx950" in text
+    B.autotune_clear()
+    B.autotune_load(path)
+    # the tuned variant is used: results still match the oracle
+    f, _ = synth.blob_clip(16, 120, 216, 3, 5)
+    x, r = Pm.power_iterate(torch.from_numpy(f).to(DEV), kern, iters=3)
+    xr, _ = oracle.iterate(f, okf(kern), iters=3)
+    assert np.linalg.norm(x.double().cpu().numpy() - xr) / np.linalg.norm(xr) < 1e-5
+    B.autotune_clear()
