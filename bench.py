@@ -68,6 +68,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=40, help="launches timed for the roofline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", default="bf16",
+                    help="comma list of extra measurements to attach: bf16, batch, channels, warm (or none)")
+    ap.add_argument("--warm-train", type=int, default=200, help="training clips for the warm-start extra")
+    ap.add_argument("--warm-eval", type=int, default=10, help="evaluation clips for the warm-start extra")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -161,6 +165,38 @@ def main():
         },
         "result": {"residual": res["residual"], "lambda": res["lambda_"], "iters": res["iters"]},
     }
+    extras = [e for e in args.extras.split(",") if e and e != "none"]
+    if "bf16" in extras and args.dtype == "f32":
+        log("bf16 storage leg")
+        with torch.cuda.stream(stream):
+            fb = f.to(torch.bfloat16)
+            xb = torch.empty_like(fb)
+            wsb = torch.empty(P.workspace_bytes(fb.shape, kern, torch.bfloat16), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            P.power_iterate(fb, kern, iters=iters, x=xb, ws=wsb, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            P.power_iterate(fb, kern, iters=iters, x=xb, ws=wsb, stream=stream)
+        torch.cuda.synchronize()
+        dtb = (time.perf_counter() - t0) / args.steps
+        kb = P.time_step(fb, xb.clone(), kern, z=torch.empty_like(fb), reps=args.kernel_reps, ws=wsb, stream=stream)
+        out["bf16"] = {"value": Nvox * iters / dtb, "ms_per_step": dtb * 1e3, "kernel_ms": kb,
+                       "hbm_gbs": 6 * Nvox / (kb * 1e-3) / 1e9,
+                       "alu_tflops": flops_per_voxel * Nvox / (kb * 1e-3) / 1e12}
+    from paper_2212_08058_amd import experiments as X
+    if "batch" in extras:
+        log("batched uneven clips")
+        out["batch"] = X.batched_workload(log=log)
+    if "channels" in extras:
+        log("channel-combination training step")
+        out["channels"] = X.channel_training_step(log=log)
+    if "warm" in extras:
+        log("warm start vs plain")
+        r = X.warm_start_experiment(n_train=args.warm_train, n_eval=args.warm_eval, log=log)
+        r.pop("rows", None)
+        out["warm"] = r
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(f_np, kern, args.cpu_seconds)

@@ -120,8 +120,8 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
 
 /* Number of compiled variants for dtype (0 for an unknown dtype). */
 int stpi_variant_count(int dtype);
-/* info[0..7] = RS, RT, TH, TW, NTHR, RY, QX, OCC (min waves per SIMD) of variant `index`; STPI_EINVAL if out of range. */
-int stpi_variant_info(int dtype, int index, int32_t info[8]);
+/* info[0..8] = RS, RT, TH, TW, NTHR, RY, QX, OCC (min waves per SIMD), PIPE (1: pipelined tile loop) of variant `index`; STPI_EINVAL if out of range. */
+int stpi_variant_info(int dtype, int index, int32_t info[9]);
 /* Force variant `index` for every later call in the process (-1: automatic
  * choice). A forced variant whose radii are too small makes calls fail with
  * STPI_EUNSUPPORTED. Not thread-safe against concurrent launches. */

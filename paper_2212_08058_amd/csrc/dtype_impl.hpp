@@ -1,6 +1,6 @@
 // Instantiates the kernel set for one storage type. Included once per type by
 // kernels_<type>.hip with STPI_ST (storage type), STPI_NAME (suffix) and
-// STPI_VARIANTS(X) (the compiled (RS, RT, TH, TW, NTHR, RY, QX, OCC) list) defined.
+// STPI_VARIANTS(X) (the compiled (RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE) list) defined.
 #pragma once
 
 #include "aux.hpp"
@@ -28,8 +28,8 @@ hipError_t normalize_impl(void *x, const void *buf1, size_t n, const DevState *s
     return hipGetLastError();
 }
 
-#define STPI_VARIANT_ENTRY(RS, RT, TH, TW, NTHR, RY, QX, OCC) \
-    {RS, RT, TH, TW, NTHR, RY, QX, OCC, &launch_fwd<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC>},
+#define STPI_VARIANT_ENTRY(RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE) \
+    {RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, &launch_fwd<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>},
 
 const Variant kVariants[] = {STPI_VARIANTS(STPI_VARIANT_ENTRY)};
 

@@ -22,7 +22,7 @@ struct FwdLaunch {
 
 // One variant of the step kernel: compiled radii and tile.
 struct Variant {
-    int RS, RT, TH, TW, NTHR, RY, QX, OCC;
+    int RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE;
     hipError_t (*launch)(const FwdLaunch &, hipStream_t);
 };
 
@@ -137,11 +137,13 @@ struct FwdOp {
 };
 
 // OCC: minimum waves per SIMD the register allocation must allow (1 = no limit).
-template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC>
+// PIPE: 1 selects the software-pipelined tile loop (stencil_tile_pipe).
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>
 __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     using CT = typename Compute<ST>::type;
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
-    __shared__ CT lds[G::LDS_ELEMS];
+    using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    __shared__ CT lds[PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS];
     __shared__ double red[NTHR / 64];
 
     const int nbx = (a.W + TW - 1) / TW, nby = (a.H + TH - 1) / TH;
@@ -165,7 +167,10 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     op.pbytes = (uint32_t)(op.plane * sizeof(ST));
     double d1 = 0.0, d2 = 0.0;
     const int x0 = (tile % nbx) * TW, y0 = (tile / nbx) * TH;
-    stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, a.H, a.W, x0, y0, lds, d1, d2);
+    if constexpr (PIPE)
+        stencil_tile_pipe<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, a.H, a.W, x0, y0, lds, d1, d2);
+    else
+        stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, a.H, a.W, x0, y0, lds, d1, d2);
     const double s1 = block_sum<NTHR>(d1, red);
     const double s2 = block_sum<NTHR>(d2, red);
     if (threadIdx.x == 0) {
@@ -174,7 +179,7 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     }
 }
 
-template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC>
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>
 hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     using CT = typename Compute<ST>::type;
     FwdArgs<ST> a;
@@ -197,7 +202,7 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     for (int d = -RT; d <= RT; ++d) a.taps.gt[d + RT] = (CT)L.gt[d + 8];
     const int ntiles = ((L.W + TW - 1) / TW) * ((L.H + TH - 1) / TH);
     const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
-    hipLaunchKernelGGL((fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC>), dim3(per * NUM_XCD), dim3(NTHR), 0,
+    hipLaunchKernelGGL((fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>), dim3(per * NUM_XCD), dim3(NTHR), 0,
                        stream, a);
     return hipGetLastError();
 }

@@ -379,7 +379,7 @@ int stpi_variant_count(int dtype) {
     return ops ? ops->nvariants : 0;
 }
 
-int stpi_variant_info(int dtype, int index, int32_t info[8]) {
+int stpi_variant_info(int dtype, int index, int32_t info[9]) {
     clear_error();
     const DtypeOps *ops = ops_for(dtype);
     if (!ops || !info || index < 0 || index >= ops->nvariants)
@@ -393,6 +393,7 @@ int stpi_variant_info(int dtype, int index, int32_t info[8]) {
     info[5] = v.RY;
     info[6] = v.QX;
     info[7] = v.OCC;
+    info[8] = v.PIPE;
     return STPI_OK;
 }
 

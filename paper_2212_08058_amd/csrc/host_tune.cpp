@@ -17,7 +17,7 @@ namespace stpi {
 struct TuneEntry {
     std::string arch;
     int dtype, rs, rt, H, W;
-    int sig[8];  // RS, RT, TH, TW, NTHR, RY, QX, OCC of the winner
+    int sig[9];  // RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE of the winner
     double ms;
 };
 
@@ -38,7 +38,7 @@ static int variant_by_sig(int dtype, const int *sig) {
     if (!ops) return -1;
     for (int i = 0; i < ops->nvariants; ++i) {
         const Variant &v = ops->variants[i];
-        const int s[8] = {v.RS, v.RT, v.TH, v.TW, v.NTHR, v.RY, v.QX, v.OCC};
+        const int s[9] = {v.RS, v.RT, v.TH, v.TW, v.NTHR, v.RY, v.QX, v.OCC, v.PIPE};
         if (std::memcmp(s, sig, sizeof(s)) == 0) return i;
     }
     return -1;
@@ -67,10 +67,11 @@ static int save_table(const char *path) {
     const std::string tmp = std::string(path) + ".tmp";
     FILE *fp = std::fopen(tmp.c_str(), "w");
     if (!fp) return fail(STPI_EINVAL, "cannot write %s", tmp.c_str());
-    std::fprintf(fp, "# stpi autotune v1: arch dtype r_s r_t H W RS RT TH TW NTHR RY QX OCC ms\n");
+    std::fprintf(fp, "# stpi autotune v2: arch dtype r_s r_t H W RS RT TH TW NTHR RY QX OCC PIPE ms\n");
     for (const auto &e : g_tune)
-        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %.6f\n", e.arch.c_str(), e.dtype, e.rs, e.rt, e.H,
-                     e.W, e.sig[0], e.sig[1], e.sig[2], e.sig[3], e.sig[4], e.sig[5], e.sig[6], e.sig[7], e.ms);
+        std::fprintf(fp, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.6f\n", e.arch.c_str(), e.dtype, e.rs, e.rt,
+                     e.H, e.W, e.sig[0], e.sig[1], e.sig[2], e.sig[3], e.sig[4], e.sig[5], e.sig[6], e.sig[7], e.sig[8],
+                     e.ms);
     std::fclose(fp);
     if (std::rename(tmp.c_str(), path) != 0) return fail(STPI_EINVAL, "cannot rename %s", tmp.c_str());
     return STPI_OK;
@@ -94,9 +95,9 @@ int stpi_autotune_load(const char *path) {
         if (line[0] == '#') continue;
         char arch[64];
         TuneEntry e;
-        if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %d %lf", arch, &e.dtype, &e.rs, &e.rt, &e.H,
-                        &e.W, &e.sig[0], &e.sig[1], &e.sig[2], &e.sig[3], &e.sig[4], &e.sig[5], &e.sig[6],
-                        &e.sig[7], &e.ms) != 15)
+        if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %lf", arch, &e.dtype, &e.rs, &e.rt,
+                        &e.H, &e.W, &e.sig[0], &e.sig[1], &e.sig[2], &e.sig[3], &e.sig[4], &e.sig[5], &e.sig[6],
+                        &e.sig[7], &e.sig[8], &e.ms) != 16)
             continue;
         e.arch = arch;
         put_entry(e);
@@ -158,7 +159,7 @@ int stpi_autotune(const stpi_problem *p, const char *cache_path, int reps, int32
     te.rt = p->r_t;
     te.H = p->H;
     te.W = p->W;
-    const int sig[8] = {v.RS, v.RT, v.TH, v.TW, v.NTHR, v.RY, v.QX, v.OCC};
+    const int sig[9] = {v.RS, v.RT, v.TH, v.TW, v.NTHR, v.RY, v.QX, v.OCC, v.PIPE};
     std::memcpy(te.sig, sig, sizeof(sig));
     te.ms = best_t;
     {

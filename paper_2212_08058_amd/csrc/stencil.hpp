@@ -336,4 +336,159 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
     }
 }
 
+// Software-pipelined variant of stencil_tile. Each phase p (one barrier per
+// phase) does three frames' worth of different work:
+//   stage frame p into U[p % 2] (and issue the loads of frame p + 1),
+//   y-pass of frame p - 1 from U[(p - 1) % 2] into Y[(p - 1) % 2],
+//   x-pass, t-scatter and epilogue of frame p - 2 from Y[p % 2].
+// A buffer written in phase q is read in phase q + 1 and rewritten in phase
+// q + 2, after the barrier of phase q + 1, so one barrier per phase suffices.
+// y-pass items are dealt to threads from the front, x-pass items from the
+// back, so that every wavefront carries a similar share of both.
+template <int RS, int RT, int TH, int TW, int NTHR, int RY, int QX>
+struct PipeGeometry {
+    using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    static constexpr int UB = G::NUP;         // one U buffer (16-byte aligned size)
+    static constexpr int YB = TH * G::LW;     // one Y buffer
+    static constexpr int LDS_ELEMS = 2 * UB + 2 * YB;
+    static constexpr int NYT = (G::NYI + NTHR - 1) / NTHR;  // y-pass items per thread
+};
+
+template <class CT, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, class Op>
+__device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &tp, int T, int H, int W, int x0,
+                                                  int y0, CT *lds, double &d1, double &d2) {
+    using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    constexpr int NC = G::NC, NU = G::NU, NPF = G::NPF, LW = G::LW, RSA = G::RSA;
+    constexpr int NYI = G::NYI, NQ = G::NQ, NXI = G::NXI, IPT = G::IPT, NTS = G::NTS, NYT = PG::NYT;
+    constexpr uint32_t ESZ = Op::ESZ;
+    const int tid = threadIdx.x;
+    CT *const U0 = lds;
+    CT *const Y0 = lds + 2 * PG::UB;
+
+    uint32_t poff[NPF];
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+        const int e = tid + k * NTHR;
+        const int r = e / NC, c = e % NC;
+        const int gy = y0 - RS + r, gx = x0 - RS + c;
+        const bool ok = e < NU && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+        poff[k] = ok ? (uint32_t)(gy * W + gx) * ESZ : OOB;
+    }
+    uint32_t ooff[IPT][QX];
+    int orow[IPT], ocol[IPT];
+    bool olive[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int item = (NTHR - 1 - tid) + i * NTHR;
+        olive[i] = item < NXI;
+        orow[i] = olive[i] ? item / NQ : 0;
+        ocol[i] = olive[i] ? (item % NQ) * QX : 0;
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int gy = y0 + orow[i], gx = x0 + ocol[i] + q;
+            ooff[i][q] = (olive[i] && gy < H && gx < W) ? (uint32_t)(gy * W + gx) * ESZ : OOB;
+        }
+    }
+
+    CT acc[NTS][IPT][QX];
+#pragma unroll
+    for (int s = 0; s < NTS; ++s)
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+#pragma unroll
+            for (int q = 0; q < QX; ++q) acc[s][i][q] = CT(0);
+
+    typename Op::template Raw<NPF> pf;
+    op.template fetch<NPF>(0, poff, pf);
+    typename Op::template OutRaw<IPT, QX> oraw;
+
+    const int nphase = T + RT + 2;
+    for (int p = 0; p < nphase; ++p) {
+        const int tx = p - 2;  // frame of the x-pass / ring step
+        if (tx >= RT && tx - RT < T) op.template fetch_out<IPT, QX>(tx - RT, ooff, oraw);
+        // stage frame p
+        if (p < T) {
+            CT *U = U0 + (p & 1) * PG::UB;
+#pragma unroll
+            for (int k = 0; k < NPF; ++k) {
+                const int e = tid + k * NTHR;
+                if (NU % NTHR == 0 || k < NPF - 1 || e < NU) U[e] = op.template input<NPF>(pf, k);
+            }
+            if (p + 1 < T) op.template fetch<NPF>(p + 1, poff, pf);
+        }
+        // y-pass of frame p - 1
+        if (p >= 1 && p - 1 < T) {
+            const CT *U = U0 + ((p - 1) & 1) * PG::UB;
+            CT *Y = Y0 + ((p - 1) & 1) * PG::YB;
+#pragma unroll
+            for (int m = 0; m < NYT; ++m) {
+                const int it = tid + m * NTHR;
+                if (it < NYI) {
+                    const int c = it % NC;
+                    const int g = it / NC;
+                    const CT *col = U + (g * RY) * NC + c;
+                    CT u[RY + 2 * RS];
+#pragma unroll
+                    for (int k = 0; k < RY + 2 * RS; ++k) u[k] = col[k * NC];
+                    CT *dstp = Y + (g * RY) * LW + c + (RSA - RS);
+#pragma unroll
+                    for (int r = 0; r < RY; ++r) {
+                        CT s = CT(0);
+#pragma unroll
+                        for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], u[r + d], s);
+                        dstp[r * LW] = s;
+                    }
+                }
+            }
+        }
+        // x-pass, t-ring and epilogue of frame p - 2
+        if (tx >= 0) {
+            CT v[IPT][QX];
+            const bool live = tx < T;
+            if (live) {
+                const CT *Y = Y0 + (tx & 1) * PG::YB;
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    using V4 = LdsVec<CT>;
+                    constexpr int NV = (QX + 2 * RSA) / V4::N;
+                    const typename V4::type *rowp = reinterpret_cast<const typename V4::type *>(
+                        __builtin_assume_aligned(Y + orow[i] * LW + ocol[i], 16));
+                    CT w[QX + 2 * RSA];
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        const typename V4::type t4 = rowp[k];
+#pragma unroll
+                        for (int e = 0; e < V4::N; ++e) w[k * V4::N + e] = t4[e];
+                    }
+#pragma unroll
+                    for (int q = 0; q < QX; ++q) {
+                        CT s = CT(0);
+#pragma unroll
+                        for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], w[q + d + RSA - RS], s);
+                        v[i][q] = s;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+#pragma unroll
+                    for (int q = 0; q < QX; ++q) v[i][q] = CT(0);
+            }
+            switch (tx % NTS) {
+#define STPI_RING_CASE(J)                                                                               \
+    case J:                                                                                             \
+        if constexpr (J < NTS) ring_step<J, CT, RT, IPT, QX>(acc, v, tp, live, tx, op, ooff, oraw, d1, d2); \
+        break;
+                STPI_RING_CASE(0) STPI_RING_CASE(1) STPI_RING_CASE(2) STPI_RING_CASE(3) STPI_RING_CASE(4)
+                STPI_RING_CASE(5) STPI_RING_CASE(6) STPI_RING_CASE(7) STPI_RING_CASE(8) STPI_RING_CASE(9)
+                STPI_RING_CASE(10) STPI_RING_CASE(11) STPI_RING_CASE(12) STPI_RING_CASE(13) STPI_RING_CASE(14)
+                STPI_RING_CASE(15) STPI_RING_CASE(16)
+#undef STPI_RING_CASE
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace stpi

@@ -45,16 +45,18 @@ def blob_mask(T: int, H: int, W: int, nblobs: int, seed: int):
     """
     rng = np.random.default_rng(seed)
     params = _blob_params(rng, nblobs, H, W)
-    yy = np.arange(H, dtype=np.float64)[:, None]
-    xx = np.arange(W, dtype=np.float64)[None, :]
+    yy = np.arange(H, dtype=np.float64)
+    xx = np.arange(W, dtype=np.float64)
     mask = np.zeros((T, H, W), dtype=np.float64)
     for t in range(T):
         m = mask[t]
         for sigma, speed, angle, cy0, cx0 in params:
             cy = cy0 + speed * math.sin(angle) * t
             cx = cx0 + speed * math.cos(angle) * t
-            d2 = (yy - cy) ** 2 + (xx - cx) ** 2
-            np.maximum(m, np.exp(-d2 / (2.0 * sigma * sigma)), out=m)
+            # isotropic Gaussian = product of its row and column profiles
+            gy = np.exp(-((yy - cy) ** 2) / (2.0 * sigma * sigma))
+            gx = np.exp(-((xx - cx) ** 2) / (2.0 * sigma * sigma))
+            np.maximum(m, np.multiply.outer(gy, gx), out=m)
     return mask, rng
 
 

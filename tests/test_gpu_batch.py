@@ -61,9 +61,9 @@ def test_batch_bitwise_equals_single_clip_path(P):
     nv = N.lib.stpi_variant_count(0)
     idx = None
     for i in range(nv):
-        a = (ctypes.c_int * 8)()
+        a = (ctypes.c_int * 9)()
         N.lib.stpi_variant_info(0, i, a)
-        if [a[k] for k in range(7)] == [info[k] for k in ("RS", "RT", "TH", "TW", "NTHR", "RY", "QX")]:
+        if a[8] == 0 and [a[k] for k in range(7)] == [info[k] for k in ("RS", "RT", "TH", "TW", "NTHR", "RY", "QX")]:
             idx = i
             break
     assert idx is not None

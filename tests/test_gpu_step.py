@@ -108,7 +108,7 @@ def test_every_compiled_variant(P):
     fd, xd = to_dev(f, torch.float32), to_dev(x, torch.float32)
     try:
         for i in range(n):
-            info = (ctypes.c_int * 8)()
+            info = (ctypes.c_int * 9)()
             assert N.lib.stpi_variant_info(N.STPI_F32, i, info) == 0
             RS, RT = info[0], info[1]
             kern = P.Kernel(0.6 * RS + 0.5, 0.6 * RT + 0.5, RS, RT)
