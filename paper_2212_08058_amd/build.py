@@ -47,6 +47,13 @@ def build(jobs: int | None = None) -> str:
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
+    # host-side check of the generated device code (the checker is not shipped to GPU runs)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("stpi_isa_check", os.path.join(HERE, "isa_check.py"))
+    if spec is not None and os.path.exists(os.path.join(HERE, "isa_check.py")):
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.check_device_code(srcs, jobs, HIPCC, FLAGS, BUILD)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
