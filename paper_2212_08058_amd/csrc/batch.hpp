@@ -60,18 +60,34 @@ __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
     __shared__ double red[NTHR / 64];
     __shared__ int s_tile;
     if (a.ctl->done_clips >= (uint32_t)a.nclips) return;
+    // Every branch of the tile loop is wave-uniform (readfirstlane values, the
+    // wave index), and no branch in it depends on the lane. With the plain
+    // form (thread 0 fetches the next tile into LDS, everyone reads it back)
+    // the compiler may thread thread 0's "store partials" and "fetch next
+    // tile" across the back-edge into a separate path; lanes 1..63 of wave 0
+    // then loop back on their own and spin on a tile index that only the
+    // parked lane 0 could update. Here wave 0 does the fetch with all lanes
+    // active: lane 0 adds one, the others add zero, so the value lane 0 reads
+    // back is the claimed tile.
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (;;) {
-        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&a.ctl->next_tile, 1u);
+        if (wid == 0) {
+            const uint32_t mine = atomicAdd(&a.ctl->next_tile, lane == 0 ? 1u : 0u);
+            s_tile = (int)__builtin_amdgcn_readfirstlane(mine);  // all lanes store the same value
+        }
         __syncthreads();
-        const int t = s_tile;
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
         __syncthreads();
         if (t >= a.ntiles) break;
-        const TileDesc td = a.tiles[t];
-        const ClipDesc cd = a.clips[td.clip];
-        const DevState *st_ = a.states + td.clip;
+        const int clip = __builtin_amdgcn_readfirstlane(a.tiles[t].clip);
+        const int tx0 = __builtin_amdgcn_readfirstlane(a.tiles[t].x0);
+        const int ty0 = __builtin_amdgcn_readfirstlane(a.tiles[t].y0);
+        const ClipDesc cd = a.clips[clip];
+        const DevState *st_ = a.states + clip;
         double d1 = 0.0, d2 = 0.0;
-        if (!st_->done) {
-            const int cur = st_->cur;
+        if (!__builtin_amdgcn_readfirstlane(st_->done)) {
+            const int cur = __builtin_amdgcn_readfirstlane(st_->cur);
             FwdOp<ST> op;
             op.f = a.f + cd.offset;
             op.src = (cur ? a.buf1 : a.buf0) + cd.offset;
@@ -80,13 +96,18 @@ __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
             op.scale = (CT)st_->scale;
             op.plane = (size_t)cd.H * cd.W;
             op.pbytes = (uint32_t)(op.plane * sizeof(ST));
-            stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, cd.T, cd.H, cd.W, td.x0, td.y0, lds, d1, d2);
+            stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, __builtin_amdgcn_readfirstlane(cd.T),
+                                                           __builtin_amdgcn_readfirstlane(cd.H),
+                                                           __builtin_amdgcn_readfirstlane(cd.W), tx0, ty0, lds, d1,
+                                                           d2);
         }
+        // block sums land in thread 0 (lane 0 of wave 0); wave 0 broadcasts and stores them
         const double s1 = block_sum<NTHR>(d1, red);
         const double s2 = block_sum<NTHR>(d2, red);
-        if (threadIdx.x == 0) {
-            a.partials[2 * (size_t)t] = s1;
-            a.partials[2 * (size_t)t + 1] = s2;
+        if (wid == 0) {
+            const double b1 = __shfl(s1, 0, 64), b2 = __shfl(s2, 0, 64);
+            a.partials[2 * (size_t)t] = b1;  // same address and value in every lane
+            a.partials[2 * (size_t)t + 1] = b2;
         }
     }
 }
