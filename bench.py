@@ -33,6 +33,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Sources that define the f32 step kernel; the committed counter summary is
+# used only while their hash matches the one recorded with the counters.
+STEP_SOURCES = ["paper_2212_08058_amd/csrc/common.hpp", "paper_2212_08058_amd/csrc/stencil.hpp",
+                "paper_2212_08058_amd/csrc/forward.hpp", "paper_2212_08058_amd/csrc/kernels_f32.hip",
+                "paper_2212_08058_amd/csrc/host.cpp"]
+
+
+def profiled_traffic(tag: str):
+    """HBM bytes per launch from profiles/<tag>_hbm_counters.md (rocprofv3
+    FETCH_SIZE and WRITE_SIZE, calibrated on a streaming kernel of known
+    size), or None if the kernel sources changed since they were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{tag}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    rec = json.loads(text.split("```json")[1].split("```")[0])
+    h = hashlib.sha256()
+    for p in STEP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec["source_sha"]:
+        return None
+    return rec
+
+
 def cpu_baseline(f_np, kern, seconds: float):
     import numpy as np
 
@@ -68,7 +95,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=40, help="launches timed for the roofline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", default="bf16",
+    ap.add_argument("--extras", default="bf16,copy",
                     help="comma list of extra measurements to attach: bf16, batch, channels, warm (or none)")
     ap.add_argument("--warm-train", type=int, default=200, help="training clips for the warm-start extra")
     ap.add_argument("--warm-eval", type=int, default=10, help="evaluation clips for the warm-start extra")
@@ -165,6 +192,13 @@ def main():
         },
         "result": {"residual": res["residual"], "lambda": res["lambda_"], "iters": res["iters"]},
     }
+    prof = profiled_traffic(f"fwd_step_{T}x{H}x{W}_{args.dtype}")
+    if prof is not None:
+        out["roofline"]["traffic"] = prof["traffic_bytes"]
+        out["roofline"]["traffic_note"] = (f"HBM bytes per launch from rocprofv3 FETCH_SIZE x {prof['fetch_scale']:.3f} + "
+                                           f"WRITE_SIZE x {prof['write_scale']:.3f} (calibrated on a streaming kernel); "
+                                           f"{prof['traffic_bytes'] / (bytes_per_voxel * Nvox):.2f}x the algorithmic "
+                                           f"{bytes_per_voxel * Nvox} B")
     extras = [e for e in args.extras.split(",") if e and e != "none"]
     if "bf16" in extras and args.dtype == "f32":
         log("bf16 storage leg")
@@ -185,6 +219,31 @@ def main():
         out["bf16"] = {"value": Nvox * iters / dtb, "ms_per_step": dtb * 1e3, "kernel_ms": kb,
                        "hbm_gbs": 6 * Nvox / (kb * 1e-3) / 1e9,
                        "alu_tflops": flops_per_voxel * Nvox / (kb * 1e-3) / 1e12}
+    if "copy" in extras:
+        # A plain streaming kernel of known traffic (x = z / 1: reads and writes
+        # one array of the clip's size), timed like the step kernel. Its HBM
+        # counters calibrate the step kernel's measured traffic.
+        from paper_2212_08058_amd import _native as N
+        one = torch.ones(1, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(f)
+        code = 0 if args.dtype == "f32" else 1
+        sp = stream.cuda_stream
+
+        def launch():
+            N.check(N.lib.stpi_normalize(Nvox, code, f.data_ptr(), one.data_ptr(), dst.data_ptr(), sp))
+
+        for _ in range(3):
+            launch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.kernel_reps):
+            launch()
+        e1.record(stream)
+        e1.synchronize()
+        cms = e0.elapsed_time(e1) / args.kernel_reps
+        out["copy"] = {"kernel": "scale_by_norm_kernel (reads one array, writes one array)",
+                       "bytes_read": Nvox * elem, "bytes_written": Nvox * elem, "kernel_ms": cms,
+                       "gbs": 2 * Nvox * elem / (cms * 1e-3) / 1e9}
     from paper_2212_08058_amd import experiments as X
     if "batch" in extras:
         log("batched uneven clips")
