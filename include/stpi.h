@@ -122,6 +122,14 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
 int stpi_variant_count(int dtype);
 /* info[0..8] = RS, RT, TH, TW, NTHR, RY, QX, OCC (min waves per SIMD), PIPE (1: pipelined tile loop) of variant `index`; STPI_EINVAL if out of range. */
 int stpi_variant_info(int dtype, int index, int32_t info[9]);
+/* Launch shape the step of problem p uses with variant `variant` (-1: the
+ * variant stpi_step would choose): info[0] = variant index, info[1] = tiles
+ * per frame, info[2] = frame segments per tile (a tile's frames are split
+ * when the chip holds more resident workgroups than there are tiles; each
+ * segment re-reads r_t frames on each inner side), info[3] = workgroups per
+ * CU that fit at once, info[4] = workgroups launched. Queries the current
+ * device. STPI_EINVAL / STPI_EUNSUPPORTED as for stpi_step. */
+int stpi_launch_shape(const stpi_problem *p, int variant, int32_t info[5]);
 /* Force variant `index` for every later call in the process (-1: automatic
  * choice). A forced variant whose radii are too small makes calls fail with
  * STPI_EUNSUPPORTED. Not thread-safe against concurrent launches. */

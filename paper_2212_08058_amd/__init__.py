@@ -3,5 +3,5 @@
 The compute path is the HIP library libstpi.so (C ABI in include/stpi.h);
 this package only marshals torch tensors (device memory) and streams into it.
 """
-from .api import Kernel, power_iterate, problem_for, step, time_step, workspace_bytes  # noqa: F401
+from .api import Kernel, launch_shape, power_iterate, problem_for, step, time_step, workspace_bytes  # noqa: F401
 from ._native import StpiError  # noqa: F401

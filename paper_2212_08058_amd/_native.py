@@ -61,6 +61,7 @@ PROTOTYPES = [
     ("stpi_iterate", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _sz, _RP, _vp]),
     ("stpi_variant_count", ctypes.c_int, [ctypes.c_int]),
     ("stpi_variant_info", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
+    ("stpi_launch_shape", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
     ("stpi_set_variant", ctypes.c_int, [ctypes.c_int]),
     ("stpi_time_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _sz, ctypes.c_int, ctypes.c_int, _vp,
                                       ctypes.POINTER(ctypes.c_double)]),

@@ -122,6 +122,14 @@ def power_iterate(f: torch.Tensor, k: Kernel, iters: int | None = None, tol: flo
     return x, out
 
 
+def launch_shape(shape, k: Kernel, dtype: torch.dtype = torch.float32, variant: int = -1) -> dict:
+    """stpi_launch_shape: the variant, tiles, frame segments and workgroups a step uses."""
+    p = problem_for(shape, k, dtype)
+    a = (ctypes.c_int32 * 5)()
+    N.check(N.lib.stpi_launch_shape(ctypes.byref(p), int(variant), a))
+    return dict(zip(("variant", "tiles", "segments", "blocks_per_cu", "workgroups"), list(a)))
+
+
 def time_step(f: torch.Tensor, x: torch.Tensor, k: Kernel, z: torch.Tensor | None = None, reps: int = 20,
               variant: int = -1, ws: torch.Tensor | None = None, stream=None) -> float:
     """Average step-kernel duration in ms over `reps` launches (stpi_time_step, HIP events)."""

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(NTHR) void adj_step_kernel(AdjArgs<ST> a) {
     op.pbytes = (uint32_t)(op.plane * sizeof(ST));
     double d1 = 0.0, d2 = 0.0;
     const int x0 = (tile % nbx) * TW, y0 = (tile / nbx) * TH;
-    stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, a.H, a.W, x0, y0, lds, d1, d2);
+    stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, 0, a.T, a.H, a.W, x0, y0, lds, d1, d2);
     const double s1 = block_sum<NTHR>(d1, red);
     const double s2 = block_sum<NTHR>(d2, red);
     if (threadIdx.x == 0) {

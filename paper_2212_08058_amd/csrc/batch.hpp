@@ -96,8 +96,8 @@ __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
             op.scale = (CT)st_->scale;
             op.plane = (size_t)cd.H * cd.W;
             op.pbytes = (uint32_t)(op.plane * sizeof(ST));
-            stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, __builtin_amdgcn_readfirstlane(cd.T),
-                                                           __builtin_amdgcn_readfirstlane(cd.H),
+            const int T = __builtin_amdgcn_readfirstlane(cd.T);
+            stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, T, 0, T, __builtin_amdgcn_readfirstlane(cd.H),
                                                            __builtin_amdgcn_readfirstlane(cd.W), tx0, ty0, lds, d1,
                                                            d2);
         }

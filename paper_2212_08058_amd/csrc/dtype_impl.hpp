@@ -29,7 +29,8 @@ hipError_t normalize_impl(void *x, const void *buf1, size_t n, const DevState *s
 }
 
 #define STPI_VARIANT_ENTRY(RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE) \
-    {RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, &launch_fwd<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>},
+    {RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, &launch_fwd<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>, \
+     &fwd_blocks_per_cu<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>},
 
 const Variant kVariants[] = {STPI_VARIANTS(STPI_VARIANT_ENTRY)};
 

@@ -14,8 +14,9 @@ struct FwdLaunch {
     double x_scale;
     const double *norm_in;  // single step: if set, x_scale = 1 / *norm_in (read on the device)
     void *vout;             // if set, also store v = G (f x) (x unit) for the adjoint
-    double *partials;    // [gridblocks][2] doubles
+    double *partials;    // [tiles * nseg][2] doubles
     int T, H, W;
+    int nseg;            // frame segments per tile (0 is read as 1)
     double gs[2 * 16 + 1];
     double gt[2 * 8 + 1];
 };
@@ -24,6 +25,7 @@ struct FwdLaunch {
 struct Variant {
     int RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE;
     hipError_t (*launch)(const FwdLaunch &, hipStream_t);
+    int (*blocks_per_cu)();  // resident workgroups per CU (occupancy query)
 };
 
 template <class ST>
@@ -38,6 +40,7 @@ struct FwdArgs {
     const double *norm_in;
     ST *vout;
     int T, H, W;
+    int nseg;  // frame segments per tile: workgroup (tile, seg) owns frames [seg T / nseg, (seg + 1) T / nseg)
     Taps<CT> taps;
 };
 
@@ -103,6 +106,51 @@ struct FwdOp {
             }
         }
     }
+    // Fixed-count forms for the straight-line tile loop: every call issues the
+    // same memory instructions (one per element), whatever the tile position
+    // and whether the frame is emitted, so the compiler's memory-counter waits
+    // never have to cover a path with fewer operations. Elements outside the
+    // frame and non-emitted frames use out-of-range offsets (loads give 0,
+    // stores are dropped) and add nothing to the sums.
+    template <int IPT, int QX>
+    __device__ __forceinline__ void fetch_out_fixed(int t, const uint32_t (&off)[IPT][QX],
+                                                    OutRaw<IPT, QX> &raw) const {
+        const auto rf = make_rsrc(f + (size_t)t * plane, pbytes);
+        const auto rx = make_rsrc(src + (size_t)t * plane, pbytes);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                raw.f[i][q] = IO::load(rf, off[i][q]);
+                raw.x[i][q] = IO::load(rx, off[i][q]);
+            }
+    }
+    template <int IPT, int QX>
+    __device__ __forceinline__ void emit_frame_fixed(int t, bool emit, const CT (&acc)[IPT][QX],
+                                                     const OutRaw<IPT, QX> &raw, const uint32_t (&off)[IPT][QX],
+                                                     double &d1, double &d2) const {
+        const auto rz = make_rsrc(dst + (size_t)t * plane, pbytes);
+        if (vout) {
+            const auto rv = make_rsrc(vout + (size_t)t * plane, pbytes);
+#pragma unroll
+            for (int i = 0; i < IPT; ++i)
+#pragma unroll
+                for (int q = 0; q < QX; ++q) IO::store(rv, emit ? off[i][q] : OOB, scale * acc[i][q]);
+        }
+        double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                const CT z = scale * (raw.f[i][q] * acc[i][q]);
+                const double zs = (double)IO::rounded(z);
+                p2 = fma(zs, zs, p2);
+                p1 = fma(zs, (double)raw.x[i][q], p1);
+                IO::store(rz, emit ? off[i][q] : OOB, z);
+            }
+        d1 += emit ? p1 : 0.0;
+        d2 += emit ? p2 : 0.0;
+    }
     template <int IPT, int QX>
     __device__ __forceinline__ void emit_frame(int t, const CT (&acc)[IPT][QX], const OutRaw<IPT, QX> &raw,
                                                const uint32_t (&off)[IPT][QX], double &d1, double &d2) const {
@@ -136,8 +184,10 @@ struct FwdOp {
     }
 };
 
-// OCC: minimum waves per SIMD the register allocation must allow (1 = no limit).
-// PIPE: 1 selects the software-pipelined tile loop (stencil_tile_pipe).
+// OCC: minimum waves per SIMD the register allocation must allow (1 = no limit;
+// with NTHR = 512, OCC = 4 lets two workgroups share a CU).
+// PIPE: 1 selects the software-pipelined tile loop (stencil_tile_pipe), 2 its
+// straight-line form (stencil_tile_flat).
 template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>
 __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     using CT = typename Compute<ST>::type;
@@ -147,8 +197,11 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     __shared__ double red[NTHR / 64];
 
     const int nbx = (a.W + TW - 1) / TW, nby = (a.H + TH - 1) / TH;
-    const int tile = xcd_tile(blockIdx.x, nbx * nby);
-    if (tile < 0) return;
+    // consecutive units (the segments of one tile, then the next tile) share an XCD
+    const int unit = xcd_tile(blockIdx.x, nbx * nby * a.nseg);
+    if (unit < 0) return;
+    const int tile = unit / a.nseg, seg = unit % a.nseg;
+    const int t0 = (int)((int64_t)seg * a.T / a.nseg), t1 = (int)((int64_t)(seg + 1) * a.T / a.nseg);
     FwdOp<ST> op;
     op.f = a.f;
     if (a.state) {
@@ -167,15 +220,17 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     op.pbytes = (uint32_t)(op.plane * sizeof(ST));
     double d1 = 0.0, d2 = 0.0;
     const int x0 = (tile % nbx) * TW, y0 = (tile / nbx) * TH;
-    if constexpr (PIPE)
-        stencil_tile_pipe<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, a.H, a.W, x0, y0, lds, d1, d2);
+    if constexpr (PIPE == 2)
+        stencil_tile_flat<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1, d2);
+    else if constexpr (PIPE == 1)
+        stencil_tile_pipe<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1, d2);
     else
-        stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, a.H, a.W, x0, y0, lds, d1, d2);
+        stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1, d2);
     const double s1 = block_sum<NTHR>(d1, red);
     const double s2 = block_sum<NTHR>(d2, red);
     if (threadIdx.x == 0) {
-        a.partials[2 * tile] = s1;
-        a.partials[2 * tile + 1] = s2;
+        a.partials[2 * unit] = s1;
+        a.partials[2 * unit + 1] = s2;
     }
 }
 
@@ -194,17 +249,27 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     a.T = L.T;
     a.H = L.H;
     a.W = L.W;
+    a.nseg = L.nseg > 0 ? L.nseg : 1;
     // L holds taps centred at index 16 (space) and 8 (time), zero beyond the
     // problem's radii; the kernel wants them centred at its compiled RS, RT.
     for (int i = 0; i < 2 * 16 + 1; ++i) a.taps.gs[i] = CT(0);
     for (int i = 0; i < 2 * 8 + 1; ++i) a.taps.gt[i] = CT(0);
     for (int d = -RS; d <= RS; ++d) a.taps.gs[d + RS] = (CT)L.gs[d + 16];
     for (int d = -RT; d <= RT; ++d) a.taps.gt[d + RT] = (CT)L.gt[d + 8];
-    const int ntiles = ((L.W + TW - 1) / TW) * ((L.H + TH - 1) / TH);
-    const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+    const int nunits = ((L.W + TW - 1) / TW) * ((L.H + TH - 1) / TH) * a.nseg;
+    const int per = (nunits + NUM_XCD - 1) / NUM_XCD;
     hipLaunchKernelGGL((fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>), dim3(per * NUM_XCD), dim3(NTHR), 0,
                        stream, a);
     return hipGetLastError();
+}
+
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>
+int fwd_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>, NTHR, 0) != hipSuccess)
+        n = 1;
+    return n > 0 ? n : 1;
 }
 
 }  // namespace stpi

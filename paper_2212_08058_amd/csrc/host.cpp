@@ -105,9 +105,39 @@ const Variant *choose_variant(const stpi_problem *p, int forced_index) {
     return best;
 }
 
-int grid_blocks(const Variant &v, const stpi_problem *p) {
+static int tiles_for(const Variant &v, const stpi_problem *p) {
     return ((p->W + v.TW - 1) / v.TW) * ((p->H + v.TH - 1) / v.TH);
 }
+
+static int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        hipDeviceProp_t prop;
+        cus[dev] = hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0
+                       ? prop.multiProcessorCount
+                       : 256;
+    }
+    return cus[dev];
+}
+
+// Frame segments per tile. When a clip has fewer tiles than the chip holds
+// resident workgroups, each tile's frames are split so that more workgroups
+// (with independent barriers) share every CU. A segment re-reads and
+// re-filters RT input frames on each inner side, so segments are kept at
+// least 4 RT frames long and their count at most STPI_NSEG_MAX.
+int segments_for(const Variant &v, const stpi_problem *p) {
+    const int tiles = tiles_for(v, p);
+    const int resident = device_cus() * v.blocks_per_cu();
+    int nseg = resident / tiles;
+    const int by_len = p->T / (4 * (v.RT > 0 ? v.RT : 1));
+    if (nseg > by_len) nseg = by_len;
+    if (nseg > STPI_NSEG_MAX) nseg = STPI_NSEG_MAX;
+    return nseg > 1 ? nseg : 1;
+}
+
+int grid_blocks(const Variant &v, const stpi_problem *p) { return tiles_for(v, p) * segments_for(v, p); }
 
 // Workspace: [state 256 B][partials][ping-pong volume]. The partials area
 // holds the largest grid any compiled variant can use for this frame size.
@@ -115,7 +145,7 @@ size_t partials_capacity(const stpi_problem *p) {
     const DtypeOps *ops = ops_for(p->dtype);
     size_t cap = (size_t)NORM_BLOCKS_HOST;
     for (int i = 0; i < ops->nvariants; ++i) {
-        const size_t g = (size_t)grid_blocks(ops->variants[i], p);
+        const size_t g = (size_t)tiles_for(ops->variants[i], p) * STPI_NSEG_MAX;
         if (g > cap) cap = g;
     }
     for (int i = 0; i < ops->nadj; ++i) {
@@ -228,6 +258,7 @@ int stpi_step(const stpi_problem *p, const void *f, const void *x, double x_scal
     FL.T = p->T;
     FL.H = p->H;
     FL.W = p->W;
+    FL.nseg = segments_for(*v, p);
     make_taps(p, FL.gs, FL.gt);
     hipError_t e = v->launch(FL, s);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
@@ -353,6 +384,7 @@ int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z,
     FL.T = p->T;
     FL.H = p->H;
     FL.W = p->W;
+    FL.nseg = segments_for(*v, p);
     make_taps(p, FL.gs, FL.gt);
     hipEvent_t e0, e1;
     hipError_t e;
@@ -397,6 +429,23 @@ int stpi_variant_info(int dtype, int index, int32_t info[9]) {
     return STPI_OK;
 }
 
+int stpi_launch_shape(const stpi_problem *p, int variant, int32_t info[5]) {
+    clear_error();
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    if (!info) return fail(STPI_EINVAL, "NULL info");
+    const DtypeOps *ops = ops_for(p->dtype);
+    const Variant *v = choose_variant(p, variant >= 0 ? variant : forced_variant());
+    if (!v) return fail(STPI_EUNSUPPORTED, "no compiled kernel for radii (%d, %d)", p->r_s, p->r_t);
+    const int nseg = segments_for(*v, p);
+    info[0] = (int32_t)(v - ops->variants);
+    info[1] = grid_blocks(*v, p) / nseg;
+    info[2] = nseg;
+    info[3] = v->blocks_per_cu();
+    info[4] = grid_blocks(*v, p);
+    return STPI_OK;
+}
+
 int stpi_set_variant(int index) {
     clear_error();
     if (index < -1) return fail(STPI_EINVAL, "variant index must be >= -1");
@@ -436,6 +485,7 @@ int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant 
     FL.T = p->T;
     FL.H = p->H;
     FL.W = p->W;
+    FL.nseg = segments_for(*v, p);
     make_taps(p, FL.gs, FL.gt);
     const int nb = grid_blocks(*v, p);
     for (int k = 0; k < max_iters; ++k) {

@@ -27,6 +27,8 @@ int validate_problem(const stpi_problem *p);
 void make_taps(const stpi_problem *p, double *gs, double *gt);
 const Variant *choose_variant(const stpi_problem *p, int forced_index);
 int grid_blocks(const Variant &v, const stpi_problem *p);
+int segments_for(const Variant &v, const stpi_problem *p);
+constexpr int STPI_NSEG_MAX = 4;  // frame segments per tile at most
 WsLayout layout_for(const stpi_problem *p);
 int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
                       void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,

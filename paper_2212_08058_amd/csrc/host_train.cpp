@@ -81,6 +81,7 @@ int stpi_train_step(const stpi_problem *p, const void *f, const void *z_in, cons
     FL.T = p->T;
     FL.H = p->H;
     FL.W = p->W;
+    FL.nseg = segments_for(*v, p);
     make_taps(p, FL.gs, FL.gt);
     hipError_t e = v->launch(FL, s);
     if (e != hipSuccess) return hip_fail(e, "train step launch");

@@ -24,6 +24,8 @@
 // tiles share are then read through the same L2.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace stpi {
@@ -179,21 +181,40 @@ __device__ __forceinline__ void ring_scatter(CT (&acc)[2 * RT + 1][IPT][QX], con
 }
 
 // t-scatter of one input frame at ring position J, then the epilogue of the
-// output frame tin - RT (or, before the clip starts, only clearing its slot:
-// it collected contributions to a frame that does not exist).
+// output frame tout = tin - RT if the block owns it (otherwise only clearing
+// its slot: it collected contributions to a frame that does not exist or
+// belongs to the previous frame segment).
 template <int J, class CT, int RT, int IPT, int QX, class Op, class ORaw>
 __device__ __forceinline__ void ring_step(CT (&acc)[2 * RT + 1][IPT][QX], const CT (&v)[IPT][QX],
-                                          const Taps<CT> &tp, bool scatter, int tin, const Op &op,
+                                          const Taps<CT> &tp, bool scatter, bool emit, int tout, const Op &op,
                                           const uint32_t (&ooff)[IPT][QX], const ORaw &oraw, double &d1,
                                           double &d2) {
     constexpr int NTS = 2 * RT + 1;
     if (scatter) ring_scatter<J, -RT, RT>(acc, v, tp);
     constexpr int es = ((J - RT) % NTS + NTS) % NTS;
-    if (tin >= RT) op.emit_frame(tin - RT, acc[es], oraw, ooff, d1, d2);
+    if (emit) op.emit_frame(tout, acc[es], oraw, ooff, d1, d2);
 #pragma unroll
     for (int i = 0; i < IPT; ++i)
 #pragma unroll
         for (int q = 0; q < QX; ++q) acc[es][i][q] = CT(0);
+}
+
+// Frame loop unrolled by the ring length: body(J, p) runs for p = 0 .. n-1
+// with J = (p + SHIFT) mod NTS as a compile-time constant. Every pass of the
+// outer loop walks the ring once, so each ring slot stays in the same
+// registers across the back-edge (a runtime ring index makes the compiler
+// re-copy the whole ring at every frame).
+template <int NTS, int SHIFT, int J, class F>
+__device__ __forceinline__ void ring_loop_unroll(int base, int n, F &body) {
+    if constexpr (J < NTS) {
+        if (base + J < n) body(std::integral_constant<int, ((J + SHIFT) % NTS + NTS) % NTS>{}, base + J);
+        ring_loop_unroll<NTS, SHIFT, J + 1>(base, n, body);
+    }
+}
+
+template <int NTS, int SHIFT, class F>
+__device__ __forceinline__ void ring_loop(int n, F &&body) {
+    for (int base = 0; base < n; base += NTS) ring_loop_unroll<NTS, SHIFT, 0>(base, n, body);
 }
 
 // Streams one tile through all frames. Op (forward step or adjoint step)
@@ -209,9 +230,11 @@ __device__ __forceinline__ void ring_step(CT (&acc)[2 * RT + 1][IPT][QX], const 
 //   template <int IPT, int QX> void emit_frame(int t, const CT (&acc)[IPT][QX],
 //       const OutRaw<IPT, QX> &raw, const uint32_t (&boff)[IPT][QX], double &d1, double &d2)
 //       epilogue of output frame t (OOB offsets are dropped stores, zero sums)
+// The block produces output frames [t0, t1) of a clip of T frames; it reads
+// input frames [t0 - RT, t1 + RT) clipped to the clip.
 template <class CT, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, class Op>
-__device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, int T, int H, int W, int x0,
-                                             int y0, CT *lds, double &d1, double &d2) {
+__device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, int T, int t0, int t1, int H, int W,
+                                             int x0, int y0, CT *lds, double &d1, double &d2) {
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
     constexpr int NC = G::NC, NU = G::NU, NPF = G::NPF, LW = G::LW, RSA = G::RSA;
     constexpr int NYI = G::NYI, NQ = G::NQ, NXI = G::NXI, IPT = G::IPT, NTS = G::NTS;
@@ -254,24 +277,32 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
 #pragma unroll
             for (int q = 0; q < QX; ++q) acc[s][i][q] = CT(0);
 
+    const int ts = t0 - RT > 0 ? t0 - RT : 0;  // first input frame
+    const int te = t1 + RT < T ? t1 + RT : T;  // one past the last input frame
     typename Op::template Raw<NPF> pf;
-    op.template fetch<NPF>(0, poff, pf);
+    op.template fetch<NPF>(ts, poff, pf);
 
     typename Op::template OutRaw<IPT, QX> oraw;
-    const int tend = T + RT;
-    for (int tin = 0; tin < tend; ++tin) {
+    // local step i takes input frame ts + i (none once past te) and emits
+    // output frame ts + i - RT when the block owns it
+    ring_loop<NTS, 0>(t1 + RT - ts, [&](auto ring_pos, int i) __attribute__((always_inline)) {
+        constexpr int J = decltype(ring_pos)::value;  // i % NTS
         CT v[IPT][QX];
-        const bool live = tin < T;
-        // the epilogue's operands load while this frame is filtered
-        if (tin >= RT) op.template fetch_out<IPT, QX>(tin - RT, ooff, oraw);
+        const int tin = ts + i;
+        const bool live = tin < te;
+        const int tout = tin - RT;
+        const bool emit = tout >= t0;
         if (live) {
-            // stage this frame's prefetched input, then prefetch the next one
+            // stage this frame's prefetched input; then the epilogue's operands
+            // load while this frame is filtered (after the staging: loads
+            // complete in issue order), then the next frame's prefetch
 #pragma unroll
             for (int k = 0; k < NPF; ++k) {
                 const int e = tid + k * NTHR;
                 if (NU % NTHR == 0 || k < NPF - 1 || e < NU) U[e] = op.template input<NPF>(pf, k);
             }
-            if (tin + 1 < T) op.template fetch<NPF>(tin + 1, poff, pf);
+            if (emit) op.template fetch_out<IPT, QX>(tout, ooff, oraw);
+            if (tin + 1 < te) op.template fetch<NPF>(tin + 1, poff, pf);
             __syncthreads();
             // y-pass
             for (int it = tid; it < NYI; it += NTHR) {
@@ -315,25 +346,14 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
                 }
             }
         } else {
+            if (emit) op.template fetch_out<IPT, QX>(tout, ooff, oraw);
 #pragma unroll
             for (int i = 0; i < IPT; ++i)
 #pragma unroll
                 for (int q = 0; q < QX; ++q) v[i][q] = CT(0);
         }
-        // ring position of this frame; a switch (not a call chain) keeps the
-        // accumulators in registers
-        switch (tin % NTS) {
-#define STPI_RING_CASE(J)                                                                           \
-    case J:                                                                                         \
-        if constexpr (J < NTS) ring_step<J, CT, RT, IPT, QX>(acc, v, tp, live, tin, op, ooff, oraw, d1, d2); \
-        break;
-            STPI_RING_CASE(0) STPI_RING_CASE(1) STPI_RING_CASE(2) STPI_RING_CASE(3) STPI_RING_CASE(4)
-            STPI_RING_CASE(5) STPI_RING_CASE(6) STPI_RING_CASE(7) STPI_RING_CASE(8) STPI_RING_CASE(9)
-            STPI_RING_CASE(10) STPI_RING_CASE(11) STPI_RING_CASE(12) STPI_RING_CASE(13) STPI_RING_CASE(14)
-            STPI_RING_CASE(15) STPI_RING_CASE(16)
-#undef STPI_RING_CASE
-        }
-    }
+        ring_step<J, CT, RT, IPT, QX>(acc, v, tp, live, emit, tout, op, ooff, oraw, d1, d2);
+    });
 }
 
 // Software-pipelined variant of stencil_tile. Each phase p (one barrier per
@@ -348,15 +368,15 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
 template <int RS, int RT, int TH, int TW, int NTHR, int RY, int QX>
 struct PipeGeometry {
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
-    static constexpr int UB = G::NUP;         // one U buffer (16-byte aligned size)
+    static constexpr int UB = (G::NU + 1 + 3) & ~3;  // one U buffer, one spare slot, 16-byte aligned size
     static constexpr int YB = TH * G::LW;     // one Y buffer
     static constexpr int LDS_ELEMS = 2 * UB + 2 * YB;
     static constexpr int NYT = (G::NYI + NTHR - 1) / NTHR;  // y-pass items per thread
 };
 
 template <class CT, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, class Op>
-__device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &tp, int T, int H, int W, int x0,
-                                                  int y0, CT *lds, double &d1, double &d2) {
+__device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &tp, int T, int t0, int t1, int H,
+                                                  int W, int x0, int y0, CT *lds, double &d1, double &d2) {
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
     using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
     constexpr int NC = G::NC, NU = G::NU, NPF = G::NPF, LW = G::LW, RSA = G::RSA;
@@ -399,26 +419,34 @@ __device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &
 #pragma unroll
             for (int q = 0; q < QX; ++q) acc[s][i][q] = CT(0);
 
+    const int ts = t0 - RT > 0 ? t0 - RT : 0;  // first input frame
+    const int te = t1 + RT < T ? t1 + RT : T;  // one past the last input frame
+    const int nin = te - ts;                   // input frames (local 0 .. nin - 1)
     typename Op::template Raw<NPF> pf;
-    op.template fetch<NPF>(0, poff, pf);
+    op.template fetch<NPF>(ts, poff, pf);
     typename Op::template OutRaw<IPT, QX> oraw;
 
-    const int nphase = T + RT + 2;
-    for (int p = 0; p < nphase; ++p) {
-        const int tx = p - 2;  // frame of the x-pass / ring step
-        if (tx >= RT && tx - RT < T) op.template fetch_out<IPT, QX>(tx - RT, ooff, oraw);
-        // stage frame p
-        if (p < T) {
+    // local frame i is input frame ts + i; its output slot holds frame ts + i - RT
+    const int nphase = t1 + RT - ts + 2;
+    ring_loop<NTS, -2>(nphase, [&](auto ring_pos, int p) __attribute__((always_inline)) {
+        constexpr int J = decltype(ring_pos)::value;  // (p - 2) mod NTS
+        const int tx = p - 2;  // local frame of the x-pass / ring step
+        const int tout = ts + tx - RT;
+        const bool emit = tx >= 0 && tout >= t0;
+        // stage local frame p; the epilogue's loads are issued after the staged
+        // values are consumed (loads complete in issue order)
+        if (p < nin) {
             CT *U = U0 + (p & 1) * PG::UB;
 #pragma unroll
             for (int k = 0; k < NPF; ++k) {
                 const int e = tid + k * NTHR;
                 if (NU % NTHR == 0 || k < NPF - 1 || e < NU) U[e] = op.template input<NPF>(pf, k);
             }
-            if (p + 1 < T) op.template fetch<NPF>(p + 1, poff, pf);
         }
-        // y-pass of frame p - 1
-        if (p >= 1 && p - 1 < T) {
+        if (emit) op.template fetch_out<IPT, QX>(tout, ooff, oraw);
+        if (p + 1 < nin) op.template fetch<NPF>(ts + p + 1, poff, pf);
+        // y-pass of local frame p - 1
+        if (p >= 1 && p - 1 < nin) {
             const CT *U = U0 + ((p - 1) & 1) * PG::UB;
             CT *Y = Y0 + ((p - 1) & 1) * PG::YB;
 #pragma unroll
@@ -445,7 +473,7 @@ __device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &
         // x-pass, t-ring and epilogue of frame p - 2
         if (tx >= 0) {
             CT v[IPT][QX];
-            const bool live = tx < T;
+            const bool live = tx < nin;
             if (live) {
                 const CT *Y = Y0 + (tx & 1) * PG::YB;
 #pragma unroll
@@ -475,20 +503,163 @@ __device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &
 #pragma unroll
                     for (int q = 0; q < QX; ++q) v[i][q] = CT(0);
             }
-            switch (tx % NTS) {
-#define STPI_RING_CASE(J)                                                                               \
-    case J:                                                                                             \
-        if constexpr (J < NTS) ring_step<J, CT, RT, IPT, QX>(acc, v, tp, live, tx, op, ooff, oraw, d1, d2); \
-        break;
-                STPI_RING_CASE(0) STPI_RING_CASE(1) STPI_RING_CASE(2) STPI_RING_CASE(3) STPI_RING_CASE(4)
-                STPI_RING_CASE(5) STPI_RING_CASE(6) STPI_RING_CASE(7) STPI_RING_CASE(8) STPI_RING_CASE(9)
-                STPI_RING_CASE(10) STPI_RING_CASE(11) STPI_RING_CASE(12) STPI_RING_CASE(13) STPI_RING_CASE(14)
-                STPI_RING_CASE(15) STPI_RING_CASE(16)
-#undef STPI_RING_CASE
-            }
+            ring_step<J, CT, RT, IPT, QX>(acc, v, tp, live, emit, tout, op, ooff, oraw, d1, d2);
         }
         __syncthreads();
+    });
+}
+
+
+// Straight-line form of stencil_tile_pipe: the same three-stage schedule, but
+// a phase's staging, prefetch, y-pass, x-pass and t-scatter run without
+// branches, so the compiler can interleave one pass's LDS reads with another
+// pass's FMAs. Out-of-range work is made harmless instead of skipped:
+//   - staging past the last input frame writes a U buffer that only a
+//     non-live frame reads; the prefetch re-reads the last frame;
+//   - lanes past the last y-pass item redo the last item (same values to the
+//     same addresses); surplus staging lanes write one spare slot;
+//   - the x-pass result of a non-live frame is replaced by zero before the
+//     t-scatter.
+// Only the epilogue (loads, stores and sums of an owned output frame) is
+// conditional.
+template <class CT, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, class Op>
+__device__ __forceinline__ void stencil_tile_flat(const Op &op, const Taps<CT> &tp, int T, int t0, int t1, int H,
+                                                  int W, int x0, int y0, CT *lds, double &d1, double &d2) {
+    using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    constexpr int NC = G::NC, NU = G::NU, NPF = G::NPF, LW = G::LW, RSA = G::RSA;
+    constexpr int NYI = G::NYI, NQ = G::NQ, NXI = G::NXI, IPT = G::IPT, NTS = G::NTS, NYT = PG::NYT;
+    constexpr uint32_t ESZ = Op::ESZ;
+    const int tid = threadIdx.x;
+    CT *const U0 = lds;
+    CT *const Y0 = lds + 2 * PG::UB;
+
+    uint32_t poff[NPF];
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+        const int e = tid + k * NTHR;
+        const int r = e / NC, c = e % NC;
+        const int gy = y0 - RS + r, gx = x0 - RS + c;
+        const bool ok = e < NU && (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+        poff[k] = ok ? (uint32_t)(gy * W + gx) * ESZ : OOB;
     }
+    // only the last staged element can lie past the tile (NPF = ceil(NU / NTHR)):
+    // those lanes write the spare slot NU
+    const int elast = tid + (NPF - 1) * NTHR < NU ? tid + (NPF - 1) * NTHR : NU;
+    // y-pass items of this thread (clamped to the last item)
+    int ycol[NYT], yrow0[NYT];
+#pragma unroll
+    for (int m = 0; m < NYT; ++m) {
+        int it = tid + m * NTHR;
+        it = it < NYI ? it : NYI - 1;
+        ycol[m] = it % NC;
+        yrow0[m] = (it / NC) * RY;
+    }
+    uint32_t ooff[IPT][QX];
+    int orow[IPT], ocol[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int item = (NTHR - 1 - tid) + i * NTHR;
+        const bool olive = item < NXI;
+        orow[i] = olive ? item / NQ : 0;
+        ocol[i] = olive ? (item % NQ) * QX : 0;
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int gy = y0 + orow[i], gx = x0 + ocol[i] + q;
+            ooff[i][q] = (olive && gy < H && gx < W) ? (uint32_t)(gy * W + gx) * ESZ : OOB;
+        }
+    }
+
+    CT acc[NTS][IPT][QX];
+#pragma unroll
+    for (int s = 0; s < NTS; ++s)
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+#pragma unroll
+            for (int q = 0; q < QX; ++q) acc[s][i][q] = CT(0);
+
+    const int ts = t0 - RT > 0 ? t0 - RT : 0;  // first input frame
+    const int te = t1 + RT < T ? t1 + RT : T;  // one past the last input frame
+    const int nin = te - ts;                   // input frames (local 0 .. nin - 1)
+    typename Op::template Raw<NPF> pf;
+    op.template fetch<NPF>(ts, poff, pf);
+    typename Op::template OutRaw<IPT, QX> oraw;
+
+    const int nphase = t1 + RT - ts + 2;
+    ring_loop<NTS, -2>(nphase, [&](auto ring_pos, int p) __attribute__((always_inline)) {
+        constexpr int J = decltype(ring_pos)::value;  // (p - 2) mod NTS
+        const int tx = p - 2;                         // local frame of the x-pass / t-scatter
+        const int tout = ts + tx - RT;
+        const bool emit = tx >= 0 && tout >= t0;
+        const bool xlive = tx >= 0 && tx < nin;
+        // stage local frame p, then issue the epilogue's loads (every phase, a
+        // valid frame, so the count is fixed) and the prefetch of local frame
+        // p + 1 (clamped). Loads complete in issue order: issuing the epilogue's
+        // before consuming the prefetch would make the staging wait for them.
+        {
+            CT *U = U0 + (p & 1) * PG::UB;
+#pragma unroll
+            for (int k = 0; k < NPF - 1; ++k) U[tid + k * NTHR] = op.template input<NPF>(pf, k);
+            U[elast] = op.template input<NPF>(pf, NPF - 1);
+            op.template fetch_out_fixed<IPT, QX>(tout >= t0 ? tout : t0, ooff, oraw);
+            const int pn = p + 1 < nin ? p + 1 : nin - 1;
+            op.template fetch<NPF>(ts + pn, poff, pf);
+        }
+        // y-pass of local frame p - 1
+        {
+            const CT *U = U0 + ((p - 1) & 1) * PG::UB;
+            CT *Y = Y0 + ((p - 1) & 1) * PG::YB;
+#pragma unroll
+            for (int m = 0; m < NYT; ++m) {
+                const CT *col = U + yrow0[m] * NC + ycol[m];
+                CT u[RY + 2 * RS];
+#pragma unroll
+                for (int k = 0; k < RY + 2 * RS; ++k) u[k] = col[k * NC];
+                CT *dstp = Y + yrow0[m] * LW + ycol[m] + (RSA - RS);
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    CT s = CT(0);
+#pragma unroll
+                    for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], u[r + d], s);
+                    dstp[r * LW] = s;
+                }
+            }
+        }
+        // x-pass of local frame tx, then its t-scatter
+        CT v[IPT][QX];
+        {
+            const CT *Y = Y0 + (tx & 1) * PG::YB;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                using V4 = LdsVec<CT>;
+                constexpr int NV = (QX + 2 * RSA) / V4::N;
+                const typename V4::type *rowp = reinterpret_cast<const typename V4::type *>(
+                    __builtin_assume_aligned(Y + orow[i] * LW + ocol[i], 16));
+                CT w[QX + 2 * RSA];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    const typename V4::type t4 = rowp[k];
+#pragma unroll
+                    for (int e = 0; e < V4::N; ++e) w[k * V4::N + e] = t4[e];
+                }
+#pragma unroll
+                for (int q = 0; q < QX; ++q) {
+                    CT s = CT(0);
+#pragma unroll
+                    for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], w[q + d + RSA - RS], s);
+                    v[i][q] = xlive ? s : CT(0);
+                }
+            }
+        }
+        ring_scatter<J, -RT, RT>(acc, v, tp);
+        constexpr int es = ((J - RT) % NTS + NTS) % NTS;
+        op.template emit_frame_fixed<IPT, QX>(tout >= t0 ? tout : t0, emit, acc[es], oraw, ooff, d1, d2);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+#pragma unroll
+            for (int q = 0; q < QX; ++q) acc[es][i][q] = CT(0);
+        __syncthreads();
+    });
 }
 
 }  // namespace stpi

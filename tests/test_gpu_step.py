@@ -297,3 +297,45 @@ def test_full_size_sampled_step(P):
         err = rel_l2(zs, ref)
         print("full-size sampled step", dtype, err)
         assert err <= TOL[dtype]
+
+
+def test_frame_segments_match_oracle(P):
+    """Every variant at the full 64 x 480 x 854 shape (r = (15, 5) and (8, 3)),
+    in whatever frame-segment split it launches with; sampled voxels include
+    every frame within r_t + 1 of each segment boundary."""
+    from paper_2212_08058_amd import _native as N
+    import ctypes
+    c = synth.CONFIGS["full"]
+    f, _ = synth.blob_clip(c["T"], c["H"], c["W"], c["nblobs"], c["seed"])
+    rng = np.random.default_rng(21)
+    x = rng.uniform(0.0, 1.0, f.shape).astype(np.float32)
+    T, H, W = f.shape
+    fd, xd = to_dev(f, torch.float32), to_dev(x, torch.float32)
+    seen_split = False
+    try:
+        for kern in (P.Kernel(5.0, 2.0, 15, 5), P.Kernel(4.0, 1.5, 8, 3)):
+            k = OKf(kern.sigma_s, kern.sigma_t, kern.r_s, kern.r_t)
+            for i in range(N.lib.stpi_variant_count(N.STPI_F32)):
+                info = (ctypes.c_int * 9)()
+                N.lib.stpi_variant_info(N.STPI_F32, i, info)
+                if info[0] < kern.r_s or info[1] < kern.r_t or info[0] > kern.r_s + 1:
+                    continue
+                shape = P.launch_shape(f.shape, kern, variant=i)
+                nseg = shape["segments"]
+                seen_split |= nseg > 1
+                bounds = sorted({s * T // nseg for s in range(1, nseg)})
+                frames = sorted({t for b in bounds for t in range(b - kern.r_t - 1, b + kern.r_t + 1)} | {0, T - 1})
+                pts = [(t, y, xx) for t in frames for y in (0, 7, H // 2, H - 1) for xx in (0, 100, W // 2, W - 1)]
+                idx = np.array([(t * H + y) * W + xx for t, y, xx in pts] + list(rng.integers(0, f.size, 300)),
+                               dtype=np.int64)
+                ref = oracle.apply_at(f, x, k, idx)
+                assert N.lib.stpi_set_variant(i) == 0
+                z, _ = P.step(fd, xd, kern)
+                torch.cuda.synchronize()
+                zs = z.double().reshape(-1)[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+                err = rel_l2(zs, ref)
+                print("variant", i, list(info), shape, err)
+                assert err <= 1e-5
+    finally:
+        N.lib.stpi_set_variant(-1)
+    assert seen_split, "no compiled variant split the frames at this shape"
