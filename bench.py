@@ -99,6 +99,7 @@ def main():
                     help="comma list of extra measurements to attach: bf16, batch, channels, warm (or none)")
     ap.add_argument("--warm-train", type=int, default=200, help="training clips for the warm-start extra")
     ap.add_argument("--warm-eval", type=int, default=10, help="evaluation clips for the warm-start extra")
+    ap.add_argument("--warm-epochs", type=int, default=2, help="training epochs for the warm-start extra")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -253,8 +254,8 @@ def main():
         out["channels"] = X.channel_training_step(log=log)
     if "warm" in extras:
         log("warm start vs plain")
-        r = X.warm_start_experiment(n_train=args.warm_train, n_eval=args.warm_eval, log=log)
-        r.pop("rows", None)
+        r = X.warm_start_experiment(n_train=args.warm_train, n_eval=args.warm_eval, epochs=args.warm_epochs, log=log)
+        r.pop("iters", None)
         out["warm"] = r
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample")

@@ -264,6 +264,27 @@ int stpi_bce(int64_t n, int dtype, const void *x, const uint8_t *gt, double *los
 int stpi_adamw(int64_t n, int dtype, void *w, const void *g, void *m, void *v, void *vmax, int step, double lr,
                double beta1, double beta2, double eps, double weight_decay, int amsgrad, void *stream);
 
+/* ---- two-level start: grid transfer -------------------------------------------
+ * The slowest modes of the power iteration on multi-object clips compete
+ * between objects far apart; an iteration on a coarse grid (cheap: sy^2 st
+ * times fewer voxels) resolves them, and its eigenvector, carried back to the
+ * full grid, starts the full iteration. Not part of the paper; its own warm
+ * start reuses the previous sub-window's solution (Sec. 4.4).
+ * Coarse size: Tc = ceil(T / st), Hc = ceil(H / sy), Wc = ceil(W / sy). */
+/* out[tc][yc][xc] = mean of in[t][y][x] over the voxels of block
+ * [tc st, (tc+1) st) x [yc sy, (yc+1) sy) x [xc sy, (xc+1) sy) inside the
+ * volume (partial blocks at the far edges average what exists). in: T x H x W,
+ * out: Tc x Hc x Wc, both of storage type dtype, device, out must not alias in.
+ * Asynchronous on `stream`. STPI_EINVAL for bad sizes, factors < 1, NULL or
+ * aliased buffers (checked before launch). */
+int stpi_downsample(int T, int H, int W, int sy, int st, int dtype, const void *in, void *out, void *stream);
+/* out (T x H x W) = up(in) (Tc x Hc x Wc), times mul[i] if mul is not NULL.
+ * mode 0: the coarse cell holding the voxel; mode 1: cell-centred trilinear,
+ * coarse coordinate c = (i + 1/2) / s - 1/2 per axis, clamped to [0, n - 1].
+ * out must not alias in or mul. Asynchronous; errors as stpi_downsample. */
+int stpi_upsample(int T, int H, int W, int sy, int st, int mode, int dtype, const void *in, const void *mul, void *out,
+                  void *stream);
+
 /* ---- learned warm start ------------------------------------------------------
  * A small 3D convolutional network predicts the start vector of the iteration
  * from f (the paper's own warm start is the previous sub-window's solution,

@@ -23,6 +23,11 @@ What it computes, each function citing the passage it restates:
 * ``net_forward``/``net_backward``: 4-layer 3x3x3 'same' conv net (C).
 * ``adamw_step``: AdamW with AMSGrad (Eq. 13).
 * ``fallback``: warm-start fallback rule.
+* ``downsample``/``upsample``/``coarse_kernel``: grid transfer for the
+  two-level start (box average; nearest-cell or cell-centred trilinear
+  prolongation) and the coarse filter. Not from the paper (its warm start is
+  the previous sub-window's solution, Sec. 4.4): restated from the textbook
+  definitions, each per output voxel.
 
 Readings of points the paper leaves open (unnormalised Gaussian with G(0)=1,
 the 2*sigma^2 convention, box support, zero padding, global normalisation,
@@ -449,3 +454,69 @@ def adamw_step(w, g, m, v, vmax, step: int, lr: float, beta1=0.9, beta2=0.999, e
 def fallback(r1: float, r2: float) -> bool:
     """Warm-start fallback: restart from uniform when the residual rises (r2 > r1)."""
     return not (r2 <= r1)
+
+
+def _coarse_size(n: int, s: int) -> int:
+    return (n + s - 1) // s
+
+
+def downsample(f, sy: int, st: int) -> np.ndarray:
+    """Box average over sy x sy pixels and st frames; partial blocks at the
+    far edges average the voxels that exist."""
+    f = _f64(f)
+    T, H, W = f.shape
+    Tc, Hc, Wc = _coarse_size(T, st), _coarse_size(H, sy), _coarse_size(W, sy)
+    out = np.empty((Tc, Hc, Wc))
+    for tc in range(Tc):
+        for yc in range(Hc):
+            for xc in range(Wc):
+                blk = f[tc * st:(tc + 1) * st, yc * sy:(yc + 1) * sy, xc * sy:(xc + 1) * sy]
+                out[tc, yc, xc] = blk.sum() / blk.size
+    return out
+
+
+def _linear_axis(n_fine: int, s: int, n_coarse: int):
+    """Cell-centred coordinate c = (i + 1/2) / s - 1/2 clamped to [0, n - 1]:
+    lower index, upper index and weight of the upper one, per fine index."""
+    i0 = np.empty(n_fine, dtype=np.int64)
+    i1 = np.empty(n_fine, dtype=np.int64)
+    w = np.empty(n_fine)
+    for i in range(n_fine):
+        c = min(max((i + 0.5) / s - 0.5, 0.0), n_coarse - 1.0)
+        i0[i] = int(math.floor(c))
+        i1[i] = min(i0[i] + 1, n_coarse - 1)
+        w[i] = c - i0[i]
+    return i0, i1, w
+
+
+def upsample(xc, shape, sy: int, st: int, mode: int = 1, mul=None) -> np.ndarray:
+    """Fine volume of the given shape from the coarse one: mode 0 takes the
+    coarse cell holding each voxel, mode 1 interpolates trilinearly between
+    cell centres (clamped at the edges). Multiplied by mul if given."""
+    xc = _f64(xc)
+    T, H, W = shape
+    Tc, Hc, Wc = xc.shape
+    if mode == 0:
+        out = np.empty(shape)
+        for t in range(T):
+            for y in range(H):
+                out[t, y, :] = xc[t // st, y // sy, np.arange(W) // sy]
+    else:
+        at0, at1, wt = _linear_axis(T, st, Tc)
+        ay0, ay1, wy = _linear_axis(H, sy, Hc)
+        ax0, ax1, wx = _linear_axis(W, sy, Wc)
+        out = np.zeros(shape)
+        for ti, tw in ((at0, 1.0 - wt), (at1, wt)):
+            for yi, yw in ((ay0, 1.0 - wy), (ay1, wy)):
+                for xi, xw in ((ax0, 1.0 - wx), (ax1, wx)):
+                    out += (tw[:, None, None] * yw[None, :, None] * xw[None, None, :]) * \
+                        xc[np.ix_(ti, yi, xi)]
+    if mul is not None:
+        out = out * _f64(mul)
+    return out
+
+
+def coarse_kernel(k: Kernel, sy: int, st: int) -> Kernel:
+    """The filter on the coarse grid: sigmas and radii in coarse units (radii
+    rounded up so the support covers the fine one)."""
+    return Kernel(k.sigma_s / sy, k.sigma_t / st, -(-k.r_s // sy), -(-k.r_t // st))

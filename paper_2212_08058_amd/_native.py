@@ -62,6 +62,8 @@ PROTOTYPES = [
     ("stpi_variant_count", ctypes.c_int, [ctypes.c_int]),
     ("stpi_variant_info", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
     ("stpi_launch_shape", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
+    ("stpi_downsample", ctypes.c_int, [ctypes.c_int] * 6 + [_vp, _vp, _vp]),
+    ("stpi_upsample", ctypes.c_int, [ctypes.c_int] * 7 + [_vp, _vp, _vp, _vp]),
     ("stpi_set_variant", ctypes.c_int, [ctypes.c_int]),
     ("stpi_time_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _sz, ctypes.c_int, ctypes.c_int, _vp,
                                       ctypes.POINTER(ctypes.c_double)]),

@@ -122,6 +122,37 @@ def power_iterate(f: torch.Tensor, k: Kernel, iters: int | None = None, tol: flo
     return x, out
 
 
+def coarse_shape(shape, sy: int, st: int):
+    T, H, W = (int(v) for v in shape)
+    return (-(-T // st), -(-H // sy), -(-W // sy))
+
+
+def downsample(x: torch.Tensor, sy: int, st: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Box average to the coarse grid (stpi_downsample)."""
+    _check_volume("x", x)
+    cs = coarse_shape(x.shape, sy, st)
+    out = torch.empty(cs, dtype=x.dtype, device=x.device) if out is None else out
+    _check_volume("out", out, cs, x.dtype)
+    T, H, W = x.shape
+    N.check(N.lib.stpi_downsample(T, H, W, int(sy), int(st), _dtype_code(x.dtype), x.data_ptr(), out.data_ptr(),
+                                  _stream_ptr(stream)))
+    return out
+
+
+def upsample(xc: torch.Tensor, shape, sy: int, st: int, mode: int = 1, mul: torch.Tensor | None = None,
+             out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Coarse volume back to `shape` (stpi_upsample), times mul if given."""
+    shape = tuple(int(v) for v in shape)
+    _check_volume("xc", xc, coarse_shape(shape, sy, st))
+    if mul is not None:
+        _check_volume("mul", mul, shape, xc.dtype)
+    out = torch.empty(shape, dtype=xc.dtype, device=xc.device) if out is None else out
+    _check_volume("out", out, shape, xc.dtype)
+    N.check(N.lib.stpi_upsample(*shape, int(sy), int(st), int(mode), _dtype_code(xc.dtype), xc.data_ptr(),
+                                mul.data_ptr() if mul is not None else None, out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
 def launch_shape(shape, k: Kernel, dtype: torch.dtype = torch.float32, variant: int = -1) -> dict:
     """stpi_launch_shape: the variant, tiles, frame segments and workgroups a step uses."""
     p = problem_for(shape, k, dtype)

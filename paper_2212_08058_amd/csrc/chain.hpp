@@ -7,7 +7,7 @@
 
 namespace stpi {
 
-constexpr int CHAIN_THREADS = 256;
+constexpr int CHAIN_THREADS = FINAL_THREADS;
 constexpr int NORM_BLOCKS = 512;  // fixed grid for the sum-of-squares pass
 
 // Sums partials[2*i + k] over i in [0, n) for k = 0, 1 (one workgroup).

@@ -18,6 +18,7 @@ __global__ void state_init_kernel(DevState *s, double scale, double tol, int max
         s->flags = 0u;
         s->max_iters = max_iters;
         s->converged = 0;
+        s->arrive = 0u;
     }
 }
 
@@ -46,32 +47,7 @@ __global__ void finalize_kernel(const double *partials, int n, DevState *s) {
     if (s->done) return;
     double p1, p2;
     sum_pairs(partials, n, p1, p2);
-    if (threadIdx.x == 0) {
-        const double scale = s->scale;
-        const double nz = sqrt(p2);
-        if (!isfinite(nz) || !isfinite(p1)) {
-            s->flags |= FLAG_NONFINITE;
-            s->done = 1;
-            return;
-        }
-        if (nz == 0.0) {
-            s->flags |= FLAG_ZERO;
-            s->done = 1;
-            return;
-        }
-        const double c = scale * p1 / nz;
-        s->rayleigh = scale * p1;
-        s->lambda = nz;
-        s->residual = sqrt(fmax(0.0, 2.0 - 2.0 * c));
-        s->scale = 1.0 / nz;
-        s->cur ^= 1;
-        s->iters += 1;
-        if (s->tol > 0.0 && s->residual < s->tol) {
-            s->converged = 1;
-            s->done = 1;
-        }
-        if (s->iters >= s->max_iters) s->done = 1;
-    }
+    if (threadIdx.x == 0) step_finalize(s, p1, p2);
 }
 
 // Single-step mode: d_sums = (sum z^2, x_scale * sum z * x).

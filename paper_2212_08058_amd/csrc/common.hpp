@@ -56,10 +56,46 @@ struct DevState {
     uint32_t flags;    // bit 0 zero norm, bit 1 non-finite
     int32_t max_iters;
     int32_t converged;
+    uint32_t arrive;   // workgroups of the running step that stored their partial sums
 };
 
 constexpr uint32_t FLAG_ZERO = 1u;
 constexpr uint32_t FLAG_NONFINITE = 2u;
+
+// Workgroup size and summation order of the per-step reduction of partial
+// sums: thread i < FINAL_THREADS adds entries i, i + FINAL_THREADS, ... in
+// turn, then the workgroup tree of block_sum.
+constexpr int FINAL_THREADS = 256;
+
+// Step finalisation from the reduced sums P1 = sum z * x_stored and
+// P2 = sum z^2: n = ||z||, x_{k+1} = z / n (Eq. 8), cos = <x_{k+1}, x_k> =
+// scale * P1 / n, residual = sqrt(2 - 2 cos), and the stopping rules.
+__device__ __forceinline__ void step_finalize(DevState *s, double p1, double p2) {
+    const double scale = s->scale;
+    const double nz = sqrt(p2);
+    if (!isfinite(nz) || !isfinite(p1)) {
+        s->flags |= FLAG_NONFINITE;
+        s->done = 1;
+        return;
+    }
+    if (nz == 0.0) {
+        s->flags |= FLAG_ZERO;
+        s->done = 1;
+        return;
+    }
+    const double c = scale * p1 / nz;
+    s->rayleigh = scale * p1;
+    s->lambda = nz;
+    s->residual = sqrt(fmax(0.0, 2.0 - 2.0 * c));
+    s->scale = 1.0 / nz;
+    s->cur ^= 1;
+    s->iters += 1;
+    if (s->tol > 0.0 && s->residual < s->tol) {
+        s->converged = 1;
+        s->done = 1;
+    }
+    if (s->iters >= s->max_iters) s->done = 1;
+}
 
 // Sum of a double over a workgroup (fixed shuffle/LDS tree: deterministic).
 template <int NTHR>

@@ -17,6 +17,7 @@ struct FwdLaunch {
     double *partials;    // [tiles * nseg][2] doubles
     int T, H, W;
     int nseg;            // frame segments per tile (0 is read as 1)
+    int fuse;            // iterate mode: finalise the step in its last workgroup (if the variant can)
     double gs[2 * 16 + 1];
     double gt[2 * 8 + 1];
 };
@@ -34,8 +35,9 @@ struct FwdArgs {
     const ST *f;
     ST *buf0;
     ST *buf1;
-    const DevState *state;
+    DevState *state;
     double *partials;
+    int fuse;  // 1: the last workgroup to finish reduces the partials and finalises the step
     double x_scale;
     const double *norm_in;
     ST *vout;
@@ -228,9 +230,43 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
         stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1, d2);
     const double s1 = block_sum<NTHR>(d1, red);
     const double s2 = block_sum<NTHR>(d2, red);
+    __shared__ int s_last;
     if (threadIdx.x == 0) {
-        a.partials[2 * unit] = s1;
-        a.partials[2 * unit + 1] = s2;
+        if (a.fuse) {
+            // Publish the two sums device-wide: agent-scope stores write through
+            // the XCD's L2, the wait makes sure they are done before this
+            // workgroup is counted in. Only these values cross workgroups, so no
+            // full L2 write-back is needed (the kernel boundary orders the rest).
+            __hip_atomic_store(&a.partials[2 * unit], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.partials[2 * unit + 1], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+            s_last = __hip_atomic_fetch_add(&a.state->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                     (unsigned)(nbx * nby * a.nseg - 1);
+        } else {
+            a.partials[2 * unit] = s1;
+            a.partials[2 * unit + 1] = s2;
+        }
+    }
+    if constexpr (NTHR >= FINAL_THREADS) {
+        if (!a.fuse) return;
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(s_last)) return;
+        // last workgroup: the step finalisation, summed in the order of the
+        // separate finalisation kernel (threads >= FINAL_THREADS add zeros);
+        // agent-scope loads read the published sums past the local L2
+        const int n = nbx * nby * a.nseg;
+        double p1 = 0.0, p2 = 0.0;
+        if (threadIdx.x < FINAL_THREADS)
+            for (int i = threadIdx.x; i < n; i += FINAL_THREADS) {
+                p1 += __hip_atomic_load(&a.partials[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                p2 += __hip_atomic_load(&a.partials[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        p1 = block_sum<NTHR>(p1, red);
+        p2 = block_sum<NTHR>(p2, red);
+        if (threadIdx.x == 0) {
+            step_finalize(a.state, p1, p2);
+            a.state->arrive = 0u;
+        }
     }
 }
 
@@ -243,6 +279,7 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     a.buf1 = (ST *)L.buf1;
     a.state = L.state;
     a.partials = L.partials;
+    a.fuse = L.state && L.fuse && NTHR >= FINAL_THREADS ? 1 : 0;
     a.x_scale = L.x_scale;
     a.norm_in = L.norm_in;
     a.vout = (ST *)L.vout;
@@ -261,6 +298,11 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     hipLaunchKernelGGL((fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>), dim3(per * NUM_XCD), dim3(NTHR), 0,
                        stream, a);
     return hipGetLastError();
+}
+
+template <int NTHR>
+constexpr bool fwd_can_fuse() {
+    return NTHR >= FINAL_THREADS;
 }
 
 template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>

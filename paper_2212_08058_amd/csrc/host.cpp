@@ -183,9 +183,10 @@ struct GraphKey {
     double tol;
     const Variant *v;
     hipStream_t s;
+    int part;  // ChainPart
     bool operator==(const GraphKey &o) const {
         return std::memcmp(&p, &o.p, sizeof(p)) == 0 && f == o.f && x == o.x && ws == o.ws && init == o.init &&
-               max_iters == o.max_iters && tol == o.tol && v == o.v && s == o.s;
+               max_iters == o.max_iters && tol == o.tol && v == o.v && s == o.s && part == o.part;
     }
 };
 struct GraphEntry {
@@ -198,6 +199,12 @@ static std::vector<GraphEntry> g_graphs;
 static unsigned long long g_graph_clock = 0;
 constexpr size_t GRAPH_CACHE_MAX = 16;
 
+// STPI_NO_FUSE=1 keeps the step finalisation in its own kernel (for comparison).
+static bool fusion_disabled() {
+    const char *e = std::getenv("STPI_NO_FUSE");
+    return e && e[0] == '1';
+}
+
 static bool graphs_enabled() {
     const char *e = std::getenv("STPI_NO_GRAPH");
     return !(e && e[0] == '1');
@@ -205,6 +212,94 @@ static bool graphs_enabled() {
 
 int forced_variant() { return g_forced_variant; }
 void set_forced_variant(int v) { g_forced_variant = v; }
+
+enum ChainPart { CHAIN_ALL = 0, CHAIN_HEAD = 1, CHAIN_CHUNK_PART = 2, CHAIN_TAIL = 3 };
+
+struct ChainArgs {
+    const stpi_problem *p;
+    const DtypeOps *ops;
+    const Variant *v;
+    const void *f;
+    void *x, *buf1;
+    DevState *state;
+    double *partials;
+    int init, max_iters;
+    double tol;
+};
+
+int enqueue_chain_part(const ChainArgs &a, int part, hipStream_t s) {
+    switch (part) {
+        case CHAIN_ALL:
+            return enqueue_iteration(a.p, a.ops, a.v, a.f, a.x, a.buf1, a.state, a.partials, a.init, a.max_iters,
+                                     a.tol, s);
+        case CHAIN_HEAD: {
+            const int rc = enqueue_chain_init(a.p, a.ops, a.x, a.state, a.partials, a.init, a.max_iters, a.tol, s);
+            return rc ? rc : enqueue_chain_steps(a.p, a.v, a.f, a.x, a.buf1, a.state, a.partials, CHAIN_CHUNK, s);
+        }
+        case CHAIN_CHUNK_PART:
+            return enqueue_chain_steps(a.p, a.v, a.f, a.x, a.buf1, a.state, a.partials, CHAIN_CHUNK, s);
+        default: {
+            const hipError_t e = a.ops->normalize(a.x, a.buf1, (size_t)a.p->T * a.p->H * a.p->W, a.state, s);
+            return e == hipSuccess ? STPI_OK : hip_fail(e, "normalize");
+        }
+    }
+}
+
+// Launches the cached graph for key, capturing `enqueue` into a new one on a miss.
+template <class F>
+int launch_cached_graph(const GraphKey &key, F &&enqueue, hipStream_t s) {
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (auto &g : g_graphs)
+            if (g.key == key) {
+                exec = g.exec;
+                g.last_use = ++g_graph_clock;
+                break;
+            }
+    }
+    hipError_t e;
+    if (!exec) {
+        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "begin capture");
+        const int rc = enqueue();
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(s, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        if (g_graphs.size() >= GRAPH_CACHE_MAX) {
+            size_t old = 0;
+            for (size_t i = 1; i < g_graphs.size(); ++i)
+                if (g_graphs[i].last_use < g_graphs[old].last_use) old = i;
+            (void)hipGraphExecDestroy(g_graphs[old].exec);
+            g_graphs.erase(g_graphs.begin() + old);
+        }
+        g_graphs.push_back(GraphEntry{key, exec, ++g_graph_clock});
+    }
+    if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+    return STPI_OK;
+}
+
+// Host-visible copy of the iteration state for the stop-flag poll (pinned,
+// one per thread, kept for the life of the process), and its event.
+DevState *pinned_state() {
+    thread_local DevState *buf = nullptr;
+    if (!buf && hipHostMalloc((void **)&buf, sizeof(DevState), hipHostMallocDefault) != hipSuccess) buf = nullptr;
+    return buf;
+}
+
+hipEvent_t poll_event() {
+    thread_local hipEvent_t ev = nullptr;
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+    return ev;
+}
 
 }  // namespace stpi
 
@@ -289,7 +384,16 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
     double *partials = (double *)((char *)ws + L.partials_off);
     void *buf1 = (char *)ws + L.buf_off;
 
-    if (s != nullptr && graphs_enabled()) {
+    // A run in tolerance mode stops early, but a chain of max_iters steps
+    // would still launch every (step, finalise) pair (they exit at once when
+    // done, at a launch latency each). Long tolerance runs therefore replay a
+    // chain of CHAIN_CHUNK steps, the host checking the stop flag one chunk
+    // behind so the device never waits for it.
+    const bool chunked = tol > 0.0 && max_iters > 2 * CHAIN_CHUNK;
+    ChainArgs ca{p, ops, v, f, x, buf1, state, partials, init, max_iters, tol};
+    const bool use_graphs = s != nullptr && graphs_enabled();
+    auto run = [&](int part) -> int {
+        if (!use_graphs) return enqueue_chain_part(ca, part, s);
         GraphKey key;
         std::memset(&key, 0, sizeof(key));
         key.p = *p;
@@ -301,45 +405,27 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
         key.tol = tol;
         key.v = v;
         key.s = s;
-        hipGraphExec_t exec = nullptr;
-        {
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            for (auto &g : g_graphs)
-                if (g.key == key) {
-                    exec = g.exec;
-                    g.last_use = ++g_graph_clock;
-                    break;
-                }
-        }
-        hipError_t e;
-        if (!exec) {
-            if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-                return hip_fail(e, "begin capture");
-            rc = enqueue_iteration(p, ops, v, f, x, buf1, state, partials, init, max_iters, tol, s);
-            hipGraph_t graph = nullptr;
-            e = hipStreamEndCapture(s, &graph);
-            if (rc) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return rc;
-            }
-            if (e != hipSuccess) return hip_fail(e, "end capture");
-            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            if (g_graphs.size() >= GRAPH_CACHE_MAX) {
-                size_t old = 0;
-                for (size_t i = 1; i < g_graphs.size(); ++i)
-                    if (g_graphs[i].last_use < g_graphs[old].last_use) old = i;
-                (void)hipGraphExecDestroy(g_graphs[old].exec);
-                g_graphs.erase(g_graphs.begin() + old);
-            }
-            g_graphs.push_back(GraphEntry{key, exec, ++g_graph_clock});
-        }
-        if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+        key.part = part;
+        return launch_cached_graph(key, [&] { return enqueue_chain_part(ca, part, s); }, s);
+    };
+    if (!chunked) {
+        if ((rc = run(CHAIN_ALL))) return rc;
     } else {
-        rc = enqueue_iteration(p, ops, v, f, x, buf1, state, partials, init, max_iters, tol, s);
-        if (rc) return rc;
+        if ((rc = run(CHAIN_HEAD))) return rc;
+        DevState *poll = pinned_state();
+        hipEvent_t ev = poll_event();
+        if (!poll || !ev) return fail(STPI_EHIP, "pinned poll buffer or event unavailable");
+        hipError_t e;
+        for (int issued = CHAIN_CHUNK; issued < max_iters; issued += CHAIN_CHUNK) {
+            // state after the chunks issued so far, then one more chunk while it travels
+            if ((e = hipMemcpyAsync(poll, state, sizeof(DevState), hipMemcpyDeviceToHost, s)) != hipSuccess)
+                return hip_fail(e, "state poll");
+            if ((e = hipEventRecord(ev, s)) != hipSuccess) return hip_fail(e, "poll event");
+            if ((rc = run(CHAIN_CHUNK_PART))) return rc;
+            if ((e = hipEventSynchronize(ev)) != hipSuccess) return hip_fail(e, "poll wait");
+            if (poll->done) break;
+        }
+        if ((rc = run(CHAIN_TAIL))) return rc;
     }
 
     DevState hs;
@@ -459,9 +545,8 @@ namespace stpi {
 
 // Enqueues start vector, max_iters (step, finalise) pairs and the final
 // normalisation. No host synchronisation.
-int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
-                      void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,
-                      hipStream_t s) {
+int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevState *state, double *partials,
+                       int init, int max_iters, double tol, hipStream_t s) {
     const size_t N = (size_t)p->T * p->H * p->W;
     hipError_t e;
     if (init == 1) {
@@ -475,6 +560,12 @@ int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant 
             return hip_fail(e, "init norm");
     }
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init");
+    return STPI_OK;
+}
+
+int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, void *x, void *buf1, DevState *state,
+                        double *partials, int steps, hipStream_t s) {
+    hipError_t e;
     FwdLaunch FL;
     std::memset(&FL, 0, sizeof(FL));
     FL.f = f;
@@ -488,12 +579,25 @@ int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant 
     FL.nseg = segments_for(*v, p);
     make_taps(p, FL.gs, FL.gt);
     const int nb = grid_blocks(*v, p);
-    for (int k = 0; k < max_iters; ++k) {
+    // workgroups of FINAL_THREADS or more finalise the step themselves (the
+    // last one to finish), saving a launch per step
+    FL.fuse = v->NTHR >= FINAL_THREADS && !fusion_disabled() ? 1 : 0;
+    for (int k = 0; k < steps; ++k) {
         if ((e = v->launch(FL, s)) != hipSuccess) return hip_fail(e, "step kernel launch");
-        if ((e = launch_finalize(partials, nb, state, s)) != hipSuccess) return hip_fail(e, "finalize launch");
+        if (!FL.fuse && (e = launch_finalize(partials, nb, state, s)) != hipSuccess)
+            return hip_fail(e, "finalize launch");
     }
-    if ((e = ops->normalize(x, buf1, N, state, s)) != hipSuccess) return hip_fail(e, "normalize");
     return STPI_OK;
+}
+
+int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
+                      void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,
+                      hipStream_t s) {
+    int rc = enqueue_chain_init(p, ops, x, state, partials, init, max_iters, tol, s);
+    if (!rc) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, max_iters, s);
+    if (rc) return rc;
+    const hipError_t e = ops->normalize(x, buf1, (size_t)p->T * p->H * p->W, state, s);
+    return e == hipSuccess ? STPI_OK : hip_fail(e, "normalize");
 }
 
 }  // namespace stpi

@@ -26,8 +26,11 @@ struct stpi_plan {
         int init, max_iters;
         double tol;
         hipStream_t s;
+        int part;
         hipGraphExec_t exec;
     };
+    stpi::BatchCtl *poll = nullptr;  // pinned copy of the chain counters (stop-flag poll)
+    hipEvent_t poll_ev = nullptr;
     std::vector<G> graphs;
 };
 
@@ -83,8 +86,9 @@ static const BatchVariant *choose_batch_variant(const stpi_problem *proto, const
     return best;
 }
 
+// part: 0 everything, 1 init + CHAIN_CHUNK steps, 2 CHAIN_CHUNK steps, 3 final normalisation
 static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int init, int max_iters, double tol,
-                         hipStream_t s) {
+                         hipStream_t s, int part = 0) {
     const DtypeOps *ops = ops_for(P->proto.dtype);
     char *w = (char *)ws;
     BatchCtl *ctl = (BatchCtl *)w;
@@ -92,15 +96,22 @@ static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int ini
     double *partials = (double *)(w + P->ws_partials_off);
     void *buf1 = w + P->ws_buf_off;
     hipError_t e;
-    if ((e = launch_batch_init(states, P->d_clips, P->nclips, tol, max_iters, init, ctl, s)) != hipSuccess)
-        return hip_fail(e, "batch init");
-    if (init == 1) {
-        if ((e = ops->batch_fill(x, P->d_clips, P->nclips, s)) != hipSuccess) return hip_fail(e, "batch fill");
-    } else {
-        if ((e = ops->batch_sumsq(x, P->d_clips, P->nclips, partials, s)) != hipSuccess)
-            return hip_fail(e, "batch norm");
-        if ((e = launch_batch_state_from_norm(partials, states, P->nclips, ctl, s)) != hipSuccess)
-            return hip_fail(e, "batch norm finalize");
+    if (part == 3) {
+        if ((e = ops->batch_normalize(x, buf1, P->d_clips, states, P->nclips, s)) != hipSuccess)
+            return hip_fail(e, "batch normalize");
+        return STPI_OK;
+    }
+    if (part <= 1) {
+        if ((e = launch_batch_init(states, P->d_clips, P->nclips, tol, max_iters, init, ctl, s)) != hipSuccess)
+            return hip_fail(e, "batch init");
+        if (init == 1) {
+            if ((e = ops->batch_fill(x, P->d_clips, P->nclips, s)) != hipSuccess) return hip_fail(e, "batch fill");
+        } else {
+            if ((e = ops->batch_sumsq(x, P->d_clips, P->nclips, partials, s)) != hipSuccess)
+                return hip_fail(e, "batch norm");
+            if ((e = launch_batch_state_from_norm(partials, states, P->nclips, ctl, s)) != hipSuccess)
+                return hip_fail(e, "batch norm finalize");
+        }
     }
     BatchLaunch BL;
     std::memset(&BL, 0, sizeof(BL));
@@ -116,12 +127,13 @@ static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int ini
     BL.nclips = P->nclips;
     BL.grid = P->grid;
     make_taps(&P->proto, BL.gs, BL.gt);
-    for (int k = 0; k < max_iters; ++k) {
+    const int steps = part == 0 ? max_iters : CHAIN_CHUNK;
+    for (int k = 0; k < steps; ++k) {
         if ((e = P->v->launch(BL, s)) != hipSuccess) return hip_fail(e, "batch step");
         if ((e = launch_batch_finalize(partials, P->d_clips, states, P->nclips, ctl, s)) != hipSuccess)
             return hip_fail(e, "batch finalize");
     }
-    if ((e = ops->batch_normalize(x, buf1, P->d_clips, states, P->nclips, s)) != hipSuccess)
+    if (part == 0 && (e = ops->batch_normalize(x, buf1, P->d_clips, states, P->nclips, s)) != hipSuccess)
         return hip_fail(e, "batch normalize");
     return STPI_OK;
 }
@@ -253,37 +265,59 @@ int stpi_batch_iterate(stpi_plan *plan, const void *f, void *x, int init, int ma
         return fail(STPI_EWORKSPACE, "batch workspace needs %zu bytes", plan->ws_total);
     hipStream_t s = (hipStream_t)stream;
     int rc;
-    if (s != nullptr) {
+    auto run = [&](int part) -> int {
+        if (s == nullptr) return enqueue_batch(plan, f, x, ws, init, max_iters, tol, s, part);
         hipGraphExec_t exec = nullptr;
         for (auto &g : plan->graphs)
             if (g.f == f && g.x == x && g.ws == ws && g.init == init && g.max_iters == max_iters && g.tol == tol &&
-                g.s == s)
+                g.s == s && g.part == part)
                 exec = g.exec;
         hipError_t e;
         if (!exec) {
             if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                 return hip_fail(e, "begin capture");
-            rc = enqueue_batch(plan, f, x, ws, init, max_iters, tol, s);
+            const int rc2 = enqueue_batch(plan, f, x, ws, init, max_iters, tol, s, part);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(s, &graph);
-            if (rc) {
+            if (rc2) {
                 if (graph) (void)hipGraphDestroy(graph);
-                return rc;
+                return rc2;
             }
             if (e != hipSuccess) return hip_fail(e, "end capture");
             e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-            if (plan->graphs.size() >= 8) {
+            if (plan->graphs.size() >= 16) {
                 (void)hipGraphExecDestroy(plan->graphs.front().exec);
                 plan->graphs.erase(plan->graphs.begin());
             }
-            plan->graphs.push_back({f, x, ws, init, max_iters, tol, s, exec});
+            plan->graphs.push_back({f, x, ws, init, max_iters, tol, s, part, exec});
         }
         if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+        return STPI_OK;
+    };
+    // Long tolerance runs replay CHAIN_CHUNK steps at a time and stop once
+    // every clip is done (checked one chunk behind, as stpi_iterate does).
+    if (!(tol > 0.0 && max_iters > 2 * CHAIN_CHUNK)) {
+        if ((rc = run(0))) return rc;
     } else {
-        rc = enqueue_batch(plan, f, x, ws, init, max_iters, tol, s);
-        if (rc) return rc;
+        hipError_t e;
+        if (!plan->poll && hipHostMalloc((void **)&plan->poll, sizeof(BatchCtl), hipHostMallocDefault) != hipSuccess) {
+            plan->poll = nullptr;
+            return fail(STPI_EHIP, "pinned poll buffer");
+        }
+        if (!plan->poll_ev && (e = hipEventCreateWithFlags(&plan->poll_ev, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "poll event");
+        if ((rc = run(1))) return rc;
+        for (int issued = CHAIN_CHUNK; issued < max_iters; issued += CHAIN_CHUNK) {
+            if ((e = hipMemcpyAsync(plan->poll, ws, sizeof(BatchCtl), hipMemcpyDeviceToHost, s)) != hipSuccess)
+                return hip_fail(e, "counter poll");
+            if ((e = hipEventRecord(plan->poll_ev, s)) != hipSuccess) return hip_fail(e, "poll event");
+            if ((rc = run(2))) return rc;
+            if ((e = hipEventSynchronize(plan->poll_ev)) != hipSuccess) return hip_fail(e, "poll wait");
+            if (plan->poll->done_clips >= (uint32_t)plan->nclips) break;
+        }
+        if ((rc = run(3))) return rc;
     }
     std::vector<DevState> hs(plan->nclips);
     hipError_t e = hipMemcpyAsync(hs.data(), (char *)ws + plan->ws_state_off, sizeof(DevState) * plan->nclips,
@@ -309,6 +343,8 @@ int stpi_batch_iterate(stpi_plan *plan, const void *f, void *x, int init, int ma
 void stpi_plan_destroy(stpi_plan *plan) {
     if (!plan) return;
     for (auto &g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (plan->poll) (void)hipHostFree(plan->poll);
+    if (plan->poll_ev) (void)hipEventDestroy(plan->poll_ev);
     if (plan->d_clips) (void)hipFree(plan->d_clips);
     if (plan->d_tiles) (void)hipFree(plan->d_tiles);
     delete plan;

@@ -30,6 +30,11 @@ int grid_blocks(const Variant &v, const stpi_problem *p);
 int segments_for(const Variant &v, const stpi_problem *p);
 constexpr int STPI_NSEG_MAX = 4;  // frame segments per tile at most
 WsLayout layout_for(const stpi_problem *p);
+constexpr int CHAIN_CHUNK = 16;  // steps per replayed chain segment in long tolerance runs
+int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevState *state, double *partials,
+                       int init, int max_iters, double tol, hipStream_t s);
+int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, void *x, void *buf1, DevState *state,
+                        double *partials, int steps, hipStream_t s);
 int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
                       void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,
                       hipStream_t s);

@@ -16,7 +16,8 @@ import synth
 from . import batch as B
 from . import learn
 from .api import Kernel, power_iterate
-from .warmstart import WarmStartNet, solve_plain, solve_warm
+from .api import workspace_bytes
+from .warmstart import TwoLevel, WarmStartNet, solve_plain, solve_two_level, solve_warm
 
 
 def _sync():
@@ -94,53 +95,148 @@ def channel_training_step(reps=5, device="cuda", log=print):
                 step_voxel_iters_per_s=N * 3 * c["iters"] / t)
 
 
+def _targets_batched(fs, kern, tol, cap, device, log):
+    """Plain eigenvectors of many clips of one shape in one batched plan."""
+    plan = B.BatchPlan([tuple(fs[0].shape)] * len(fs), kern)
+    f_flat = plan.pack(fs)
+    x_flat, res = plan.iterate(f_flat, max_iters=cap, tol=tol, check=False)
+    xs = [v.clone() for v in plan.views(x_flat)]
+    iters = [r["iters"] for r in res]
+    log(f"  targets: {len(fs)} clips, iterations median {int(np.median(iters))}, max {max(iters)}, "
+        f"unconverged {sum(not r['converged'] for r in res)}")
+    del f_flat, x_flat, plan
+    return xs, iters
+
+
 def warm_start_experiment(n_train=2000, n_eval=200, epochs=2, train_shape=(16, 240, 432), eval_shape=(32, 480, 854),
-                          tol=1e-4, target_tol=1e-6, cap=2000, lr=2e-3, device="cuda", log=print):
-    """Train the warm-start net on plain-method eigenvectors, then compare wall time to tol."""
+                          tol=1e-4, target_tol=1e-6, cap=2000, lr=2e-3, sy=4, st=2, coarse_tol=1e-3, chunk=250,
+                          batched=True, device="cuda", log=print):
+    """Warm starts against the plain method, wall time to tol per clip.
+
+    Trains two nets with the library's kernels: one on f (net_f) and one on
+    the two-level start (net_tl). Evaluates, clip by clip with preallocated
+    buffers: plain (uniform start), net_f, two-level, two-level + net_tl; and
+    batched: plain vs two-level + net_tl over all evaluation clips.
+    """
     c = synth.CONFIGS["warm"]
     kern = Kernel(c["sigma_s"], c["sigma_t"], c["r_s"], c["r_t"])
-    net = WarmStartNet(lr=lr, device=device)
     t_gen = time.perf_counter()
-    train = []
-    for i in range(n_train):
-        f, _ = synth.blob_clip(*train_shape, 3, c["train_seed"] + i)
-        fd = torch.from_numpy(f).to(device)
-        x, r = power_iterate(fd, kern, tol=target_tol, max_iters=20000, check=False)
-        train.append((fd, x.clone()))
+    fs, xs, tl_in = [], [], []
+    tl_train = TwoLevel(train_shape, kern, sy, st, tol=coarse_tol, device=device)
+    for c0 in range(0, n_train, chunk):
+        fc = [torch.from_numpy(synth.blob_clip(*train_shape, 3, c["train_seed"] + i)[0]).to(device)
+              for i in range(c0, min(n_train, c0 + chunk))]
+        xc, _ = _targets_batched(fc, kern, target_tol, 20000, device, log)
+        for f in fc:
+            tl_in.append(tl_train.net_input(tl_train.start(f)).clone())
+        fs += fc
+        xs += xc
     _sync()
-    log(f"warm start: {n_train} training targets in {time.perf_counter() - t_gen:.1f} s")
+    gen_s = time.perf_counter() - t_gen
+    log(f"warm start: {n_train} training clips (targets + two-level inputs) in {gen_s:.1f} s")
+    nets = {"net_f": WarmStartNet(lr=lr, device=device), "net_tl": WarmStartNet(lr=lr, device=device)}
+    hist = {k: [] for k in nets}
     rng = np.random.default_rng(0)
-    hist = []
     t_train = time.perf_counter()
     for ep in range(epochs):
-        tot = torch.zeros((), dtype=torch.float64, device=device)
+        tot = {k: torch.zeros((), dtype=torch.float64, device=device) for k in nets}
         for i in rng.permutation(n_train):
-            tot += net.train_step(*train[i])
-        hist.append(float(tot) / n_train)
-        log(f"  epoch {ep}: mean loss {hist[-1]:.4f}")
+            tot["net_f"] += nets["net_f"].train_step(fs[i], xs[i])
+            tot["net_tl"] += nets["net_tl"].train_step(tl_in[i], xs[i])
+        for k in nets:
+            hist[k].append(float(tot[k]) / n_train)
+        log(f"  epoch {ep}: mean loss net_f {hist['net_f'][-1]:.4f} net_tl {hist['net_tl'][-1]:.4f}")
     _sync()
     train_s = time.perf_counter() - t_train
-    del train
-    ws = None
-    plain_t, warm_t, rows = [], [], []
-    for i in range(n_eval):
-        f, _ = synth.blob_clip(*eval_shape, 3, c["eval_seed"] + i)
-        fd = torch.from_numpy(f).to(device)
-        if i == 0:  # warm-up (graph capture, allocations)
-            solve_plain(fd, kern, tol=tol, cap=cap)
-            solve_warm(net, fd, kern, tol=tol, cap=cap)
-        xp, rp, tp = solve_plain(fd, kern, tol=tol, cap=cap)
-        xw, iw, tw = solve_warm(net, fd, kern, tol=tol, cap=cap)
-        x0 = net.x0(fd)
-        cosd = 1.0 - float(torch.sum(x0.double() * xp.double()) / torch.linalg.vector_norm(x0.double()))
-        plain_t.append(tp)
-        warm_t.append(tw)
-        rows.append(dict(plain_iters=rp["iters"], warm_iters=iw["iters"], fallback=iw["fallback"],
-                         plain_s=tp, warm_s=tw, x0_cos_dist=cosd,
-                         agree_cos_dist=1.0 - float(torch.sum(xp.double() * xw.double()))))
-    ratios = [p / w for p, w in zip(plain_t, warm_t)]
-    return dict(n_train=n_train, n_eval=n_eval, epochs=epochs, train_shape=train_shape, eval_shape=eval_shape,
-                loss_history=hist, train_seconds=train_s, sum_ratio=sum(plain_t) / sum(warm_t),
-                median_ratio=float(np.median(ratios)), fallbacks=sum(r["fallback"] for r in rows),
-                plain_iters=[r["plain_iters"] for r in rows], warm_iters=[r["warm_iters"] for r in rows],
-                rows=rows)
+    del fs, xs, tl_in
+
+    # clip-by-clip evaluation, one set of buffers (captured graphs are reused)
+    fbuf = torch.empty(eval_shape, dtype=torch.float32, device=device)
+    xbuf = torch.empty_like(fbuf)
+    ws = torch.empty(workspace_bytes(eval_shape, kern), dtype=torch.uint8, device=device)
+    tl = TwoLevel(eval_shape, kern, sy, st, tol=coarse_tol, device=device)
+    modes = ("plain", "net_f", "two_level", "two_level_net")
+    times = {m: [] for m in modes}
+    iters = {m: [] for m in modes}
+    falls = {m: 0 for m in modes}
+    coarse_it, cosd = [], {m: [] for m in modes}
+    eval_fs = []
+    for i in range(-1, n_eval):
+        f, _ = synth.blob_clip(*eval_shape, 3, c["eval_seed"] + max(i, 0))
+        fbuf.copy_(torch.from_numpy(f))
+        if i >= 0:
+            eval_fs.append(fbuf.clone())
+        xp, rp, tp = solve_plain(fbuf, kern, tol=tol, cap=cap, x=xbuf, ws=ws)
+        xref = xp.double().clone()
+        runs = {"plain": (rp["iters"], tp, False)}
+        _, info, t = solve_warm(nets["net_f"], fbuf, kern, tol=tol, cap=cap, x=xbuf, ws=ws)
+        runs["net_f"] = (info["iters"], t, info["fallback"])
+        cosd["net_f"].append(1.0 - float(torch.sum(xbuf.double() * xref)))
+        _, info, t = solve_two_level(tl, fbuf, kern, tol=tol, cap=cap, x=xbuf, ws=ws)
+        runs["two_level"] = (info["iters"], t, info["fallback"])
+        cosd["two_level"].append(1.0 - float(torch.sum(xbuf.double() * xref)))
+        ci = info["coarse_iters"]
+        _, info, t = solve_two_level(tl, fbuf, kern, net=nets["net_tl"], tol=tol, cap=cap, x=xbuf, ws=ws)
+        runs["two_level_net"] = (info["iters"], t, info["fallback"])
+        cosd["two_level_net"].append(1.0 - float(torch.sum(xbuf.double() * xref)))
+        if i < 0:
+            continue  # first pass: graph capture and allocations
+        coarse_it.append(ci)
+        for m, (it, t, fb) in runs.items():
+            iters[m].append(it)
+            times[m].append(t)
+            falls[m] += int(fb)
+    out = dict(n_train=n_train, n_eval=n_eval, epochs=epochs, train_shape=train_shape, eval_shape=eval_shape,
+               coarse=dict(sy=sy, st=st, shape=tl.cshape, kernel=vars(tl.kc), iters_median=float(np.median(coarse_it))),
+               gen_seconds=gen_s, train_seconds=train_s, loss_history=hist, tol=tol, cap=cap)
+    for m in modes:
+        out[m] = dict(seconds=sum(times[m]), iters_median=float(np.median(iters[m])), iters_max=int(max(iters[m])),
+                      fallbacks=falls[m])
+        if m != "plain":
+            out[m]["sum_ratio"] = sum(times["plain"]) / sum(times[m])
+            out[m]["median_ratio"] = float(np.median([p / w for p, w in zip(times["plain"], times[m])]))
+            out[m]["cos_dist_max"] = float(max(cosd[m]))
+    out["iters"] = {m: iters[m] for m in modes}
+    out["ms"] = {m: [round(t * 1e3, 3) for t in times[m]] for m in modes}
+    out["coarse"]["tol"] = coarse_tol
+
+    if batched:
+        # batched: plain (uniform) vs two-level + net_tl starts, all evaluation clips in one plan
+        plan = B.BatchPlan([eval_shape] * n_eval, kern)
+        f_flat = plan.pack(eval_fs)
+        x_flat = plan.empty(device)
+        bws = plan.workspace(device)
+        s = torch.cuda.Stream()
+        plan.iterate(f_flat, x_flat, max_iters=cap, tol=tol, ws=bws, stream=s, check=False)  # capture
+        _sync()
+        t0 = time.perf_counter()
+        _, res_p = plan.iterate(f_flat, x_flat, max_iters=cap, tol=tol, ws=bws, stream=s, check=False)
+        _sync()
+        t_bp = time.perf_counter() - t0
+        for rep in range(2):  # first repetition captures the graphs
+            _sync()
+            t0 = time.perf_counter()
+            with torch.cuda.stream(s):
+                for f, xv in zip(eval_fs, plan.views(x_flat)):
+                    u0 = tl.start(f, s)
+                    xv.copy_(nets["net_tl"].x0(tl.net_input(u0)))
+            # fallback rule per clip: two single steps, restart from uniform where r2 > r1
+            _, r1 = plan.iterate(f_flat, x_flat, init=0, max_iters=1, tol=0.0, ws=bws, stream=s, check=False)
+            _, r2 = plan.iterate(f_flat, x_flat, init=0, max_iters=1, tol=0.0, ws=bws, stream=s, check=False)
+            nfb = 0
+            with torch.cuda.stream(s):
+                for a, b, xv in zip(r1, r2, plan.views(x_flat)):
+                    if not (b["residual"] <= a["residual"]):
+                        xv.fill_(1.0)
+                        nfb += 1
+            _, res_w = plan.iterate(f_flat, x_flat, init=0, max_iters=cap - 2, tol=tol, ws=bws, stream=s,
+                                    check=False)
+            _sync()
+            t_bw = time.perf_counter() - t0
+        out["batched"] = dict(plain_seconds=t_bp, warm_seconds=t_bw, ratio_vs_batched_plain=t_bp / t_bw,
+                              ratio_vs_single_plain=sum(times["plain"]) / t_bw, fallbacks=nfb,
+                              plain_iters_median=float(np.median([r["iters"] for r in res_p])),
+                              warm_iters_median=float(np.median([r["iters"] for r in res_w])) + 2,
+                              unconverged_plain=sum(not r["converged"] for r in res_p),
+                              unconverged_warm=sum(not r["converged"] for r in res_w))
+    return out

@@ -1,11 +1,22 @@
-"""Learned warm start: a 4-layer 3x3x3 conv net predicts the start vector.
+"""Warm starts: a two-level (coarse-grid) start and a learned 3x3x3 conv net.
 
-Training targets are eigenvectors computed by the plain method (uniform start,
-tight tolerance). The net is trained with the library's own forward/backward
-kernels and AdamW; at inference its output gives x0 = max(y, 0) + eps. The
-plain uniform-start iteration stays the fallback: if, from the warm start, the
-residual of the second step exceeds that of the first (r2 > r1), the run
-restarts from the uniform vector (the two wasted steps count in its time).
+Two-level start: f is box-averaged to a coarse grid (sy x sy pixels, st
+frames per cell), the power iteration runs there with the filter in coarse
+units, and its eigenvector, prolongated back and multiplied by f, starts the
+full-resolution iteration. On clips with several objects the slowest modes of
+the iteration are the competition between objects far apart; the coarse
+iteration settles them at a fraction of the cost.
+
+Learned start: a 4-layer 3x3x3 conv net maps its input volume to the start
+vector, trained on eigenvectors of the plain method (uniform start, tight
+tolerance) with the library's forward/backward kernels and AdamW; its output
+gives x0 = max(y, 0) + eps. Its input is either f, or the two-level start
+(scaled to O(1)), which the net then refines locally.
+
+The plain uniform-start iteration stays the fallback of every warm start: if,
+from the warm start, the residual of the second step exceeds that of the
+first (r2 > r1), the run restarts from the uniform vector (the wasted steps
+count in its time).
 """
 from __future__ import annotations
 
@@ -17,7 +28,8 @@ import numpy as np
 import torch
 
 from . import _native as N
-from .api import Kernel, _stream_ptr, power_iterate, problem_for, workspace_bytes
+from .api import (Kernel, _stream_ptr, coarse_shape, downsample, power_iterate, problem_for, upsample,
+                  workspace_bytes)
 from .learn import AdamW
 
 CHANNELS = (1, 16, 16, 16, 1)
@@ -108,29 +120,47 @@ class WarmStartNet:
         return x0
 
 
-def solve_plain(f, kern, tol=1e-4, cap=2000, ws=None, stream=None):
-    """Uniform start to tolerance; returns (x, result, seconds)."""
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    x, r = power_iterate(f, kern, tol=tol, max_iters=cap, ws=ws, stream=stream, check=False)
-    torch.cuda.synchronize()
-    return x, r, time.perf_counter() - t0
+class TwoLevel:
+    """Coarse-grid start for clips of one shape (buffers kept for graph reuse)."""
+
+    def __init__(self, shape, kern: Kernel, sy: int = 4, st: int = 2, mode: int = 1, tol: float = 1e-4,
+                 cap: int = 2000, device="cuda"):
+        self.shape = tuple(int(v) for v in shape)
+        self.sy, self.st, self.mode, self.tol, self.cap = int(sy), int(st), int(mode), float(tol), int(cap)
+        self.cshape = coarse_shape(self.shape, sy, st)
+        self.kc = Kernel(kern.sigma_s / sy, kern.sigma_t / st, -(-kern.r_s // sy), -(-kern.r_t // st))
+        self.fc = torch.empty(self.cshape, dtype=torch.float32, device=device)
+        self.xc = torch.empty_like(self.fc)
+        self.wsc = torch.empty(workspace_bytes(self.cshape, self.kc), dtype=torch.uint8, device=device)
+        self.u0 = torch.empty(self.shape, dtype=torch.float32, device=device)
+        self.last = None
+
+    def start(self, f: torch.Tensor, stream=None) -> torch.Tensor:
+        """u0 = f * up(x_coarse) (not normalised; iterate normalises it)."""
+        downsample(f, self.sy, self.st, out=self.fc, stream=stream)
+        _, r = power_iterate(self.fc, self.kc, tol=self.tol, max_iters=self.cap, x=self.xc, ws=self.wsc,
+                             stream=stream, check=False)
+        self.last = r
+        return upsample(self.xc, self.shape, self.sy, self.st, self.mode, mul=f, out=self.u0, stream=stream)
+
+    def net_input(self, u0: torch.Tensor) -> torch.Tensor:
+        """The start scaled to O(1) for the net: u0 * sqrt(coarse voxels)."""
+        return u0 * math.sqrt(self.fc.numel())
 
 
-def solve_warm(net: WarmStartNet, f, kern, tol=1e-4, cap=2000, ws=None, stream=None):
-    """Net start, fallback to uniform when the second residual exceeds the first.
+def solve_from(x0: torch.Tensor, f, kern, tol=1e-4, cap=2000, x=None, ws=None, stream=None):
+    """Iterate from x0 with the fallback rule; x0 is copied into x (or used as x).
 
-    Returns (x, info dict, seconds); info has iters (all applications,
-    including the fallback's wasted ones), fallback flag, r1, r2.
+    Returns (x, info dict); info has iters (all applications, including the
+    fallback's wasted ones), fallback flag, r1, r2, converged, residual.
     """
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    x = net.x0(f)
+    if x is None:
+        x = x0
+    elif x.data_ptr() != x0.data_ptr():
+        x.copy_(x0)
     _, r1 = power_iterate(f, kern, iters=1, x0=x, x=x, ws=ws, stream=stream, check=False)
     if r1["residual"] < tol:
-        torch.cuda.synchronize()
-        return x, dict(iters=1, fallback=False, r1=r1["residual"], r2=None, converged=True,
-                       residual=r1["residual"]), time.perf_counter() - t0
+        return x, dict(iters=1, fallback=False, r1=r1["residual"], r2=None, converged=True, residual=r1["residual"])
     _, r2 = power_iterate(f, kern, iters=1, x0=x, x=x, ws=ws, stream=stream, check=False)
     info = dict(r1=r1["residual"], r2=r2["residual"], fallback=False)
     if not (r2["residual"] <= r1["residual"]):
@@ -142,5 +172,37 @@ def solve_warm(net: WarmStartNet, f, kern, tol=1e-4, cap=2000, ws=None, stream=N
     else:
         x, r = power_iterate(f, kern, tol=tol, max_iters=cap - 2, x0=x, x=x, ws=ws, stream=stream, check=False)
         info.update(iters=2 + r["iters"], converged=r["converged"], residual=r["residual"])
+    return x, info
+
+
+def solve_plain(f, kern, tol=1e-4, cap=2000, x=None, ws=None, stream=None):
+    """Uniform start to tolerance; returns (x, result, seconds)."""
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, r = power_iterate(f, kern, tol=tol, max_iters=cap, x=x, ws=ws, stream=stream, check=False)
+    torch.cuda.synchronize()
+    return x, r, time.perf_counter() - t0
+
+
+def solve_warm(net: WarmStartNet, f, kern, tol=1e-4, cap=2000, x=None, ws=None, stream=None):
+    """Net start from f, with the fallback; returns (x, info, seconds)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = solve_from(net.x0(f), f, kern, tol, cap, x, ws, stream)
+    torch.cuda.synchronize()
+    return x, info, time.perf_counter() - t0
+
+
+def solve_two_level(tl: TwoLevel, f, kern, net: WarmStartNet | None = None, tol=1e-4, cap=2000, x=None, ws=None,
+                    stream=None):
+    """Two-level start (refined by the net if given), with the fallback.
+
+    Returns (x, info, seconds); info adds the coarse iteration count."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u0 = tl.start(f, stream)
+    x0 = net.x0(tl.net_input(u0)) if net is not None else u0
+    x, info = solve_from(x0, f, kern, tol, cap, x, ws, stream)
+    torch.cuda.synchronize()
+    info["coarse_iters"] = tl.last["iters"]
     return x, info, time.perf_counter() - t0

@@ -339,3 +339,60 @@ def test_frame_segments_match_oracle(P):
     finally:
         N.lib.stpi_set_variant(-1)
     assert seen_split, "no compiled variant split the frames at this shape"
+
+
+def test_long_tolerance_runs_stop_in_chunks(P):
+    """A tolerance run with a large cap replays short chain segments and stops
+    once converged: it must end exactly where a fixed-count run of the same
+    number of steps ends (bitwise), on the captured-graph and the direct path,
+    and the same holds for the batched chain."""
+    from paper_2212_08058_amd import batch as B
+    f, _ = synth.blob_clip(12, 60, 100, 3, 7)
+    kern = P.Kernel(4.0, 1.5, 8, 3)
+    fd = to_dev(f, torch.float32)
+    s = torch.cuda.Stream()
+    for stream in (s, None):
+        x_tol, r_tol = P.power_iterate(fd, kern, tol=1e-6, max_iters=5000, stream=stream)
+        torch.cuda.synchronize()
+        assert r_tol["converged"] and 48 < r_tol["iters"] < 5000, r_tol  # several 16-step segments
+        x_fix, r_fix = P.power_iterate(fd, kern, iters=r_tol["iters"], stream=stream)
+        torch.cuda.synchronize()
+        assert torch.equal(x_tol, x_fix) and r_tol["residual"] == r_fix["residual"]
+    shapes = [(12, 60, 100), (9, 40, 70)]
+    fs = [f, synth.blob_clip(9, 40, 70, 2, 8)[0]]
+    plan = B.BatchPlan(shapes, kern)
+    f_flat = plan.pack([to_dev(v, torch.float32) for v in fs])
+    x_flat, res = plan.iterate(f_flat, max_iters=5000, tol=1e-4, stream=s)
+    torch.cuda.synchronize()
+    for v, xv, r in zip(fs, plan.views(x_flat), res):
+        assert r["converged"] and r["iters"] < 5000
+        xs, rs = P.power_iterate(to_dev(v, torch.float32), kern, tol=1e-4, max_iters=5000)
+        cosd = 1.0 - float(torch.sum(xs.double() * xv.double()))
+        assert abs(r["iters"] - rs["iters"]) <= 1 and cosd < 1e-6
+
+
+def test_fused_finalisation_is_bitwise_equal(P, monkeypatch):
+    """The last workgroup's in-kernel step finalisation sums the partials in
+    the separate finalisation kernel's order: every variant gives bitwise the
+    same iterate and results either way (direct launches, so nothing cached)."""
+    from paper_2212_08058_amd import _native as N
+    import ctypes
+    f, _ = synth.blob_clip(20, 64, 240, 3, 9)
+    fd = to_dev(f, torch.float32)
+    try:
+        for i in range(N.lib.stpi_variant_count(N.STPI_F32)):
+            info = (ctypes.c_int * 9)()
+            N.lib.stpi_variant_info(N.STPI_F32, i, info)
+            kern = P.Kernel(0.5 * info[0] + 0.5, 0.5 * info[1] + 0.5, info[0], info[1])
+            assert N.lib.stpi_set_variant(i) == 0
+            out = []
+            for flag in ("0", "1"):
+                monkeypatch.setenv("STPI_NO_FUSE", flag)
+                x, r = P.power_iterate(fd, kern, iters=7)
+                torch.cuda.synchronize()
+                out.append((x, r))
+            (xa, ra), (xb, rb) = out
+            assert torch.equal(xa, xb), list(info)
+            assert ra == rb, (list(info), ra, rb)
+    finally:
+        N.lib.stpi_set_variant(-1)

@@ -412,3 +412,66 @@ def test_fallback_rule():
     assert not oracle.fallback(0.2, 0.1)
     assert not oracle.fallback(0.1, 0.1)
     assert oracle.fallback(0.1, float("nan"))
+
+
+# ---- two-level start: grid transfer ------------------------------------------
+
+def test_downsample_divisible_is_block_mean(oracle_mod):
+    """On divisible sizes the box average is numpy's reshape-and-mean."""
+    rng = np.random.default_rng(40)
+    f = rng.uniform(0, 1, (6, 12, 20))
+    ref = f.reshape(3, 2, 3, 4, 5, 4).mean(axis=(1, 3, 5))
+    assert np.allclose(oracle_mod.downsample(f, 4, 2), ref, rtol=0, atol=1e-15)
+
+
+def test_downsample_ragged_conserves_mass_and_constants(oracle_mod):
+    """Partial edge blocks average what exists: constants stay constant and
+    sum(coarse * block size) = sum(fine)."""
+    rng = np.random.default_rng(41)
+    f = rng.uniform(0, 1, (7, 13, 22))
+    sy, st = 4, 3
+    c = oracle_mod.downsample(f, sy, st)
+    assert c.shape == (3, 4, 6)
+    sizes = np.einsum("i,j,k->ijk", [3, 3, 1], [4, 4, 4, 1], [4, 4, 4, 4, 4, 2])
+    assert abs(float((c * sizes).sum()) - float(f.sum())) < 1e-12 * f.size
+    assert np.allclose(oracle_mod.downsample(np.full(f.shape, 0.37), sy, st), 0.37, rtol=0, atol=1e-15)
+
+
+def test_upsample_nearest_is_replication(oracle_mod):
+    rng = np.random.default_rng(42)
+    xc = rng.uniform(0, 1, (3, 4, 6))
+    ref = np.repeat(np.repeat(np.repeat(xc, 3, 0), 4, 1), 4, 2)[:7, :13, :22]
+    assert np.array_equal(oracle_mod.upsample(xc, (7, 13, 22), 4, 3, mode=0), ref)
+
+
+def test_upsample_linear_reproduces_affine_functions(oracle_mod):
+    """Trilinear interpolation between cell centres is exact for affine data
+    away from the clamped borders, and exact for constants everywhere; at a
+    cell centre (odd factor) it returns the cell's value."""
+    sy, st = 3, 3
+    Tc, Hc, Wc = 4, 5, 6
+    tc, yc, xc_ = np.meshgrid(np.arange(Tc), np.arange(Hc), np.arange(Wc), indexing="ij")
+    coarse = 0.5 + 0.25 * tc - 0.125 * yc + 0.0625 * xc_
+    shape = (Tc * st, Hc * sy, Wc * sy)
+    up = oracle_mod.upsample(coarse, shape, sy, st, mode=1)
+    t, y, x = np.meshgrid(np.arange(shape[0]), np.arange(shape[1]), np.arange(shape[2]), indexing="ij")
+    affine = 0.5 + 0.25 * ((t + 0.5) / st - 0.5) - 0.125 * ((y + 0.5) / sy - 0.5) + 0.0625 * ((x + 0.5) / sy - 0.5)
+    inner = (slice(1, shape[0] - 1), slice(1, shape[1] - 1), slice(1, shape[2] - 1))
+    assert np.allclose(up[inner], affine[inner], rtol=0, atol=1e-14)
+    assert np.allclose(up[1::3, 1::3, 1::3], coarse, rtol=0, atol=1e-14)
+    assert np.allclose(oracle_mod.upsample(np.full((Tc, Hc, Wc), 2.5), (11, 14, 17), sy, st, mode=1), 2.5,
+                       rtol=0, atol=1e-14)
+
+
+def test_upsample_multiplies_by_field(oracle_mod):
+    rng = np.random.default_rng(43)
+    xc = rng.uniform(0, 1, (2, 3, 3))
+    m = rng.uniform(0, 1, (4, 6, 6))
+    for mode in (0, 1):
+        assert np.allclose(oracle_mod.upsample(xc, m.shape, 2, 2, mode=mode, mul=m),
+                           oracle_mod.upsample(xc, m.shape, 2, 2, mode=mode) * m, rtol=0, atol=1e-15)
+
+
+def test_coarse_kernel_units(oracle_mod):
+    k = oracle_mod.coarse_kernel(oracle_mod.Kernel(4.0, 1.5, 8, 3), 4, 2)
+    assert (k.sigma_s, k.sigma_t, k.r_s, k.r_t) == (1.0, 0.75, 2, 2)
