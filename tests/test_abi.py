@@ -71,3 +71,16 @@ def test_invalid_calls_fail_before_any_launch(native):
     big = _prob(native, r_s=20)
     rc = native.lib.stpi_iterate(ctypes.byref(big), 16, 32, 1, 1, 0.0, 64, 1 << 30, ctypes.byref(res), None)
     assert rc == native.STPI_EUNSUPPORTED
+
+
+def test_grid_transfer_rejects_bad_arguments(native):
+    """stpi_downsample / stpi_upsample validate before any launch."""
+    L = native.lib
+    assert L.stpi_downsample(0, 4, 4, 2, 1, 0, 16, 32, None) == native.STPI_EINVAL      # empty volume
+    assert L.stpi_downsample(4, 4, 4, 0, 1, 0, 16, 32, None) == native.STPI_EINVAL      # factor < 1
+    assert L.stpi_downsample(4, 4, 4, 2, 1, 9, 16, 32, None) == native.STPI_EINVAL      # dtype
+    assert L.stpi_downsample(4, 4, 4, 2, 1, 0, None, 32, None) == native.STPI_EINVAL    # NULL
+    assert L.stpi_downsample(4, 4, 4, 2, 1, 0, 16, 16, None) == native.STPI_EINVAL      # alias
+    assert L.stpi_upsample(4, 4, 4, 2, 1, 2, 0, 16, None, 32, None) == native.STPI_EINVAL  # mode
+    assert L.stpi_upsample(4, 4, 4, 2, 1, 1, 0, 16, 32, 32, None) == native.STPI_EINVAL    # out aliases mul
+    assert b"alias" in L.stpi_last_error()
