@@ -171,8 +171,9 @@ int stpi_batch_plan(const stpi_clip *clips, int nclips, float sigma_s, float sig
                     stpi_plan **out);
 /* Device workspace stpi_batch_iterate needs (0 for NULL). */
 size_t stpi_batch_workspace_bytes(const stpi_plan *plan);
-/* info[0..9] = nclips, ntiles, persistent grid size, RS, RT, TH, TW, NTHR, RY, QX. */
-int stpi_batch_info(const stpi_plan *plan, int32_t info[10]);
+/* info[0..10] = nclips, ntiles, persistent grid size, RS, RT, TH, TW, NTHR, RY, QX,
+ * PIPE (1: software-pipelined tile loop). */
+int stpi_batch_info(const stpi_plan *plan, int32_t info[11]);
 /* Power iteration of every clip (as stpi_iterate, per clip): x_flat is in/out,
  * init = 1 overwrites each clip with the uniform start, init = 0 uses x_flat.
  * Stops each clip at its first residual < tol (tol > 0) or after max_iters.

@@ -44,9 +44,9 @@ class BatchPlan:
             self._h = None
 
     def info(self) -> dict:
-        a = (ctypes.c_int32 * 10)()
+        a = (ctypes.c_int32 * 11)()
         N.check(N.lib.stpi_batch_info(self._h, a))
-        keys = ("nclips", "ntiles", "grid", "RS", "RT", "TH", "TW", "NTHR", "RY", "QX")
+        keys = ("nclips", "ntiles", "grid", "RS", "RT", "TH", "TW", "NTHR", "RY", "QX", "PIPE")
         return dict(zip(keys, list(a)))
 
     def empty(self, device="cuda") -> torch.Tensor:

@@ -52,11 +52,13 @@ struct BatchArgs {
     Taps<CT> taps;
 };
 
-template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX>
+// PIPE: 1 runs each tile through the software-pipelined tile loop.
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int PIPE>
 __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
     using CT = typename Compute<ST>::type;
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
-    __shared__ CT lds[G::LDS_ELEMS];
+    using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
+    __shared__ CT lds[PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS];
     __shared__ double red[NTHR / 64];
     __shared__ int s_tile;
     if (a.ctl->done_clips >= (uint32_t)a.nclips) return;
@@ -97,9 +99,13 @@ __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
             op.plane = (size_t)cd.H * cd.W;
             op.pbytes = (uint32_t)(op.plane * sizeof(ST));
             const int T = __builtin_amdgcn_readfirstlane(cd.T);
-            stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, T, 0, T, __builtin_amdgcn_readfirstlane(cd.H),
-                                                           __builtin_amdgcn_readfirstlane(cd.W), tx0, ty0, lds, d1,
-                                                           d2);
+            const int H = __builtin_amdgcn_readfirstlane(cd.H), W = __builtin_amdgcn_readfirstlane(cd.W);
+            if constexpr (PIPE)
+                stencil_tile_pipe<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, T, 0, T, H, W, tx0, ty0, lds, d1, d2);
+            else
+                stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, T, 0, T, H, W, tx0, ty0, lds, d1, d2);
+            // the next tile's staging reuses the LDS tiles
+            __syncthreads();
         }
         // block sums land in thread 0 (lane 0 of wave 0); wave 0 broadcasts and stores them
         const double s1 = block_sum<NTHR>(d1, red);
@@ -163,12 +169,12 @@ struct BatchLaunch {
 };
 
 struct BatchVariant {
-    int RS, RT, TH, TW, NTHR, RY, QX;
+    int RS, RT, TH, TW, NTHR, RY, QX, PIPE;
     hipError_t (*launch)(const BatchLaunch &, hipStream_t);
     int (*blocks_per_cu)();
 };
 
-template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX>
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int PIPE>
 hipError_t launch_batch(const BatchLaunch &L, hipStream_t stream) {
     using CT = typename Compute<ST>::type;
     BatchArgs<ST> a;
@@ -186,16 +192,16 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t stream) {
     for (int i = 0; i < 2 * 8 + 1; ++i) a.taps.gt[i] = CT(0);
     for (int d = -RS; d <= RS; ++d) a.taps.gs[d + RS] = (CT)L.gs[d + 16];
     for (int d = -RT; d <= RT; ++d) a.taps.gt[d + RT] = (CT)L.gt[d + 8];
-    hipLaunchKernelGGL((batch_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX>), dim3(L.grid), dim3(NTHR), 0, stream,
-                       a);
+    hipLaunchKernelGGL((batch_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, PIPE>), dim3(L.grid), dim3(NTHR), 0,
+                       stream, a);
     return hipGetLastError();
 }
 
-template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX>
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int PIPE>
 int batch_blocks_per_cu() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX>, NTHR,
-                                                     0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, PIPE>,
+                                                     NTHR, 0) != hipSuccess)
         n = 1;
     return n > 0 ? n : 1;
 }

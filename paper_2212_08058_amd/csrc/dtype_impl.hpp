@@ -86,9 +86,9 @@ hipError_t bce_fin_impl(size_t n, int nblocks, const double *partials, const dou
 }
 
 #ifdef STPI_BATCH_VARIANTS
-#define STPI_BATCH_ENTRY(RS, RT, TH, TW, NTHR, RY, QX)                                \
-    {RS, RT, TH, TW, NTHR, RY, QX, &launch_batch<ST_, RS, RT, TH, TW, NTHR, RY, QX>, \
-     &batch_blocks_per_cu<ST_, RS, RT, TH, TW, NTHR, RY, QX>},
+#define STPI_BATCH_ENTRY(RS, RT, TH, TW, NTHR, RY, QX, PIPE)                                      \
+    {RS, RT, TH, TW, NTHR, RY, QX, PIPE, &launch_batch<ST_, RS, RT, TH, TW, NTHR, RY, QX, PIPE>, \
+     &batch_blocks_per_cu<ST_, RS, RT, TH, TW, NTHR, RY, QX, PIPE>},
 const BatchVariant kBatch[] = {STPI_BATCH_VARIANTS(STPI_BATCH_ENTRY)};
 constexpr int kNBatch = (int)(sizeof(kBatch) / sizeof(kBatch[0]));
 #else

@@ -62,7 +62,7 @@ static const BatchVariant *choose_batch_variant(const stpi_problem *proto, const
             for (int i = 0; i < ops->nbatch; ++i) {
                 const BatchVariant &b = ops->batch_variants[i];
                 if (b.RS == fv.RS && b.RT == fv.RT && b.TH == fv.TH && b.TW == fv.TW && b.NTHR == fv.NTHR &&
-                    b.RY == fv.RY && b.QX == fv.QX)
+                    b.RY == fv.RY && b.QX == fv.QX && b.PIPE == (fv.PIPE ? 1 : 0))
                     return &b;
             }
         }
@@ -236,7 +236,7 @@ int stpi_batch_plan(const stpi_clip *clips, int nclips, float sigma_s, float sig
 
 size_t stpi_batch_workspace_bytes(const stpi_plan *plan) { return plan ? plan->ws_total : 0; }
 
-int stpi_batch_info(const stpi_plan *plan, int32_t info[10]) {
+int stpi_batch_info(const stpi_plan *plan, int32_t info[11]) {
     clear_error();
     if (!plan || !info) return fail(STPI_EINVAL, "NULL plan or info");
     const BatchVariant *v = plan->v;
@@ -250,6 +250,7 @@ int stpi_batch_info(const stpi_plan *plan, int32_t info[10]) {
     info[7] = v->NTHR;
     info[8] = v->RY;
     info[9] = v->QX;
+    info[10] = v->PIPE;
     return STPI_OK;
 }
 

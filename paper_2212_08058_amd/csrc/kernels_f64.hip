@@ -18,6 +18,6 @@
     X(8, 3, 16, 64, 256, 8, 4)   \
     X(16, 8, 16, 64, 256, 8, 4)
 #define STPI_BATCH_VARIANTS(X)       \
-    X(4, 2, 16, 64, 256, 8, 4)   \
-    X(16, 8, 16, 64, 256, 8, 4)
+    X(4, 2, 16, 64, 256, 8, 4, 0)   \
+    X(16, 8, 16, 64, 256, 8, 4, 0)
 #include "dtype_impl.hpp"

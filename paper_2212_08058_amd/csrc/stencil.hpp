@@ -199,6 +199,52 @@ __device__ __forceinline__ void ring_step(CT (&acc)[2 * RT + 1][IPT][QX], const 
         for (int q = 0; q < QX; ++q) acc[es][i][q] = CT(0);
 }
 
+// y-pass of one work item: RY outputs down a column from RY + 2 RS inputs
+// (stride NC in LDS), streamed: each input is added into every output that
+// uses it, so only RY accumulators and the value in flight stay live. Each
+// output still sums its taps in increasing d.
+template <class CT, int RS, int RY, int NC, int LW>
+__device__ __forceinline__ void ypass_item(const CT *col, CT *dstp, const Taps<CT> &tp) {
+    CT s[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) s[r] = CT(0);
+#pragma unroll
+    for (int k = 0; k < RY + 2 * RS; ++k) {
+        const CT u = col[k * NC];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int d = k - r;
+            if (d >= 0 && d <= 2 * RS) s[r] = fma(tp.gs[d], u, s[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) dstp[r * LW] = s[r];
+}
+
+// x-pass of one work item: QX outputs along a row from 16-byte LDS reads of
+// the window starting RSA - RS before the first tap, streamed the same way.
+template <class CT, int RS, int QX, int RSA>
+__device__ __forceinline__ void xpass_item(const CT *row, CT (&o)[QX], const Taps<CT> &tp) {
+    using V4 = LdsVec<CT>;
+    constexpr int NV = (QX + 2 * RSA) / V4::N;
+    const typename V4::type *rowp = reinterpret_cast<const typename V4::type *>(__builtin_assume_aligned(row, 16));
+#pragma unroll
+    for (int q = 0; q < QX; ++q) o[q] = CT(0);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const typename V4::type t4 = rowp[k];
+#pragma unroll
+        for (int e = 0; e < V4::N; ++e) {
+            const int j = k * V4::N + e;  // window index
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                const int d = j - q - (RSA - RS);
+                if (d >= 0 && d <= 2 * RS) o[q] = fma(tp.gs[d], t4[e], o[q]);
+            }
+        }
+    }
+}
+
 // Frame loop unrolled by the ring length: body(J, p) runs for p = 0 .. n-1
 // with J = (p + SHIFT) mod NTS as a compile-time constant. Every pass of the
 // outer loop walks the ring once, so each ring slot stays in the same
@@ -455,18 +501,7 @@ __device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &
                 if (it < NYI) {
                     const int c = it % NC;
                     const int g = it / NC;
-                    const CT *col = U + (g * RY) * NC + c;
-                    CT u[RY + 2 * RS];
-#pragma unroll
-                    for (int k = 0; k < RY + 2 * RS; ++k) u[k] = col[k * NC];
-                    CT *dstp = Y + (g * RY) * LW + c + (RSA - RS);
-#pragma unroll
-                    for (int r = 0; r < RY; ++r) {
-                        CT s = CT(0);
-#pragma unroll
-                        for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], u[r + d], s);
-                        dstp[r * LW] = s;
-                    }
+                    ypass_item<CT, RS, RY, NC, LW>(U + (g * RY) * NC + c, Y + (g * RY) * LW + c + (RSA - RS), tp);
                 }
             }
         }
@@ -477,26 +512,7 @@ __device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &
             if (live) {
                 const CT *Y = Y0 + (tx & 1) * PG::YB;
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    using V4 = LdsVec<CT>;
-                    constexpr int NV = (QX + 2 * RSA) / V4::N;
-                    const typename V4::type *rowp = reinterpret_cast<const typename V4::type *>(
-                        __builtin_assume_aligned(Y + orow[i] * LW + ocol[i], 16));
-                    CT w[QX + 2 * RSA];
-#pragma unroll
-                    for (int k = 0; k < NV; ++k) {
-                        const typename V4::type t4 = rowp[k];
-#pragma unroll
-                        for (int e = 0; e < V4::N; ++e) w[k * V4::N + e] = t4[e];
-                    }
-#pragma unroll
-                    for (int q = 0; q < QX; ++q) {
-                        CT s = CT(0);
-#pragma unroll
-                        for (int d = 0; d <= 2 * RS; ++d) s = fma(tp.gs[d], w[q + d + RSA - RS], s);
-                        v[i][q] = s;
-                    }
-                }
+                for (int i = 0; i < IPT; ++i) xpass_item<CT, RS, QX, RSA>(Y + orow[i] * LW + ocol[i], v[i], tp);
             } else {
 #pragma unroll
                 for (int i = 0; i < IPT; ++i)

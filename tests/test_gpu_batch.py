@@ -53,7 +53,7 @@ def test_batch_bitwise_equals_single_clip_path(P):
     Pm, B = P
     from paper_2212_08058_amd import _native as N
     kern = Pm.Kernel(4.0, 1.5, 8, 3)
-    shapes = [(11, 60, 130), (4, 45, 70), (20, 33, 150)]
+    shapes = [(11, 60, 216), (4, 45, 108), (20, 30, 150)]
     fs = _clips(shapes, seed=10)
     plan = B.BatchPlan(shapes, kern)
     info = plan.info()
@@ -63,7 +63,8 @@ def test_batch_bitwise_equals_single_clip_path(P):
     for i in range(nv):
         a = (ctypes.c_int * 9)()
         N.lib.stpi_variant_info(0, i, a)
-        if a[8] == 0 and [a[k] for k in range(7)] == [info[k] for k in ("RS", "RT", "TH", "TW", "NTHR", "RY", "QX")]:
+        if a[8] == info["PIPE"] and [a[k] for k in range(7)] == [info[k] for k in
+                                                              ("RS", "RT", "TH", "TW", "NTHR", "RY", "QX")]:
             idx = i
             break
     assert idx is not None
@@ -135,3 +136,36 @@ def test_autotune_roundtrip(P, tmp_path):
     xr, _ = oracle.iterate(f, okf(kern), iters=3)
     assert np.linalg.norm(x.double().cpu().numpy() - xr) / np.linalg.norm(xr) < 1e-5
     B.autotune_clear()
+
+
+def test_pipelined_batch_variant(P, tmp_path):
+    """A tuned entry for the dominant frame size steers the plan to the
+    pipelined 15 x 108 tile: its results match the oracle per clip and are
+    bitwise those of the single-clip path on the same variant."""
+    Pm, B = P
+    from paper_2212_08058_amd import _native as N
+    kern = Pm.Kernel(4.0, 1.5, 8, 3)
+    shapes = [(14, 45, 216), (6, 45, 216), (9, 30, 108)]
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = tmp_path / "tune.txt"
+    path.write_text(f"{arch} 0 8 3 45 216 8 3 15 108 512 5 4 1 1 1.0\n")
+    B.autotune_clear()
+    B.autotune_load(str(path))
+    try:
+        plan = B.BatchPlan(shapes, kern)
+        info = plan.info()
+        assert (info["TH"], info["TW"], info["PIPE"]) == (15, 108, 1), info
+        fs = _clips(shapes, seed=40)
+        f_flat = plan.pack([torch.from_numpy(f).to(DEV) for f in fs])
+        s = torch.cuda.Stream()
+        x_flat, res = plan.iterate(f_flat, max_iters=6, tol=0.0, stream=s)
+        torch.cuda.synchronize()
+        for f, xv, r in zip(fs, plan.views(x_flat), res):
+            xr, _ = oracle.iterate(f, okf(kern), iters=6)
+            err = float(np.linalg.norm(xv.double().cpu().numpy() - xr) / np.linalg.norm(xr))
+            assert r["iters"] == 6 and err < 1e-5, (f.shape, err)
+            xs, rs = Pm.power_iterate(torch.from_numpy(f).to(DEV), kern, iters=6)
+            if Pm.launch_shape(f.shape, kern)["segments"] == 1:
+                assert torch.equal(xs, xv), f.shape
+    finally:
+        B.autotune_clear()
