@@ -7,12 +7,16 @@
 // The two 16 -> 16 layers, and their input gradients, run as implicit GEMMs on
 // the matrix cores (v_mfma_f32_16x16x16_bf16): per wavefront a 16-channel x
 // 16-voxel output block accumulates 27 taps of (16 out x 16 in) weights times
-// (16 in x 16 voxels) inputs. The 1 -> 16 and 16 -> 1 layers and the weight
-// gradients are VALU kernels (their shapes fit the matrix cores badly).
+// (16 in x 16 voxels) inputs; so do their weight gradients (wgrad16_kernel,
+// a sum over voxels of 16 x 16 outer products per tap). The 1 -> 16 and
+// 16 -> 1 layers and their weight gradients are VALU kernels (their shapes fit
+// the matrix cores badly).
 //
 // Parameter layout (FP32 masters, PyTorch conv3d order [Cout][Cin][3][3][3]):
 //   w1[16][1][27] b1[16] w2[16][16][27] b2[16] w3[16][16][27] b3[16] w4[1][16][27] b4[1]
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include <cmath>
 #include <cstring>
@@ -301,6 +305,55 @@ __global__ __launch_bounds__(256) void wgrad_kernel(Dims d, const void *a_, cons
     }
 }
 
+// Weight and bias gradients of a 16 -> 16 layer on the matrix cores. For each
+// tap, dW_tap[co][ci] = sum_v g[v][co] a[v + tap][ci] is a (16 x V) x (V x 16)
+// product: v_mfma_f32_16x16x4f32 takes 4 voxels per instruction, lane l
+// holding g[v0 + l/16][co = l%16] (A) and a[v0 + l/16 + tap][ci = l%16] (B),
+// so a wavefront's loads are contiguous runs of the channels-last volumes.
+// Operands are the stored bfloat16 values widened exactly to float, so the
+// products and FP32 sums are those of a bfloat16 matrix product with FP32
+// accumulation. Each wavefront writes its partial sums (layout as
+// wgrad_kernel's, one "block" per wavefront); wgrad_reduce sums them.
+__global__ __launch_bounds__(256) void wgrad16_kernel(Dims d, const short *a, const short *g, float *partials) {
+    constexpr int NP = C * (C * NT + 1);
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * 4;
+    const int ch = lane % 16, kv = lane / 16;
+    const size_t V = (size_t)d.T * d.H * d.W;
+    const size_t nq = (V + 3) / 4;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int tap = 0; tap < NT; ++tap) acc[tap] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.0f;
+    for (size_t q = wave; q < nq; q += nwaves) {
+        const size_t v = q * 4 + kv;
+        const bool vin = v < V;
+        const int x = vin ? (int)(v % d.W) : 0, y = vin ? (int)((v / d.W) % d.H) : 0;
+        const int t = vin ? (int)(v / ((size_t)d.W * d.H)) : 0;
+        const float gv = vin ? bf2f(g[v * C + ch]) : 0.0f;
+        bacc += gv;
+#pragma unroll
+        for (int tap = 0; tap < NT; ++tap) {
+            const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
+            const float av = vin && inside(d, tt, yy, xx) ? bf2f(a[(((size_t)tt * d.H + yy) * d.W + xx) * C + ch]) : 0.0f;
+            acc[tap] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, av, acc[tap], 0, 0, 0);
+        }
+    }
+    // lane holds dW_tap[co = 4 kv + j][ci = ch]
+    float *out = partials + (size_t)wave * NP;
+#pragma unroll
+    for (int tap = 0; tap < NT; ++tap)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[(4 * kv + j) * (C * NT + 1) + ch * NT + tap] = acc[tap][j];
+    // bias: lanes ch, ch + 16, ch + 32, ch + 48 hold the four voxel rows of channel ch
+    float b = bacc + __shfl_xor(bacc, 16, 64);
+    b += __shfl_xor(b, 32, 64);
+    if (kv == 0) out[ch * (C * NT + 1) + C * NT] = b;
+}
+
+constexpr int WG16_BLOCKS = 256;  // x 4 wavefronts: wgrad16_kernel's partial sums
+
 // Sums the workgroup partials of one layer into the gradient buffer (same
 // layout as the masters): dW[co][ci][tap] at w_off, db[co] at b_off.
 template <int CI, int CO>
@@ -346,7 +399,7 @@ size_t stpi_net_workspace_bytes(const stpi_problem *p) {
     size_t b = 5 * ((V * C * 2 + 255) & ~(size_t)255);
     b += (V * 4 + 255) & ~(size_t)255;
     b += 4096 * 8;
-    b += (size_t)WG_BLOCKS * C * (C * NT + 1) * sizeof(float);
+    b += (size_t)std::max(WG_BLOCKS, 4 * WG16_BLOCKS) * C * (C * NT + 1) * sizeof(float);
     return b;
 }
 
@@ -437,17 +490,17 @@ int stpi_net_backward(const stpi_problem *p, const float *f, const void *prep, c
     hipLaunchKernelGGL((wgrad_reduce<C, 1>), dim3(2), dim3(256), 0, s, WG_BLOCKS, n.wpart, grad, OFF_W4, OFF_B4);
     hipLaunchKernelGGL(out_bwd_kernel, dim3(2048), dim3(256), 0, s, d, n.gy, n.act3, P, n.g_a);  // g at pre3
     // layer 3
-    hipLaunchKernelGGL((wgrad_kernel<C, C>), dim3(WG_BLOCKS), dim3(256), 0, s, d, (const void *)n.act2,
-                       (const void *)n.g_a, n.wpart);
-    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s, WG_BLOCKS,
-                       n.wpart, grad, OFF_W3, OFF_B3);
+    hipLaunchKernelGGL(wgrad16_kernel, dim3(WG16_BLOCKS), dim3(256), 0, s, d, (const short *)n.act2, n.g_a,
+                       n.wpart);
+    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s,
+                       4 * WG16_BLOCKS, n.wpart, grad, OFF_W3, OFF_B3);
     hipLaunchKernelGGL(conv16_kernel<1>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.g_a, P->a3d,
                        (const float *)nullptr, n.act2, n.g_b);  // g at pre2
     // layer 2
-    hipLaunchKernelGGL((wgrad_kernel<C, C>), dim3(WG_BLOCKS), dim3(256), 0, s, d, (const void *)n.act1,
-                       (const void *)n.g_b, n.wpart);
-    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s, WG_BLOCKS,
-                       n.wpart, grad, OFF_W2, OFF_B2);
+    hipLaunchKernelGGL(wgrad16_kernel, dim3(WG16_BLOCKS), dim3(256), 0, s, d, (const short *)n.act1, n.g_b,
+                       n.wpart);
+    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s,
+                       4 * WG16_BLOCKS, n.wpart, grad, OFF_W2, OFF_B2);
     hipLaunchKernelGGL(conv16_kernel<1>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.g_b, P->a2d,
                        (const float *)nullptr, n.act1, n.g_a);  // g at pre1
     // layer 1
