@@ -9,8 +9,11 @@ device, final normalisation, one host synchronisation.
 
 value = 64*480*854 * 20 / (seconds per step), inputs resident in HBM.
 roofline: the fused step kernel alone, timed with HIP events on the stream it
-runs on; its bound is the vector ALU (non-packed FP32 FMA, 78.6 TFLOP/s on
-256 CUs at 2.4 GHz) and its HBM fraction is reported beside it.
+runs on. With the matrix-core tile loop (both spatial passes on MFMA) the step
+is bound by memory traffic: achieved = algorithmic bytes (read f and x, write
+z) over the kernel time, against 8 TB/s. With a vector-ALU tile loop its bound
+is the non-packed FP32 FMA rate (78.6 TFLOP/s on 256 CUs at 2.4 GHz). The other
+figure is reported beside the bound in either case.
 cpu_baseline: the FP64 oracle on a bounded sample of the same voxels.
 """
 from __future__ import annotations
@@ -36,8 +39,9 @@ def log(msg):
 # Sources that define the f32 step kernel; the committed counter summary is
 # used only while their hash matches the one recorded with the counters.
 STEP_SOURCES = ["paper_2212_08058_amd/csrc/common.hpp", "paper_2212_08058_amd/csrc/stencil.hpp",
-                "paper_2212_08058_amd/csrc/forward.hpp", "paper_2212_08058_amd/csrc/kernels_f32.hip",
-                "paper_2212_08058_amd/csrc/host.cpp"]
+                "paper_2212_08058_amd/csrc/stencil_mfma.hpp", "paper_2212_08058_amd/csrc/forward.hpp",
+                "paper_2212_08058_amd/csrc/kernels_f32.hip", "paper_2212_08058_amd/csrc/host.cpp"]
+LOOP_KIND = {0: "plain", 1: "pipelined", 2: "straight-line", 3: "matrix-core"}
 
 
 def profiled_traffic(tag: str):
@@ -191,24 +195,23 @@ def main():
             "voxels": Nvox,
             "iters": iters,
             "parallelism": "single GPU",
-            "tile": dict(zip(("r_s", "r_t", "TH", "TW", "threads", "RY", "QX", "min_waves", "pipelined"), list(vinfo)),
+            "tile": dict(zip(("r_s", "r_t", "TH", "TW", "threads", "RY", "QX", "min_waves"), list(vinfo)[:8]),
+                         loop=LOOP_KIND.get(vinfo[8], str(vinfo[8])),
                          segments=P.launch_shape(f.shape, kern, dtype)["segments"]),
         },
-        "roofline": {
-            "bound": "alu",
-            "achieved": tflops,
-            "peak": VALU_FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": tflops / VALU_FP32_PEAK_TFLOPS,
-            "traffic": None,
-            "kernel": "fwd_step_kernel",
-            "kernel_ms": kern_ms,
-            "flop_per_voxel": flops_per_voxel,
-            "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
-                    "bytes_per_voxel": bytes_per_voxel},
-        },
+        "roofline": {},
         "result": {"residual": res["residual"], "lambda": res["lambda_"], "iters": res["iters"]},
     }
+    alu = {"achieved": tflops, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / VALU_FP32_PEAK_TFLOPS,
+           "flop_per_voxel": flops_per_voxel}
+    hbm = {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
+           "bytes_per_voxel": bytes_per_voxel}
+    if vinfo[8] == 3:
+        out["roofline"] = {"bound": "hbm", **hbm, "traffic": None, "kernel": "fwd_step_kernel", "kernel_ms": kern_ms,
+                           "alu": alu}
+    else:
+        out["roofline"] = {"bound": "alu", **alu, "traffic": None, "kernel": "fwd_step_kernel", "kernel_ms": kern_ms,
+                           "hbm": hbm}
     prof = profiled_traffic(f"fwd_step_{T}x{H}x{W}_{args.dtype}")
     ctype = "float" if args.dtype == "f32" else "stpi::bf16"
     sig = f"fwd_step_kernel<{ctype}, " + ", ".join(str(v) for v in vinfo) + ">"

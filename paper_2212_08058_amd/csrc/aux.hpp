@@ -88,6 +88,46 @@ __global__ void train_init_kernel(size_t n, ST *x, double *norm) {
 }
 
 // Per-workgroup maximum and its first index: partials[2b] = max, [2b+1] = index.
+// *out = max(*out, max_i |f_i| (x null) or |f_i x_i|) as float bits (the
+// values are >= 0, so their bit patterns order as the floats do; NaNs are
+// skipped). The bound that scales the matrix-core step's half-precision
+// operands.
+template <class ST>
+__global__ void bound_kernel(size_t n, const ST *f, const ST *x, uint32_t *out) {
+    __shared__ float red[AUX_THREADS / 64];
+    // four independent maxima per thread keep four loads in flight
+    float m[4] = {0.f, 0.f, 0.f, 0.f};
+    const size_t stride = (size_t)gridDim.x * AUX_THREADS;
+    size_t i = (size_t)blockIdx.x * AUX_THREADS + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float v = fabsf((float)ld(f + i + k * stride));
+            if (x) v *= fabsf((float)ld(x + i + k * stride));
+            m[k] = v > m[k] ? v : m[k];
+        }
+    }
+    for (; i < n; i += stride) {
+        float v = fabsf((float)ld(f + i));
+        if (x) v *= fabsf((float)ld(x + i));
+        m[0] = v > m[0] ? v : m[0];
+    }
+    float r = m[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) r = m[k] > r ? m[k] : r;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float w = __shfl_xor(r, o, 64);
+        r = w > r ? w : r;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < AUX_THREADS / 64; ++w) r = red[w] > r ? red[w] : r;
+        atomicMax(out, __float_as_uint(r));
+    }
+}
+
 template <class ST>
 __global__ void max_kernel(size_t n, const ST *x, double *partials) {
     __shared__ double sv[AUX_THREADS];

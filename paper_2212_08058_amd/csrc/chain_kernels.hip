@@ -19,7 +19,12 @@ __global__ void state_init_kernel(DevState *s, double scale, double tol, int max
         s->max_iters = max_iters;
         s->converged = 0;
         s->arrive = 0u;
+        s->ubound = 0u;
     }
+}
+
+__global__ void clear_word_kernel(uint32_t *w) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *w = 0u;
 }
 
 // Start from the caller's vector: scale = 1 / ||x0||.
@@ -186,6 +191,11 @@ hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iter
 
 hipError_t launch_state_from_norm(const double *partials, int n, DevState *s, hipStream_t st) {
     hipLaunchKernelGGL(state_from_norm_kernel, dim3(1), dim3(CHAIN_THREADS), 0, st, partials, n, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_word(uint32_t *w, hipStream_t st) {
+    hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(64), 0, st, w);
     return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ struct DevState {
     int32_t max_iters;
     int32_t converged;
     uint32_t arrive;   // workgroups of the running step that stored their partial sums
+    uint32_t ubound;   // float bits of max |f| (matrix-core step variants)
 };
 
 constexpr uint32_t FLAG_ZERO = 1u;

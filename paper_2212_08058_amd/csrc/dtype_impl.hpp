@@ -28,6 +28,12 @@ hipError_t normalize_impl(void *x, const void *buf1, size_t n, const DevState *s
     return hipGetLastError();
 }
 
+hipError_t bound_impl(size_t n, const void *f, const void *x, uint32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(bound_kernel<ST_>, dim3(4096), dim3(AUX_THREADS), 0, s, n, (const ST_ *)f,
+                       (const ST_ *)x, out);
+    return hipGetLastError();
+}
+
 #define STPI_VARIANT_ENTRY(RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE) \
     {RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, &launch_fwd<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>, \
      &fwd_blocks_per_cu<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>},
@@ -114,6 +120,7 @@ hipError_t batch_normalize_impl(void *x, const void *buf1, const ClipDesc *clips
 
 const DtypeOps kOps = {sizeof(ST_),       kVariants,        (int)(sizeof(kVariants) / sizeof(kVariants[0])),
                        &fill_ones_impl,   &sumsq_impl,      &normalize_impl,
+                       &bound_impl,
                        kAdj,              kNAdj,            &combine_fwd_impl,
                        &combine_bwd_impl, &scale_impl,      &dot_impl,
                        &train_init_impl,  &max_impl,        &bce_impl,

@@ -14,6 +14,8 @@ struct DtypeOps {
     hipError_t (*fill_ones)(void *x, size_t n, hipStream_t);
     hipError_t (*sumsq)(const void *x, size_t n, double *partials, hipStream_t);
     hipError_t (*normalize)(void *x, const void *buf1, size_t n, const DevState *s, hipStream_t);
+    // *out = max(*out, max |f| or max |f x|) as float bits (matrix-core step variants)
+    hipError_t (*bound)(size_t n, const void *f, const void *x, uint32_t *out, hipStream_t);
     // differentiation path (null where a storage type does not provide it)
     const AdjVariant *adj_variants;
     int nadj;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "stencil.hpp"
+#include "stencil_mfma.hpp"
 
 namespace stpi {
 
@@ -18,6 +19,10 @@ struct FwdLaunch {
     int T, H, W;
     int nseg;            // frame segments per tile (0 is read as 1)
     int fuse;            // iterate mode: finalise the step in its last workgroup (if the variant can)
+    // matrix-core variants: float bits of a bound on |f x_stored scale| (iterate
+    // mode: on |f|, the iterate being unit; single step: on |f x_stored|, scaled
+    // by |x_scale| in the kernel)
+    const uint32_t *ubound;
     double gs[2 * 16 + 1];
     double gt[2 * 8 + 1];
 };
@@ -43,6 +48,8 @@ struct FwdArgs {
     ST *vout;
     int T, H, W;
     int nseg;  // frame segments per tile: workgroup (tile, seg) owns frames [seg T / nseg, (seg + 1) T / nseg)
+    const uint32_t *ubound;  // matrix-core variants (see FwdLaunch)
+    int rs;                  // the problem's space radius
     Taps<CT> taps;
 };
 
@@ -189,13 +196,15 @@ struct FwdOp {
 // OCC: minimum waves per SIMD the register allocation must allow (1 = no limit;
 // with NTHR = 512, OCC = 4 lets two workgroups share a CU).
 // PIPE: 1 selects the software-pipelined tile loop (stencil_tile_pipe), 2 its
-// straight-line form (stencil_tile_flat).
+// straight-line form (stencil_tile_flat), 3 the matrix-core tile loop
+// (stencil_tile_mfma; RS = 16, any space radius up to 16).
 template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>
 __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     using CT = typename Compute<ST>::type;
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
     using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
-    __shared__ CT lds[PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS];
+    static_assert(PIPE != 3 || (RS == 16 && sizeof(CT) == 4), "matrix-core variants: RS 16, float arithmetic");
+    __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR>::value : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
     __shared__ double red[NTHR / 64];
 
     const int nbx = (a.W + TW - 1) / TW, nby = (a.H + TH - 1) / TH;
@@ -206,23 +215,44 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     const int t0 = (int)((int64_t)seg * a.T / a.nseg), t1 = (int)((int64_t)(seg + 1) * a.T / a.nseg);
     FwdOp<ST> op;
     op.f = a.f;
+    double scale;
     if (a.state) {
         if (a.state->done) return;
         const int cur = a.state->cur;
         op.src = cur ? a.buf1 : a.buf0;
         op.dst = cur ? a.buf0 : a.buf1;
-        op.scale = (CT)a.state->scale;
+        scale = a.state->scale;
     } else {
         op.src = a.buf0;
         op.dst = a.buf1;
-        op.scale = a.norm_in ? (CT)(1.0 / *a.norm_in) : (CT)a.x_scale;
+        scale = a.norm_in ? 1.0 / *a.norm_in : a.x_scale;
     }
+    op.scale = (CT)scale;
     op.vout = a.vout;
     op.plane = (size_t)a.H * a.W;
     op.pbytes = (uint32_t)(op.plane * sizeof(ST));
     double d1 = 0.0, d2 = 0.0;
     const int x0 = (tile % nbx) * TW, y0 = (tile / nbx) * TH;
-    if constexpr (PIPE == 2)
+    if constexpr (PIPE == 3) {
+        // staging multiplier scale 2^S with |f x scale 2^S| < 2^10, output scale 2^-S
+        float bound = __uint_as_float(*a.ubound);
+        if (!a.state) bound *= (float)fabs(scale);
+        int e = 0;
+        if (bound > 0.f && bound <= 3.0e38f) (void)frexpf(bound, &e);
+        e = e < -100 ? -100 : (e > 100 ? 100 : e);
+        const float umul = (float)(scale * ldexp(1.0, 10 - e));
+        op.scale = ldexpf(1.f, e - 10);
+        __shared__ float tapl[2 * 16 + 1];
+        if (threadIdx.x < 2 * 16 + 1) {
+            float g = 0.f;
+#pragma unroll
+            for (int i = 0; i < 2 * 16 + 1; ++i) g = (int)threadIdx.x == i ? (float)a.taps.gs[i] : g;
+            tapl[threadIdx.x] = g;
+        }
+        __syncthreads();
+        stencil_tile_mfma<CT, RT, TH, TW, NTHR>(op, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1,
+                                               d2);
+    } else if constexpr (PIPE == 2)
         stencil_tile_flat<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1, d2);
     else if constexpr (PIPE == 1)
         stencil_tile_pipe<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1, d2);
@@ -287,6 +317,11 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     a.H = L.H;
     a.W = L.W;
     a.nseg = L.nseg > 0 ? L.nseg : 1;
+    a.ubound = L.ubound;
+    a.rs = 0;
+    for (int d = 1; d <= 16; ++d)
+        if (L.gs[16 + d] != 0.0) a.rs = d;
+    if (PIPE == 3 && !L.ubound) return hipErrorInvalidValue;
     // L holds taps centred at index 16 (space) and 8 (time), zero beyond the
     // problem's radii; the kernel wants them centred at its compiled RS, RT.
     for (int i = 0; i < 2 * 16 + 1; ++i) a.taps.gs[i] = CT(0);

@@ -74,12 +74,20 @@ static double variant_cost(const Variant &v, const stpi_problem *p) {
     // Taps per voxel plus the y-pass over the x-halo, on the padded tile grid.
     const double gx = std::ceil((double)p->W / v.TW), gy = std::ceil((double)p->H / v.TH);
     const double cover = gx * v.TW * gy * v.TH / ((double)p->W * p->H);
+    if (v.PIPE == 3) {
+        // matrix-core spatial passes: bound by memory traffic and latency, not
+        // by the space radius; in the units of the tap count above, measured
+        // at 480 x 854 frames as 42 plus two per temporal tap
+        return (42.0 + 2.0 * (2.0 * v.RT + 1)) * cover;
+    }
     const double taps = (2.0 * v.RS + 1) * (1.0 + 2.0 * v.RS / v.TW) + (2.0 * v.RS + 1) + (2.0 * v.RT + 1);
     return taps * cover;
 }
 
-const Variant *choose_variant(const stpi_problem *p, int forced_index) {
+const Variant *choose_variant(const stpi_problem *p, int forced_index, bool allow_mfma) {
     const DtypeOps *ops = ops_for(p->dtype);
+    if (forced_index >= 0 && forced_index < ops->nvariants && !allow_mfma && ops->variants[forced_index].PIPE == 3)
+        forced_index = -1;
     if (forced_index >= 0) {
         if (forced_index >= ops->nvariants) return nullptr;
         const Variant &v = ops->variants[forced_index];
@@ -89,13 +97,14 @@ const Variant *choose_variant(const stpi_problem *p, int forced_index) {
     int tuned = tuned_variant(p);
     if (tuned >= 0 && tuned < ops->nvariants) {
         const Variant &v = ops->variants[tuned];
-        if (v.RS >= p->r_s && v.RT >= p->r_t) return &v;
+        if (v.RS >= p->r_s && v.RT >= p->r_t && (allow_mfma || v.PIPE != 3)) return &v;
     }
     const Variant *best = nullptr;
     double best_cost = 1e300;
     for (int i = 0; i < ops->nvariants; ++i) {
         const Variant &v = ops->variants[i];
         if (v.RS < p->r_s || v.RT < p->r_t) continue;
+        if (v.PIPE == 3 && !allow_mfma) continue;
         const double c = variant_cost(v, p);
         if (c < best_cost) {
             best_cost = c;
@@ -233,7 +242,8 @@ int enqueue_chain_part(const ChainArgs &a, int part, hipStream_t s) {
             return enqueue_iteration(a.p, a.ops, a.v, a.f, a.x, a.buf1, a.state, a.partials, a.init, a.max_iters,
                                      a.tol, s);
         case CHAIN_HEAD: {
-            const int rc = enqueue_chain_init(a.p, a.ops, a.x, a.state, a.partials, a.init, a.max_iters, a.tol, s);
+            const int rc =
+                enqueue_chain_init(a.p, a.ops, a.x, a.state, a.partials, a.init, a.max_iters, a.tol, s, a.v, a.f);
             return rc ? rc : enqueue_chain_steps(a.p, a.v, a.f, a.x, a.buf1, a.state, a.partials, CHAIN_CHUNK, s);
         }
         case CHAIN_CHUNK_PART:
@@ -329,6 +339,19 @@ size_t stpi_workspace_bytes(const stpi_problem *p) {
     return layout_for(p).total;
 }
 
+// Matrix-core variants scale their half-precision operands by a bound on
+// |f x_stored| (times |x_scale|, applied in the kernel); it is computed here
+// into the workspace's state area, which a single step does not otherwise use.
+static hipError_t single_step_bound(const Variant *v, const stpi_problem *p, const void *f, const void *x, void *ws,
+                                    FwdLaunch &FL, hipStream_t s) {
+    if (v->PIPE != 3) return hipSuccess;
+    uint32_t *w = &((DevState *)ws)->ubound;
+    FL.ubound = w;
+    hipError_t e = launch_clear_word(w, s);
+    if (e == hipSuccess) e = ops_for(p->dtype)->bound((size_t)p->T * p->H * p->W, f, x, w, s);
+    return e;
+}
+
 int stpi_step(const stpi_problem *p, const void *f, const void *x, double x_scale, void *z, double *d_sums,
               void *ws, size_t ws_bytes, void *stream) {
     clear_error();
@@ -355,7 +378,9 @@ int stpi_step(const stpi_problem *p, const void *f, const void *x, double x_scal
     FL.W = p->W;
     FL.nseg = segments_for(*v, p);
     make_taps(p, FL.gs, FL.gt);
-    hipError_t e = v->launch(FL, s);
+    hipError_t e = single_step_bound(v, p, f, x, ws, FL, s);
+    if (e != hipSuccess) return hip_fail(e, "operand bound");
+    e = v->launch(FL, s);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     e = launch_step_sums(FL.partials, grid_blocks(*v, p), x_scale, d_sums, s);
     if (e != hipSuccess) return hip_fail(e, "step sums launch");
@@ -474,6 +499,7 @@ int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z,
     make_taps(p, FL.gs, FL.gt);
     hipEvent_t e0, e1;
     hipError_t e;
+    if ((e = single_step_bound(v, p, f, x, ws, FL, s)) != hipSuccess) return hip_fail(e, "operand bound");
     if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event create");
     if ((e = hipEventCreate(&e1)) != hipSuccess) {
         (void)hipEventDestroy(e0);
@@ -546,7 +572,8 @@ namespace stpi {
 // Enqueues start vector, max_iters (step, finalise) pairs and the final
 // normalisation. No host synchronisation.
 int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevState *state, double *partials,
-                       int init, int max_iters, double tol, hipStream_t s) {
+                       int init, int max_iters, double tol, hipStream_t s, const Variant *v,
+                       const void *f) {
     const size_t N = (size_t)p->T * p->H * p->W;
     hipError_t e;
     if (init == 1) {
@@ -559,6 +586,9 @@ int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevS
         if ((e = launch_state_from_norm(partials, NORM_BLOCKS_HOST, state, s)) != hipSuccess)
             return hip_fail(e, "init norm");
     }
+    // matrix-core steps scale their operands by max |f| (the iterate is unit)
+    if (v && v->PIPE == 3 && (e = ops->bound(N, f, nullptr, &state->ubound, s)) != hipSuccess)
+        return hip_fail(e, "operand bound");
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init");
     return STPI_OK;
 }
@@ -572,6 +602,7 @@ int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, 
     FL.buf0 = x;
     FL.buf1 = buf1;
     FL.state = state;
+    FL.ubound = &state->ubound;
     FL.partials = partials;
     FL.T = p->T;
     FL.H = p->H;
@@ -593,7 +624,7 @@ int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, 
 int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
                       void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,
                       hipStream_t s) {
-    int rc = enqueue_chain_init(p, ops, x, state, partials, init, max_iters, tol, s);
+    int rc = enqueue_chain_init(p, ops, x, state, partials, init, max_iters, tol, s, v, f);
     if (!rc) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, max_iters, s);
     if (rc) return rc;
     const hipError_t e = ops->normalize(x, buf1, (size_t)p->T * p->H * p->W, state, s);

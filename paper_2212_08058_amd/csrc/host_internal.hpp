@@ -25,14 +25,16 @@ void clear_error();
 const DtypeOps *ops_for(int dtype);
 int validate_problem(const stpi_problem *p);
 void make_taps(const stpi_problem *p, double *gs, double *gt);
-const Variant *choose_variant(const stpi_problem *p, int forced_index);
+// allow_mfma false skips the matrix-core variants (callers that cannot supply
+// their operand bound).
+const Variant *choose_variant(const stpi_problem *p, int forced_index, bool allow_mfma = true);
 int grid_blocks(const Variant &v, const stpi_problem *p);
 int segments_for(const Variant &v, const stpi_problem *p);
 constexpr int STPI_NSEG_MAX = 4;  // frame segments per tile at most
 WsLayout layout_for(const stpi_problem *p);
 constexpr int CHAIN_CHUNK = 16;  // steps per replayed chain segment in long tolerance runs
 int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevState *state, double *partials,
-                       int init, int max_iters, double tol, hipStream_t s);
+                       int init, int max_iters, double tol, hipStream_t s, const Variant *v, const void *f);
 int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, void *x, void *buf1, DevState *state,
                         double *partials, int steps, hipStream_t s);
 int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
@@ -45,6 +47,7 @@ int tuned_variant(const stpi_problem *p);
 
 hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, hipStream_t st);
 hipError_t launch_state_from_norm(const double *partials, int n, DevState *s, hipStream_t st);
+hipError_t launch_clear_word(uint32_t *w, hipStream_t st);
 hipError_t launch_finalize(const double *partials, int n, DevState *s, hipStream_t st);
 hipError_t launch_step_sums(const double *partials, int n, double x_scale, double *d_sums, hipStream_t st);
 hipError_t launch_combine_bwd_finalize(int C, int nblocks, const double *partials, const double *w, double *gw,

@@ -66,7 +66,7 @@ int stpi_train_step(const stpi_problem *p, const void *f, const void *z_in, cons
         return fail(STPI_EINVAL, "outputs must not alias inputs");
     const WsLayout L = layout_for(p);
     if (!ws || ws_bytes < L.total) return fail(STPI_EWORKSPACE, "workspace needs %zu bytes", L.total);
-    const Variant *v = choose_variant(p, forced_variant());
+    const Variant *v = choose_variant(p, forced_variant(), false);
     if (!v) return fail(STPI_EUNSUPPORTED, "no compiled kernel for radii (%d, %d)", p->r_s, p->r_t);
     hipStream_t s = (hipStream_t)stream;
     FwdLaunch FL;

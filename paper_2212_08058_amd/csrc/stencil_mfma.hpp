@@ -1,0 +1,298 @@
+// Matrix-core form of the step's two spatial passes (space radius up to 16).
+//
+// A 1D Gaussian pass over a tile is a product with a banded Toeplitz matrix,
+// so both spatial passes of the separable filter (Eq. 3's spatial factor,
+// applied along y then x) run as v_mfma_f32_16x16x32_f16 products. To keep
+// float accuracy, every operand is split into two half-precision parts,
+// a = a_hi + a_lo with a_hi = fp16(a) and a_lo = fp16(a - a_hi) (about 22
+// significant bits), and each product is formed from the three terms that
+// matter: hi*hi + hi*lo + lo*hi (the dropped lo*lo term and the split
+// residuals are below 2^-21 of each product). Products accumulate in float.
+//
+// Range. The staged input is u' = f x_stored scale 2^S, where scale makes the
+// iterate unit and 2^S is chosen on the device from a bound B >= |f x scale|
+// so that |u'| < 2^10; the y-pass output is then below 33 * 2^10 (the taps are
+// <= 1), inside half precision. The output picks up 2^-S in the epilogue's
+// scale, so z is the same as in the plain form. Values far below the largest
+// one lose relative precision (half precision subnormals), but never more
+// than 2^-24 * 2^10 / 2^S in absolute terms.
+//
+// Tile. A workgroup owns TH x TW outputs (multiples of 16) and streams its
+// frames as the plain tile loop does (three-stage pipeline, one barrier per
+// phase, the same t-ring and epilogue; the epilogue's loads are issued at the
+// start of the phase). Per frame:
+//   stage:  u' on the (TH + 32) x (TW + 32) slab around the tile, split into
+//           hi and lo planes stored column-major (U^T[c][k], k = slab row),
+//           each thread writing 8 consecutive rows of one column (16 bytes);
+//   y-pass: for each 16 x 16 block of Y (16 tile rows x 16 slab columns),
+//           Y^T = sum_kb U^T[cols][32 kb .. 32 kb + 32) * Bband_kb, giving
+//           each lane 4 consecutive columns of one row, stored row-major in
+//           hi and lo planes;
+//   x-pass: for each 16 x 16 output block, Out^T = sum_kb Bband_kb^T *
+//           Y^T[32 kb ..], again 4 consecutive columns of one row per lane,
+//           which feed the t-ring (2 RT + 1 register slots) and the epilogue.
+// Both band matrices hold g(32 kb + k - 16 - i) at (row i, col k) in the
+// operand layout, so one set of tap registers serves as the y-pass B operand
+// and the x-pass A operand. Rows and columns of the slab beyond the space
+// radius are staged as zeros; the 16 extra U rows and Y columns that the
+// last K block of the bottom / right blocks reads are zero once for all.
+#pragma once
+
+#include "stencil.hpp"
+
+namespace stpi {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// Halves per LDS line: a multiple of 8 (16-byte rows) with an odd number of
+// 16-byte chunks, so 16-byte accesses of lanes one line apart spread over
+// the banks.
+constexpr int mfma_pitch(int n) {
+    const int p = (n + 7) & ~7;
+    return ((p / 8) % 2 == 1) ? p : p + 8;
+}
+
+template <int TH, int TW, int NTHR>
+struct MfmaGeometry {
+    static constexpr int MB = TH / 16, NB = TW / 16;  // output blocks down / across
+    static constexpr int SR = TH + 32, SC = TW + 32;  // staged slab rows / columns
+    static constexpr int UK = TH + 48;                // U^T column length read by the y-pass
+    static constexpr int UP = mfma_pitch(UK);
+    static constexpr int YW = TW + 48;                // Y row length read by the x-pass
+    static constexpr int YP = mfma_pitch(YW);
+    static constexpr int UPL = SC * UP;               // halves per U plane
+    static constexpr int YPL = TH * YP;               // halves per Y plane
+    static constexpr int UBUF = 2 * UPL;              // hi and lo planes
+    static constexpr int YBUF = 2 * YPL;
+    static constexpr int LDS_HALVES = 2 * UBUF + 2 * YBUF;  // double-buffered
+    static constexpr int LDS_FLOATS = LDS_HALVES / 2;
+    static constexpr int NG = SR / 8;                 // 8-row groups per slab column
+    static constexpr int NITEM = SC * NG;             // staging items
+    static constexpr int IPS = (NITEM + NTHR - 1) / NTHR;
+    static constexpr int NPF = 8 * IPS;               // prefetched elements per thread
+    static constexpr int NWAVE = NTHR / 64;
+    static constexpr int NYB = MB * (NB + 2);         // y-pass blocks
+    static constexpr int NXB = MB * NB;               // x-pass blocks
+    static constexpr int YPW = (NYB + NWAVE - 1) / NWAVE;
+    static constexpr int XPW = NXB / NWAVE;           // x-pass blocks per wavefront
+    static_assert(TH % 16 == 0 && TW % 16 == 0, "tile of whole 16 x 16 blocks");
+    static_assert(NXB % NWAVE == 0, "x-pass blocks must split evenly over the wavefronts");
+    static_assert(NB % XPW == 0, "a wavefront's x-pass blocks lie in one block row");
+    static_assert(LDS_HALVES % 2 == 0 && LDS_HALVES * 2 <= 160 * 1024, "LDS");
+};
+
+// LDS floats of a tile loop kind (instantiates the geometry only for PIPE 3).
+template <int PIPE, int TH, int TW, int NTHR>
+struct MfmaLds {
+    static constexpr int value = 1;
+};
+template <int TH, int TW, int NTHR>
+struct MfmaLds<3, TH, TW, NTHR> {
+    static constexpr int value = MfmaGeometry<TH, TW, NTHR>::LDS_FLOATS;
+};
+
+__device__ __forceinline__ void split_half(float v, _Float16 &hi, _Float16 &lo) {
+    hi = (_Float16)v;
+    lo = (_Float16)(v - (float)hi);
+}
+
+// y-pass of one 16 x 16 block of Y: reads the U^T planes, writes the Y planes.
+template <class G>
+__device__ __forceinline__ void mfma_yblock(const _Float16 *U, _Float16 *Y, int b, int lane,
+                                            const half8_t (&thi)[2], const half8_t (&tlo)[2]) {
+    const int rb = b / (G::NB + 2), cb = b % (G::NB + 2);
+    const int li = lane & 15, lg = lane >> 4;
+    const _Float16 *p = U + (16 * cb + li) * G::UP + 16 * rb + 8 * lg;
+    float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        const half8_t ah = *reinterpret_cast<const half8_t *>(p + 32 * kb);
+        const half8_t al = *reinterpret_cast<const half8_t *>(p + G::UPL + 32 * kb);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, thi[kb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, tlo[kb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], acc, 0, 0, 0);
+    }
+    half4_t h, l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        _Float16 a, c;
+        split_half(acc[j], a, c);
+        h[j] = a;
+        l[j] = c;
+    }
+    _Float16 *q = Y + (16 * rb + li) * G::YP + 16 * cb + 4 * lg;
+    *reinterpret_cast<half4_t *>(q) = h;
+    *reinterpret_cast<half4_t *>(q + G::YPL) = l;
+}
+
+// x-pass of one 16 x 16 output block: 4 consecutive outputs of one row per lane.
+template <class G>
+__device__ __forceinline__ void mfma_xblock(const _Float16 *Y, int b, int lane, const half8_t (&thi)[2],
+                                            const half8_t (&tlo)[2], float (&v)[4]) {
+    const int rb = b / G::NB, ob = b % G::NB;
+    const int li = lane & 15, lg = lane >> 4;
+    const _Float16 *p = Y + (16 * rb + li) * G::YP + 16 * ob + 8 * lg;
+    float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        const half8_t bh = *reinterpret_cast<const half8_t *>(p + 32 * kb);
+        const half8_t bl = *reinterpret_cast<const half8_t *>(p + G::YPL + 32 * kb);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(tlo[kb], bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bl, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = acc[j];
+}
+
+// Streams one tile through frames [t0, t1) (reading [t0 - RT, t1 + RT) clipped
+// to the clip). Op is the forward step's FwdOp; umul = scale * 2^S multiplies
+// f * x at staging and op.scale must be 2^-S. rs is the problem's space
+// radius (slab rows and columns beyond it are not read). lds holds
+// MfmaGeometry::LDS_FLOATS floats; tapl holds the 33 space taps centred at 16.
+template <class CT, int RT, int TH, int TW, int NTHR, class Op>
+__device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &tp, const float *tapl, float umul,
+                                                  int rs, int T, int t0, int t1, int H, int W, int x0, int y0,
+                                                  float *lds, double &d1, double &d2) {
+    using G = MfmaGeometry<TH, TW, NTHR>;
+    constexpr int NPF = G::NPF, IPS = G::IPS, NTS = 2 * RT + 1, XPW = G::XPW;
+    constexpr uint32_t ESZ = Op::ESZ;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    _Float16 *const U0 = reinterpret_cast<_Float16 *>(lds);
+    _Float16 *const Y0 = U0 + 2 * G::UBUF;
+
+    // band taps in the operand layout: lane l, element j of K block kb holds
+    // g(32 kb + 8 (l / 16) + j - 16 - l % 16)
+    half8_t thi[2], tlo[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int d = 32 * kb + 8 * (lane >> 4) + j - 16 - (lane & 15);
+            const float g = (d >= -16 && d <= 16) ? tapl[d + 16] : 0.f;
+            _Float16 h, l;
+            split_half(g, h, l);
+            thi[kb][j] = h;
+            tlo[kb][j] = l;
+        }
+
+    // zero the U^T rows [SR, UK) and the Y columns [SC, YW) of both buffers
+    for (int i = tid; i < 2 * 2 * G::SC * (G::UK - G::SR); i += NTHR) {
+        const int k = i % (G::UK - G::SR), rest = i / (G::UK - G::SR);
+        const int c = rest % G::SC, plane = rest / G::SC;  // plane: buffer * 2 + hi/lo
+        U0[plane * G::UPL + c * G::UP + G::SR + k] = (_Float16)0.f;
+    }
+    for (int i = tid; i < 2 * 2 * TH * (G::YW - G::SC); i += NTHR) {
+        const int k = i % (G::YW - G::SC), rest = i / (G::YW - G::SC);
+        const int r = rest % TH, plane = rest / TH;
+        Y0[plane * G::YPL + r * G::YP + G::SC + k] = (_Float16)0.f;
+    }
+
+    // staging offsets: item m of this thread is slab column c, rows 8 g .. 8 g + 7
+    uint32_t poff[NPF];
+#pragma unroll
+    for (int m = 0; m < IPS; ++m) {
+        const int it = tid + m * NTHR;
+        const int c = it % G::SC, g = it / G::SC;
+        const int gx = x0 - 16 + c;
+        const bool colok = it < G::NITEM && c >= 16 - rs && c < TW + 16 + rs && (unsigned)gx < (unsigned)W;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int r = 8 * g + j;
+            const int gy = y0 - 16 + r;
+            const bool ok = colok && r >= 16 - rs && r < TH + 16 + rs && (unsigned)gy < (unsigned)H;
+            poff[8 * m + j] = ok ? (uint32_t)(gy * W + gx) * ESZ : OOB;
+        }
+    }
+    // output offsets: x-pass block i of this wavefront, row li, columns 4 lg .. 4 lg + 3
+    uint32_t ooff[XPW][4];
+#pragma unroll
+    for (int i = 0; i < XPW; ++i) {
+        const int b = wid * XPW + i;
+        const int rb = b / G::NB, ob = b % G::NB;
+        const int gy = y0 + 16 * rb + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gx = x0 + 16 * ob + 4 * (lane >> 4) + q;
+            ooff[i][q] = (gy < H && gx < W) ? (uint32_t)(gy * W + gx) * ESZ : OOB;
+        }
+    }
+
+    CT acc[NTS][XPW][4];
+#pragma unroll
+    for (int s = 0; s < NTS; ++s)
+#pragma unroll
+        for (int i = 0; i < XPW; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[s][i][q] = CT(0);
+
+    const int ts = t0 - RT > 0 ? t0 - RT : 0;
+    const int te = t1 + RT < T ? t1 + RT : T;
+    const int nin = te - ts;
+    typename Op::template Raw<NPF> pf;
+    op.template fetch<NPF>(ts, poff, pf);
+    typename Op::template OutRaw<XPW, 4> oraw;
+
+    const int nphase = t1 + RT - ts + 2;
+    ring_loop<NTS, -2>(nphase, [&](auto ring_pos, int p) __attribute__((always_inline)) {
+        constexpr int J = decltype(ring_pos)::value;
+        const int tx = p - 2;
+        const int tout = ts + tx - RT;
+        const bool emit = tx >= 0 && tout >= t0;
+        // the epilogue's loads go first: they have the whole phase to arrive
+        if (emit) op.template fetch_out<XPW, 4>(tout, ooff, oraw);
+        if (p < nin) {
+            _Float16 *U = U0 + (p & 1) * G::UBUF;
+#pragma unroll
+            for (int m = 0; m < IPS; ++m) {
+                const int it = tid + m * NTHR;
+                if (G::NITEM % NTHR == 0 || m < IPS - 1 || it < G::NITEM) {
+                    const int c = it % G::SC, g = it / G::SC;
+                    half8_t h, l;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        _Float16 a, b;
+                        split_half(op.template input<NPF>(pf, 8 * m + j) * umul, a, b);
+                        h[j] = a;
+                        l[j] = b;
+                    }
+                    _Float16 *q = U + c * G::UP + 8 * g;
+                    *reinterpret_cast<half8_t *>(q) = h;
+                    *reinterpret_cast<half8_t *>(q + G::UPL) = l;
+                }
+            }
+        }
+        if (p + 1 < nin) op.template fetch<NPF>(ts + p + 1, poff, pf);
+        if (p >= 1 && p - 1 < nin) {
+            const _Float16 *U = U0 + ((p - 1) & 1) * G::UBUF;
+            _Float16 *Y = Y0 + ((p - 1) & 1) * G::YBUF;
+#pragma unroll
+            for (int m = 0; m < G::YPW; ++m) {
+                const int b = wid + m * G::NWAVE;
+                if (G::NYB % G::NWAVE == 0 || b < G::NYB) mfma_yblock<G>(U, Y, b, lane, thi, tlo);
+            }
+        }
+        if (tx >= 0) {
+            CT v[XPW][4];
+            const bool live = tx < nin;
+            if (live) {
+                const _Float16 *Y = Y0 + (tx & 1) * G::YBUF;
+#pragma unroll
+                for (int i = 0; i < XPW; ++i) mfma_xblock<G>(Y, wid * XPW + i, lane, thi, tlo, v[i]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < XPW; ++i)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[i][q] = CT(0);
+            }
+            ring_step<J, CT, RT, XPW, 4>(acc, v, tp, live, emit, tout, op, ooff, oraw, d1, d2);
+        }
+        __syncthreads();
+    });
+}
+
+}  // namespace stpi

@@ -1,0 +1,230 @@
+"""Matrix-core step variants (both spatial passes as banded products on
+v_mfma_f32_16x16x32_f16, operands split into two half-precision parts)
+against the FP64 oracle: every space radius they serve, ragged and
+degenerate shapes, values far from 1 and of both signs, the single-step
+scale, the iteration chain and bfloat16 storage. Same bars as the plain
+variants: FP32 per step relative L2 <= 1e-5, BF16 storage <= 2^-8."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import Kernel as OK
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2212_08058_amd as P
+    return P
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def OKf(k):
+    return OK(float(np.float32(k.sigma_s)), float(np.float32(k.sigma_t)), k.r_s, k.r_t)
+
+
+def mfma_variants(dtype_code):
+    from paper_2212_08058_amd import _native as N
+    out = []
+    for i in range(N.lib.stpi_variant_count(dtype_code)):
+        info = (ctypes.c_int * 9)()
+        assert N.lib.stpi_variant_info(dtype_code, i, info) == 0
+        if info[8] == 3:
+            out.append((i, list(info)))
+    return out
+
+
+class forced:
+    def __init__(self, i):
+        from paper_2212_08058_amd import _native as N
+        self.N, self.i = N, i
+
+    def __enter__(self):
+        assert self.N.lib.stpi_set_variant(self.i) == 0
+
+    def __exit__(self, *a):
+        self.N.lib.stpi_set_variant(-1)
+
+
+def test_variants_are_compiled():
+    from paper_2212_08058_amd import _native as N
+    v32 = mfma_variants(N.STPI_F32)
+    assert v32 and all(info[0] == 16 for _, info in v32)
+    assert mfma_variants(N.STPI_BF16)
+
+
+CASES = [
+    ((5, 37, 70), (2.0, 1.0, 4, 2)),       # ragged, one tile
+    ((13, 40, 131), (4.0, 1.5, 8, 3)),     # three tiles across
+    ((12, 35, 150), (5.0, 2.0, 15, 5)),
+    ((7, 70, 200), (10.0, 3.0, 16, 5)),    # the largest space radius, two tile rows
+    ((20, 64, 64), (5.0, 2.0, 15, 5)),     # exactly one tile
+    ((2, 129, 67), (3.0, 1.0, 6, 3)),      # ragged bottom tile row
+    ((3, 17, 19), (1.3, 0.7, 1, 1)),
+    ((1, 1, 1), (1.0, 1.0, 2, 1)),         # single voxel
+    ((1, 30, 1), (2.0, 1.0, 4, 2)),        # single column
+    ((9, 1, 40), (2.0, 1.0, 4, 2)),        # single row
+    ((3, 18, 20), (2.0, 1.0, 0, 0)),       # no neighbours: A = diag(f^2)
+    ((16, 33, 47), (3.0, 1.0, 5, 0)),      # no temporal neighbours
+]
+
+
+@pytest.mark.parametrize("shape,kp", CASES)
+def test_step_matches_oracle(P, shape, kp):
+    from paper_2212_08058_amd import _native as N
+    kern = P.Kernel(*kp)
+    rng = np.random.default_rng(sum(shape))
+    f = rng.uniform(0.05, 1.0, shape).astype(np.float32)
+    x = rng.uniform(0.0, 1.0, shape).astype(np.float32)
+    ref = 0.7 * oracle.apply(f.astype(np.float64), x.astype(np.float64), OKf(kern))
+    fd, xd = torch.from_numpy(f).to(DEV), torch.from_numpy(x).to(DEV)
+    ran = 0
+    for i, info in mfma_variants(N.STPI_F32):
+        if info[1] < kern.r_t:
+            continue
+        with forced(i):
+            z, sums = P.step(fd, xd, kern, x_scale=0.7)
+            torch.cuda.synchronize()
+        zz = z.double().cpu().numpy()
+        err = rel_l2(zz, ref)
+        print(shape, kp, "variant", i, info[:5], f"rel L2 {err:.3e}")
+        assert err <= 1e-5, (i, err)
+        s = sums.cpu().numpy()
+        assert abs(s[0] - np.sum(zz * zz)) <= 1e-12 * np.sum(zz * zz)
+        ran += 1
+    assert ran
+
+
+@pytest.mark.parametrize("kind", ["tiny", "huge", "signed", "decades"])
+def test_value_ranges(P, kind):
+    """The half-precision operands are scaled by a power of two from max |f x|:
+    results keep float accuracy for inputs far from 1, of either sign, or
+    spread over many decades."""
+    from paper_2212_08058_amd import _native as N
+    kern = P.Kernel(5.0, 2.0, 15, 5)
+    shape = (10, 50, 90)
+    rng = np.random.default_rng(7)
+    f = rng.uniform(0.05, 1.0, shape)
+    x = rng.uniform(0.0, 1.0, shape)
+    if kind == "tiny":
+        f, x = f * 1e-12, x * 1e-9
+    elif kind == "huge":
+        f, x = f * 1e8, x * 1e11
+    elif kind == "signed":
+        f = rng.uniform(-1.0, 1.0, shape)
+        x = rng.uniform(-1.0, 1.0, shape)
+    else:
+        f = 10.0 ** rng.uniform(-7, 0, shape)
+    f, x = f.astype(np.float32), x.astype(np.float32)
+    scale = {"tiny": 1e6, "huge": 1e-9}.get(kind, 1.0)
+    ref = scale * oracle.apply(f.astype(np.float64), x.astype(np.float64), OKf(kern))
+    fd, xd = torch.from_numpy(f).to(DEV), torch.from_numpy(x).to(DEV)
+    for i, info in mfma_variants(N.STPI_F32):
+        if info[1] < kern.r_t:
+            continue
+        with forced(i):
+            z, _ = P.step(fd, xd, kern, x_scale=scale)
+            torch.cuda.synchronize()
+        err = rel_l2(z.double().cpu().numpy(), ref)
+        print(kind, "variant", i, info[:5], f"rel L2 {err:.3e}")
+        assert err <= 1e-5, (kind, i, err)
+
+
+def test_iteration_chain_matches_oracle(P):
+    from paper_2212_08058_amd import _native as N
+    c = synth.CONFIGS["small"]
+    f, _ = synth.blob_clip(c["T"], 96, 150, 3, 0)
+    kern = P.Kernel(5.0, 2.0, 15, 5)
+    xr, info = oracle.iterate(f, OKf(kern), iters=10)
+    fd = torch.from_numpy(f).to(DEV)
+    for i, vi in mfma_variants(N.STPI_F32):
+        if vi[1] < kern.r_t:
+            continue
+        with forced(i):
+            x, r = P.power_iterate(fd, kern, iters=10)
+            torch.cuda.synchronize()
+        err = rel_l2(x.double().cpu().numpy(), xr)
+        print("chain variant", i, vi[:5], f"rel L2 {err:.3e}", r["lambda_"], info.lambdas[-1])
+        assert r["iters"] == 10 and err <= 1e-5
+        assert abs(r["lambda_"] - info.lambdas[-1]) <= 1e-5 * info.lambdas[-1]
+
+
+def test_tolerance_run_converges_to_oracle(P):
+    from paper_2212_08058_amd import _native as N
+    f, _ = synth.blob_clip(8, 64, 112, 3, 4)
+    kern = P.Kernel(2.0, 1.0, 4, 2)
+    xr, info = oracle.iterate(f, OKf(kern), tol=1e-4, cap=400)
+    fd = torch.from_numpy(f).to(DEV)
+    i, vi = mfma_variants(N.STPI_F32)[0]
+    with forced(i):
+        x, r = P.power_iterate(fd, kern, tol=1e-4, max_iters=400)
+        torch.cuda.synchronize()
+    cosd = 1.0 - float(np.sum(x.double().cpu().numpy() * xr))
+    print("tolerance run", r["iters"], info.iters, f"cos distance {cosd:.3e}")
+    assert r["converged"] and abs(r["iters"] - info.iters) <= 2 and cosd <= 1e-3
+
+
+def test_bf16_storage(P):
+    from paper_2212_08058_amd import _native as N
+    kern = P.Kernel(5.0, 2.0, 15, 5)
+    shape = (9, 70, 133)
+    rng = np.random.default_rng(11)
+    f = torch.from_numpy(rng.uniform(0.05, 1.0, shape).astype(np.float32)).to(torch.bfloat16)
+    x = torch.from_numpy(rng.uniform(0.0, 1.0, shape).astype(np.float32)).to(torch.bfloat16)
+    ref = oracle.apply(f.double().numpy(), x.double().numpy(), OKf(kern))
+    fd, xd = f.to(DEV), x.to(DEV)
+    for i, vi in mfma_variants(N.STPI_BF16):
+        if vi[1] < kern.r_t:
+            continue
+        with forced(i):
+            z, _ = P.step(fd, xd, kern)
+            torch.cuda.synchronize()
+        err = rel_l2(z.double().cpu().numpy(), ref)
+        print("bf16 variant", i, vi[:5], f"rel L2 {err:.3e}")
+        assert err <= 2.0 ** -8
+
+
+def test_matches_plain_variant_at_full_frame(P):
+    """At 16 x 480 x 854 the matrix-core and the plain variant agree to float
+    accuracy everywhere (the oracle is sampled by the frame-segment test)."""
+    from paper_2212_08058_amd import _native as N
+    kern = P.Kernel(5.0, 2.0, 15, 5)
+    f, _ = synth.blob_clip(16, 480, 854, 5, 3)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0.0, 1.0, f.shape).astype(np.float32)
+    fd, xd = torch.from_numpy(f).to(DEV), torch.from_numpy(x).to(DEV)
+    plain = None
+    for i in range(N.lib.stpi_variant_count(N.STPI_F32)):
+        info = (ctypes.c_int * 9)()
+        N.lib.stpi_variant_info(N.STPI_F32, i, info)
+        if info[0] == 15 and info[1] == 5 and info[8] == 0:
+            plain = i
+            break
+    assert plain is not None
+    with forced(plain):
+        zp, sp = P.step(fd, xd, kern)
+        torch.cuda.synchronize()
+    idx = np.random.default_rng(5).integers(0, f.size, 400)
+    ref = oracle.apply_at(f, x, OKf(kern), idx)
+    for i, vi in mfma_variants(N.STPI_F32):
+        if vi[1] < kern.r_t:
+            continue
+        with forced(i):
+            z, s = P.step(fd, xd, kern)
+            torch.cuda.synchronize()
+        d = rel_l2(z.double().cpu().numpy(), zp.double().cpu().numpy())
+        e = rel_l2(z.double().reshape(-1)[torch.from_numpy(idx).to(DEV)].cpu().numpy(), ref)
+        print("full frame variant", i, vi[:5], f"vs plain {d:.3e}, sampled vs oracle {e:.3e}")
+        assert d <= 1e-5 and e <= 1e-5
+        assert abs(float(s[0]) / float(sp[0]) - 1.0) <= 2e-5
