@@ -124,7 +124,10 @@ __global__ void bound_kernel(size_t n, const ST *f, const ST *x, uint32_t *out) 
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < AUX_THREADS / 64; ++w) r = red[w] > r ? red[w] : r;
-        atomicMax(out, __float_as_uint(r));
+        // only workgroups that raise the maximum touch it: thousands of
+        // atomics on one word would serialise
+        const uint32_t cur = __hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__float_as_uint(r) > cur) atomicMax(out, __float_as_uint(r));
     }
 }
 

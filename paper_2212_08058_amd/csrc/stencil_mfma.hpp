@@ -93,6 +93,15 @@ struct MfmaLds<3, TH, TW, NTHR> {
     static constexpr int value = MfmaGeometry<TH, TW, NTHR>::LDS_FLOATS;
 };
 
+// Staging item m of thread tid. When the items do not fill the last round,
+// that round goes to the highest threads: the y-pass's extra blocks go to the
+// lowest wavefronts, so no wavefront carries both.
+template <class G, int NTHR>
+__device__ __forceinline__ int stage_item(int tid, int m) {
+    if (G::NITEM % NTHR != 0 && m == G::IPS - 1) return (G::IPS - 1) * NTHR + (NTHR - 1 - tid);
+    return tid + m * NTHR;
+}
+
 __device__ __forceinline__ void split_half(float v, _Float16 &hi, _Float16 &lo) {
     hi = (_Float16)v;
     lo = (_Float16)(v - (float)hi);
@@ -105,15 +114,17 @@ __device__ __forceinline__ void mfma_yblock(const _Float16 *U, _Float16 *Y, int 
     const int rb = b / (G::NB + 2), cb = b % (G::NB + 2);
     const int li = lane & 15, lg = lane >> 4;
     const _Float16 *p = U + (16 * cb + li) * G::UP + 16 * rb + 8 * lg;
-    float4_t acc = {0.f, 0.f, 0.f, 0.f};
+    // one accumulator per K half: two dependency chains of three products
+    float4_t ac[2];
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
         const half8_t ah = *reinterpret_cast<const half8_t *>(p + 32 * kb);
         const half8_t al = *reinterpret_cast<const half8_t *>(p + G::UPL + 32 * kb);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, thi[kb], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, tlo[kb], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], acc, 0, 0, 0);
+        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, thi[kb], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, tlo[kb], ac[kb], 0, 0, 0);
+        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], ac[kb], 0, 0, 0);
     }
+    const float4_t acc = ac[0] + ac[1];
     half4_t h, l;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -134,17 +145,17 @@ __device__ __forceinline__ void mfma_xblock(const _Float16 *Y, int b, int lane, 
     const int rb = b / G::NB, ob = b % G::NB;
     const int li = lane & 15, lg = lane >> 4;
     const _Float16 *p = Y + (16 * rb + li) * G::YP + 16 * ob + 8 * lg;
-    float4_t acc = {0.f, 0.f, 0.f, 0.f};
+    float4_t ac[2];
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
         const half8_t bh = *reinterpret_cast<const half8_t *>(p + 32 * kb);
         const half8_t bl = *reinterpret_cast<const half8_t *>(p + G::YPL + 32 * kb);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(tlo[kb], bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bl, acc, 0, 0, 0);
+        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bh, float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tlo[kb], bh, ac[kb], 0, 0, 0);
+        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bl, ac[kb], 0, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = acc[j];
+    for (int j = 0; j < 4; ++j) v[j] = ac[0][j] + ac[1][j];
 }
 
 // Streams one tile through frames [t0, t1) (reading [t0 - RT, t1 + RT) clipped
@@ -196,7 +207,7 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
     uint32_t poff[NPF];
 #pragma unroll
     for (int m = 0; m < IPS; ++m) {
-        const int it = tid + m * NTHR;
+        const int it = stage_item<G, NTHR>(tid, m);
         const int c = it % G::SC, g = it / G::SC;
         const int gx = x0 - 16 + c;
         const bool colok = it < G::NITEM && c >= 16 - rs && c < TW + 16 + rs && (unsigned)gx < (unsigned)W;
@@ -249,7 +260,7 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
             _Float16 *U = U0 + (p & 1) * G::UBUF;
 #pragma unroll
             for (int m = 0; m < IPS; ++m) {
-                const int it = tid + m * NTHR;
+                const int it = stage_item<G, NTHR>(tid, m);
                 if (G::NITEM % NTHR == 0 || m < IPS - 1 || it < G::NITEM) {
                     const int c = it % G::SC, g = it / G::SC;
                     half8_t h, l;
