@@ -70,7 +70,10 @@ typedef struct stpi_problem {
 /* Outcome of an iteration (host memory). residual is ||x_k - x_{k-1}||_2
  * between the last two unit iterates; lambda = ||A x_{k-1}|| (tends to the
  * principal eigenvalue); rayleigh = <x_{k-1}, A x_{k-1}>. flags: bit 0 zero
- * norm, bit 1 non-finite. Not converging is not an error (converged = 0). */
+ * norm, bit 1 non-finite, bit 2 stopped by the init = 2 rise check. Not
+ * converging is not an error (converged = 0).
+ * first_residuals: the residuals after the first and second applications of
+ * this call (0 where not reached), e.g. for a warm start's fallback rule. */
 typedef struct stpi_result {
     int32_t iters;
     int32_t converged;
@@ -79,6 +82,7 @@ typedef struct stpi_result {
     double residual;
     double lambda;
     double rayleigh;
+    double first_residuals[2];
 } stpi_result;
 
 /* Message for a status code; never NULL. */
@@ -104,11 +108,17 @@ int stpi_step(const stpi_problem *p, const void *f, const void *x, double x_scal
 /* Power iteration (Eq. 4 + Eq. 8, outer loop of Alg. 1).
  * x (device, in/out): with init = 1 it is overwritten by the uniform start
  * 1/sqrt(N); with init = 0 it holds the caller's start (normalised first,
- * must not be zero). On return x holds the last unit iterate.
+ * must not be zero); init = 2 is init = 0 plus the warm-start check: the run
+ * stops after its second application if that residual is above the first
+ * (flags bit 2 set, status OK; the caller restarts from uniform). On return
+ * x holds the last unit iterate.
  * tol > 0: stop at the first k with ||x_k - x_{k-1}|| < tol, or after
  * max_iters applications; tol <= 0: exactly max_iters applications.
  * The iteration runs on the device without host round trips; the call
- * synchronises `stream` once at the end and fills *out (host). */
+ * synchronises `stream` once at the end and fills *out (host). out may be
+ * NULL: the call then returns as soon as the chain is enqueued (tolerance
+ * runs of more than 32 steps still wait on the stream for their stop checks),
+ * and no status is read back. */
 int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int max_iters, double tol,
                  void *ws, size_t ws_bytes, stpi_result *out, void *stream);
 
@@ -120,7 +130,9 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
 
 /* Number of compiled variants for dtype (0 for an unknown dtype). */
 int stpi_variant_count(int dtype);
-/* info[0..8] = RS, RT, TH, TW, NTHR, RY, QX, OCC (min waves per SIMD), PIPE (1: pipelined tile loop) of variant `index`; STPI_EINVAL if out of range. */
+/* info[0..8] = RS, RT, TH, TW, NTHR, RY, QX, OCC (min waves per SIMD), PIPE of
+ * variant `index` (tile loop: 0 plain, 1 software-pipelined, 2 straight-line,
+ * 3 matrix-core spatial passes); STPI_EINVAL if out of range. */
 int stpi_variant_info(int dtype, int index, int32_t info[9]);
 /* Launch shape the step of problem p uses with variant `variant` (-1: the
  * variant stpi_step would choose): info[0] = variant index, info[1] = tiles

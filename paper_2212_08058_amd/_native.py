@@ -40,11 +40,12 @@ class Clip(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("status", ctypes.c_int32), ("residual", ctypes.c_double), ("lambda_", ctypes.c_double),
-                ("rayleigh", ctypes.c_double)]
+                ("rayleigh", ctypes.c_double), ("first_residuals", ctypes.c_double * 2)]
 
     def as_dict(self):
         return dict(iters=self.iters, converged=bool(self.converged), flags=self.flags, status=self.status,
-                    residual=self.residual, lambda_=self.lambda_, rayleigh=self.rayleigh)
+                    residual=self.residual, lambda_=self.lambda_, rayleigh=self.rayleigh,
+                    r1=self.first_residuals[0], r2=self.first_residuals[1])
 
 
 # (name, restype, argtypes); pointers to device memory and streams are void*.

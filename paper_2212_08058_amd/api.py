@@ -87,12 +87,16 @@ def step(f: torch.Tensor, x: torch.Tensor, k: Kernel, x_scale: float = 1.0, z: t
 
 def power_iterate(f: torch.Tensor, k: Kernel, iters: int | None = None, tol: float | None = None,
                   max_iters: int = 1000, x0: torch.Tensor | None = None, x: torch.Tensor | None = None,
-                  ws: torch.Tensor | None = None, stream=None, check: bool = True):
+                  ws: torch.Tensor | None = None, stream=None, check: bool = True, wait: bool = True,
+                  rise_check: bool = False):
     """Power iteration x <- A x / ||A x|| (stpi_iterate).
 
     iters: exact number of applications; otherwise stop when
     ||x_k - x_{k-1}|| < tol or after max_iters. x0 (optional) is the start
-    vector (uniform 1/sqrt(N) otherwise). Returns (x, result dict).
+    vector (uniform 1/sqrt(N) otherwise). Returns (x, result dict); with
+    wait=False the chain is only enqueued on `stream` and the result is None.
+    rise_check (with x0): stop after the second application if its residual
+    is above the first (result flags bit 2), the warm-start fallback test.
     """
     _check_volume("f", f)
     if iters is not None:
@@ -109,14 +113,16 @@ def power_iterate(f: torch.Tensor, k: Kernel, iters: int | None = None, tol: flo
         _check_volume("x0", x0, f.shape, f.dtype)
         if x0.data_ptr() != x.data_ptr():
             x.copy_(x0)
-        init = 0
+        init = 2 if rise_check else 0
     ws = _workspace(f.shape, k, f.dtype, f.device, ws)
     p = problem_for(f.shape, k, f.dtype)
     res = N.Result()
     rc = N.lib.stpi_iterate(ctypes.byref(p), f.data_ptr(), x.data_ptr(), init, n_iter, t, ws.data_ptr(),
-                            ws.numel(), ctypes.byref(res), _stream_ptr(stream))
-    if check:
+                            ws.numel(), ctypes.byref(res) if wait else None, _stream_ptr(stream))
+    if check or not wait:
         N.check(rc)
+    if not wait:
+        return x, None
     out = res.as_dict()
     out["rc"] = rc
     return x, out

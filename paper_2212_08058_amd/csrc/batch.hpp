@@ -137,6 +137,7 @@ __device__ __forceinline__ void finalize_state(DevState *s, double p1, double p2
         s->scale = 1.0 / nz;
         s->cur ^= 1;
         s->iters += 1;
+        if (s->iters <= 2) s->first_res[s->iters - 1] = s->residual;
         if (s->tol > 0.0 && s->residual < s->tol) {
             s->converged = 1;
             stop = true;

@@ -27,6 +27,10 @@ __global__ void batch_init_kernel(DevState *states, const ClipDesc *clips, int n
     s->flags = 0u;
     s->max_iters = max_iters;
     s->converged = 0;
+    s->arrive = 0u;
+    s->ubound = 0u;
+    s->first_res[0] = s->first_res[1] = 0.0;
+    s->check_rise = 0;
 }
 
 __global__ void batch_state_from_norm_kernel(const double *partials, DevState *states, BatchCtl *ctl) {

@@ -5,7 +5,7 @@
 
 namespace stpi {
 
-__global__ void state_init_kernel(DevState *s, double scale, double tol, int max_iters) {
+__global__ void state_init_kernel(DevState *s, double scale, double tol, int max_iters, int check_rise) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         s->scale = scale;
         s->residual = 0.0;
@@ -20,6 +20,8 @@ __global__ void state_init_kernel(DevState *s, double scale, double tol, int max
         s->converged = 0;
         s->arrive = 0u;
         s->ubound = 0u;
+        s->first_res[0] = s->first_res[1] = 0.0;
+        s->check_rise = check_rise;
     }
 }
 
@@ -184,8 +186,8 @@ hipError_t launch_adamw(int dtype, int64_t n, void *w, const void *g, void *m, v
     return hipGetLastError();
 }
 
-hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, hipStream_t st) {
-    hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, st, s, scale, tol, max_iters);
+hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, int check_rise, hipStream_t st) {
+    hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, st, s, scale, tol, max_iters, check_rise);
     return hipGetLastError();
 }
 

@@ -58,10 +58,16 @@ struct DevState {
     int32_t converged;
     uint32_t arrive;   // workgroups of the running step that stored their partial sums
     uint32_t ubound;   // float bits of max |f| (matrix-core step variants)
+    double first_res[2];  // residuals after the chain's first and second steps
+    int32_t check_rise;   // 1: stop after the second step if its residual is above the first's
+    int32_t pad_;
 };
+
+static_assert(sizeof(DevState) <= 256, "the iteration state lives in a 256-byte workspace slot");
 
 constexpr uint32_t FLAG_ZERO = 1u;
 constexpr uint32_t FLAG_NONFINITE = 2u;
+constexpr uint32_t FLAG_ROSE = 4u;  // stopped by the check_rise rule (not an error)
 
 // Workgroup size and summation order of the per-step reduction of partial
 // sums: thread i < FINAL_THREADS adds entries i, i + FINAL_THREADS, ... in
@@ -91,6 +97,12 @@ __device__ __forceinline__ void step_finalize(DevState *s, double p1, double p2)
     s->scale = 1.0 / nz;
     s->cur ^= 1;
     s->iters += 1;
+    if (s->iters <= 2) s->first_res[s->iters - 1] = s->residual;
+    if (s->check_rise && s->iters == 2 && !(s->first_res[1] <= s->first_res[0])) {
+        s->flags |= FLAG_ROSE;
+        s->done = 1;
+        return;
+    }
     if (s->tol > 0.0 && s->residual < s->tol) {
         s->converged = 1;
         s->done = 1;

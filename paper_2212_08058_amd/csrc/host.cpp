@@ -2,6 +2,7 @@
 // workspace layout and the C ABI declared in include/stpi.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -134,16 +135,24 @@ static int device_cus() {
 // Frame segments per tile. When a clip has fewer tiles than the chip holds
 // resident workgroups, each tile's frames are split so that more workgroups
 // (with independent barriers) share every CU. A segment re-reads and
-// re-filters RT input frames on each inner side, so segments are kept at
-// least 4 RT frames long and their count at most STPI_NSEG_MAX.
+// re-filters RT input frames on each inner side, so segments are normally at
+// least 4 RT frames long and at most 4 per tile. A launch that would still
+// fill less than half of the resident slots (a small clip, e.g. a coarse
+// level of a two-level start) is bound by the frame-after-frame latency of
+// its few workgroups, not by work: there segments may be as short as 2 RT
+// frames and up to STPI_NSEG_MAX per tile.
 int segments_for(const Variant &v, const stpi_problem *p) {
     const int tiles = tiles_for(v, p);
     const int resident = device_cus() * v.blocks_per_cu();
-    int nseg = resident / tiles;
-    const int by_len = p->T / (4 * (v.RT > 0 ? v.RT : 1));
-    if (nseg > by_len) nseg = by_len;
-    if (nseg > STPI_NSEG_MAX) nseg = STPI_NSEG_MAX;
-    return nseg > 1 ? nseg : 1;
+    const int rt = v.RT > 0 ? v.RT : 1;
+    const int fit = resident / tiles;
+    int nseg = std::min(std::min(fit, p->T / (4 * rt)), 4);
+    if (nseg < 1) nseg = 1;
+    if ((long)tiles * nseg * 2 <= resident) {
+        const int small = std::min(std::min(fit, p->T / (2 * rt)), STPI_NSEG_MAX);
+        if (small > nseg) nseg = small;
+    }
+    return nseg;
 }
 
 int grid_blocks(const Variant &v, const stpi_problem *p) { return tiles_for(v, p) * segments_for(v, p); }
@@ -201,6 +210,7 @@ struct GraphKey {
 struct GraphEntry {
     GraphKey key;
     hipGraphExec_t exec;
+    hipEvent_t launched;  // recorded after every launch: eviction waits for it
     unsigned long long last_use;
 };
 static std::mutex g_graph_mu;
@@ -256,19 +266,27 @@ int enqueue_chain_part(const ChainArgs &a, int part, hipStream_t s) {
 }
 
 // Launches the cached graph for key, capturing `enqueue` into a new one on a miss.
+// A graph may still be queued when its entry is evicted (callers need not
+// synchronise between calls), so every launch records the entry's event and
+// eviction waits for it before destroying the executable graph.
 template <class F>
 int launch_cached_graph(const GraphKey &key, F &&enqueue, hipStream_t s) {
     hipGraphExec_t exec = nullptr;
+    hipEvent_t launched = nullptr;
+    hipError_t e;
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
         for (auto &g : g_graphs)
             if (g.key == key) {
                 exec = g.exec;
+                launched = g.launched;
                 g.last_use = ++g_graph_clock;
-                break;
+                // launch under the lock: no other thread can evict the entry in between
+                if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+                if ((e = hipEventRecord(launched, s)) != hipSuccess) return hip_fail(e, "graph event");
+                return STPI_OK;
             }
     }
-    hipError_t e;
     if (!exec) {
         if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "begin capture");
@@ -283,17 +301,24 @@ int launch_cached_graph(const GraphKey &key, F &&enqueue, hipStream_t s) {
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+        if ((e = hipEventCreateWithFlags(&launched, hipEventDisableTiming)) != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            return hip_fail(e, "graph event");
+        }
         std::lock_guard<std::mutex> lk(g_graph_mu);
         if (g_graphs.size() >= GRAPH_CACHE_MAX) {
             size_t old = 0;
             for (size_t i = 1; i < g_graphs.size(); ++i)
                 if (g_graphs[i].last_use < g_graphs[old].last_use) old = i;
+            (void)hipEventSynchronize(g_graphs[old].launched);
             (void)hipGraphExecDestroy(g_graphs[old].exec);
+            (void)hipEventDestroy(g_graphs[old].launched);
             g_graphs.erase(g_graphs.begin() + old);
         }
-        g_graphs.push_back(GraphEntry{key, exec, ++g_graph_clock});
+        g_graphs.push_back(GraphEntry{key, exec, launched, ++g_graph_clock});
+        if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+        if ((e = hipEventRecord(launched, s)) != hipSuccess) return hip_fail(e, "graph event");
     }
-    if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
     return STPI_OK;
 }
 
@@ -392,16 +417,16 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
     clear_error();
     int rc = validate_problem(p);
     if (rc) return rc;
-    if (!f || !x || !out) return fail(STPI_EINVAL, "NULL buffer or result");
+    if (!f || !x) return fail(STPI_EINVAL, "NULL buffer");
     if (f == x) return fail(STPI_EINVAL, "x must not alias f");
     if (max_iters < 0) return fail(STPI_EINVAL, "max_iters must be >= 0");
-    if (init != 0 && init != 1) return fail(STPI_EINVAL, "init must be 0 (use x) or 1 (uniform)");
+    if (init < 0 || init > 2) return fail(STPI_EINVAL, "init must be 0 (use x), 1 (uniform) or 2 (use x, rise check)");
     if (!std::isfinite(tol)) return fail(STPI_EINVAL, "tol must be finite");
     const WsLayout L = layout_for(p);
     if (!ws || ws_bytes < L.total) return fail(STPI_EWORKSPACE, "workspace needs %zu bytes", L.total);
     const Variant *v = choose_variant(p, forced_variant());
     if (!v) return fail(STPI_EUNSUPPORTED, "no compiled kernel for radii (%d, %d)", p->r_s, p->r_t);
-    std::memset(out, 0, sizeof(*out));
+    if (out) std::memset(out, 0, sizeof(*out));
     hipStream_t s = (hipStream_t)stream;
     const DtypeOps *ops = ops_for(p->dtype);
     const size_t N = (size_t)p->T * p->H * p->W;
@@ -452,6 +477,7 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
         }
         if ((rc = run(CHAIN_TAIL))) return rc;
     }
+    if (!out) return STPI_OK;
 
     DevState hs;
     hipError_t e = hipMemcpyAsync(&hs, state, sizeof(hs), hipMemcpyDeviceToHost, s);
@@ -464,6 +490,8 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
     out->residual = hs.residual;
     out->lambda = hs.lambda;
     out->rayleigh = hs.rayleigh;
+    out->first_residuals[0] = hs.first_res[0];
+    out->first_residuals[1] = hs.first_res[1];
     out->status = STPI_OK;
     if (hs.flags & FLAG_NONFINITE) out->status = STPI_ENONFINITE;
     else if (hs.flags & FLAG_ZERO) out->status = STPI_EZERO_NORM;
@@ -578,10 +606,11 @@ int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevS
     hipError_t e;
     if (init == 1) {
         if ((e = ops->fill_ones(x, N, s)) != hipSuccess) return hip_fail(e, "fill");
-        if ((e = launch_state_init(state, 1.0 / std::sqrt((double)N), tol, max_iters, s)) != hipSuccess)
+        if ((e = launch_state_init(state, 1.0 / std::sqrt((double)N), tol, max_iters, 0, s)) != hipSuccess)
             return hip_fail(e, "init");
     } else {
-        if ((e = launch_state_init(state, 1.0, tol, max_iters, s)) != hipSuccess) return hip_fail(e, "init");
+        if ((e = launch_state_init(state, 1.0, tol, max_iters, init == 2 ? 1 : 0, s)) != hipSuccess)
+            return hip_fail(e, "init");
         if ((e = ops->sumsq(x, N, partials, s)) != hipSuccess) return hip_fail(e, "norm");
         if ((e = launch_state_from_norm(partials, NORM_BLOCKS_HOST, state, s)) != hipSuccess)
             return hip_fail(e, "init norm");

@@ -28,6 +28,7 @@ struct stpi_plan {
         hipStream_t s;
         int part;
         hipGraphExec_t exec;
+        hipEvent_t launched;  // recorded after every launch: eviction waits for it
     };
     stpi::BatchCtl *poll = nullptr;  // pinned copy of the chain counters (stop-flag poll)
     hipEvent_t poll_ev = nullptr;
@@ -269,10 +270,13 @@ int stpi_batch_iterate(stpi_plan *plan, const void *f, void *x, int init, int ma
     auto run = [&](int part) -> int {
         if (s == nullptr) return enqueue_batch(plan, f, x, ws, init, max_iters, tol, s, part);
         hipGraphExec_t exec = nullptr;
+        hipEvent_t launched = nullptr;
         for (auto &g : plan->graphs)
             if (g.f == f && g.x == x && g.ws == ws && g.init == init && g.max_iters == max_iters && g.tol == tol &&
-                g.s == s && g.part == part)
+                g.s == s && g.part == part) {
                 exec = g.exec;
+                launched = g.launched;
+            }
         hipError_t e;
         if (!exec) {
             if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
@@ -288,13 +292,21 @@ int stpi_batch_iterate(stpi_plan *plan, const void *f, void *x, int init, int ma
             e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            if ((e = hipEventCreateWithFlags(&launched, hipEventDisableTiming)) != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                return hip_fail(e, "graph event");
+            }
             if (plan->graphs.size() >= 16) {
+                // the oldest graph may still be queued: wait for its last launch
+                (void)hipEventSynchronize(plan->graphs.front().launched);
                 (void)hipGraphExecDestroy(plan->graphs.front().exec);
+                (void)hipEventDestroy(plan->graphs.front().launched);
                 plan->graphs.erase(plan->graphs.begin());
             }
-            plan->graphs.push_back({f, x, ws, init, max_iters, tol, s, part, exec});
+            plan->graphs.push_back({f, x, ws, init, max_iters, tol, s, part, exec, launched});
         }
         if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+        if ((e = hipEventRecord(launched, s)) != hipSuccess) return hip_fail(e, "graph event");
         return STPI_OK;
     };
     // Long tolerance runs replay CHAIN_CHUNK steps at a time and stop once
@@ -334,6 +346,8 @@ int stpi_batch_iterate(stpi_plan *plan, const void *f, void *x, int init, int ma
         r.residual = hs[i].residual;
         r.lambda = hs[i].lambda;
         r.rayleigh = hs[i].rayleigh;
+        r.first_residuals[0] = hs[i].first_res[0];
+        r.first_residuals[1] = hs[i].first_res[1];
         r.status = (hs[i].flags & FLAG_NONFINITE) ? STPI_ENONFINITE : (hs[i].flags & FLAG_ZERO) ? STPI_EZERO_NORM : 0;
         if (r.status && !worst) worst = r.status;
     }
@@ -343,7 +357,11 @@ int stpi_batch_iterate(stpi_plan *plan, const void *f, void *x, int init, int ma
 
 void stpi_plan_destroy(stpi_plan *plan) {
     if (!plan) return;
-    for (auto &g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto &g : plan->graphs) {
+        (void)hipEventSynchronize(g.launched);
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipEventDestroy(g.launched);
+    }
     if (plan->poll) (void)hipHostFree(plan->poll);
     if (plan->poll_ev) (void)hipEventDestroy(plan->poll_ev);
     if (plan->d_clips) (void)hipFree(plan->d_clips);

@@ -30,7 +30,7 @@ void make_taps(const stpi_problem *p, double *gs, double *gt);
 const Variant *choose_variant(const stpi_problem *p, int forced_index, bool allow_mfma = true);
 int grid_blocks(const Variant &v, const stpi_problem *p);
 int segments_for(const Variant &v, const stpi_problem *p);
-constexpr int STPI_NSEG_MAX = 4;  // frame segments per tile at most
+constexpr int STPI_NSEG_MAX = 8;  // frame segments per tile at most
 WsLayout layout_for(const stpi_problem *p);
 constexpr int CHAIN_CHUNK = 16;  // steps per replayed chain segment in long tolerance runs
 int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevState *state, double *partials,
@@ -45,7 +45,7 @@ int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant 
 int forced_variant();
 int tuned_variant(const stpi_problem *p);
 
-hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, hipStream_t st);
+hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, int check_rise, hipStream_t st);
 hipError_t launch_state_from_norm(const double *partials, int n, DevState *s, hipStream_t st);
 hipError_t launch_clear_word(uint32_t *w, hipStream_t st);
 hipError_t launch_finalize(const double *partials, int n, DevState *s, hipStream_t st);

@@ -151,27 +151,23 @@ class TwoLevel:
 def solve_from(x0: torch.Tensor, f, kern, tol=1e-4, cap=2000, x=None, ws=None, stream=None):
     """Iterate from x0 with the fallback rule; x0 is copied into x (or used as x).
 
-    Returns (x, info dict); info has iters (all applications, including the
-    fallback's wasted ones), fallback flag, r1, r2, converged, residual.
+    One device chain: it stops after its second step if that residual is
+    above the first (the rule is checked on the device), and only then is the
+    iteration restarted from the uniform start. Returns (x, info dict); info
+    has iters (all applications, including the fallback's wasted ones),
+    fallback flag, r1, r2, converged, residual.
     """
     if x is None:
         x = x0
     elif x.data_ptr() != x0.data_ptr():
         x.copy_(x0)
-    _, r1 = power_iterate(f, kern, iters=1, x0=x, x=x, ws=ws, stream=stream, check=False)
-    if r1["residual"] < tol:
-        return x, dict(iters=1, fallback=False, r1=r1["residual"], r2=None, converged=True, residual=r1["residual"])
-    _, r2 = power_iterate(f, kern, iters=1, x0=x, x=x, ws=ws, stream=stream, check=False)
-    info = dict(r1=r1["residual"], r2=r2["residual"], fallback=False)
-    if not (r2["residual"] <= r1["residual"]):
-        info["fallback"] = True
-        x, r = power_iterate(f, kern, tol=tol, max_iters=cap, x=x, ws=ws, stream=stream, check=False)
-        info.update(iters=2 + r["iters"], converged=r["converged"], residual=r["residual"])
-    elif r2["residual"] < tol:
-        info.update(iters=2, converged=True, residual=r2["residual"])
-    else:
-        x, r = power_iterate(f, kern, tol=tol, max_iters=cap - 2, x0=x, x=x, ws=ws, stream=stream, check=False)
-        info.update(iters=2 + r["iters"], converged=r["converged"], residual=r["residual"])
+    x, r = power_iterate(f, kern, tol=tol, max_iters=cap, x0=x, x=x, ws=ws, stream=stream, check=False,
+                         rise_check=True)
+    info = dict(r1=r["r1"], r2=r["r2"] if r["iters"] >= 2 else None, fallback=bool(r["flags"] & 4),
+                iters=r["iters"], converged=r["converged"], residual=r["residual"])
+    if info["fallback"]:
+        x, r2 = power_iterate(f, kern, tol=tol, max_iters=cap, x=x, ws=ws, stream=stream, check=False)
+        info.update(iters=r["iters"] + r2["iters"], converged=r2["converged"], residual=r2["residual"])
     return x, info
 
 

@@ -64,7 +64,7 @@ def test_invalid_calls_fail_before_any_launch(native):
     assert rc == native.STPI_EWORKSPACE
     rc = native.lib.stpi_iterate(ctypes.byref(p), 16, 16, 1, 10, 0.0, 64, 1 << 30, ctypes.byref(res), None)
     assert rc == native.STPI_EINVAL   # x aliases f
-    rc = native.lib.stpi_iterate(ctypes.byref(p), 16, 32, 2, 10, 0.0, 64, 1 << 30, ctypes.byref(res), None)
+    rc = native.lib.stpi_iterate(ctypes.byref(p), 16, 32, 3, 10, 0.0, 64, 1 << 30, ctypes.byref(res), None)
     assert rc == native.STPI_EINVAL   # bad init
     rc = native.lib.stpi_iterate(ctypes.byref(p), 16, 32, 1, -1, 0.0, 64, 1 << 30, ctypes.byref(res), None)
     assert rc == native.STPI_EINVAL   # negative count

@@ -49,7 +49,10 @@ def test_batch_fixed_iterations_match_oracle(P):
 
 
 def test_batch_bitwise_equals_single_clip_path(P):
-    """Same kernel variant, same tiles, same reduction order: per-clip results are identical."""
+    """Same kernel variant, same tiles, same reduction order: per-clip results are
+    identical where the single-clip launch does not split the clip's frames
+    (a split changes the order of the partial sums), and agree to rounding
+    where it does."""
     Pm, B = P
     from paper_2212_08058_amd import _native as N
     kern = Pm.Kernel(4.0, 1.5, 8, 3)
@@ -74,11 +77,19 @@ def test_batch_bitwise_equals_single_clip_path(P):
     x_flat, res = plan.iterate(f_flat, max_iters=60, tol=1e-4, stream=s)
     try:
         N.lib.stpi_set_variant(idx)
+        split = 0
         for f, xv, r in zip(fs, plan.views(x_flat), res):
             xs, rs = Pm.power_iterate(torch.from_numpy(f).to(DEV), kern, tol=1e-4, max_iters=60)
-            assert torch.equal(xs, xv), f.shape
-            assert r["iters"] == rs["iters"] and r["converged"] == rs["converged"]
-            assert r["residual"] == rs["residual"] and r["lambda_"] == rs["lambda_"]
+            if Pm.launch_shape(f.shape, kern)["segments"] == 1:
+                assert torch.equal(xs, xv), f.shape
+                assert r["iters"] == rs["iters"] and r["converged"] == rs["converged"]
+                assert r["residual"] == rs["residual"] and r["lambda_"] == rs["lambda_"]
+            else:
+                split += 1
+                assert abs(r["iters"] - rs["iters"]) <= 1 and r["converged"] == rs["converged"]
+                assert abs(r["lambda_"] - rs["lambda_"]) <= 1e-12 * rs["lambda_"]
+                assert float((xs.double() - xv.double()).norm()) <= 1e-5
+        assert split < len(fs), "no clip compared bitwise"
     finally:
         N.lib.stpi_set_variant(-1)
 

@@ -396,3 +396,55 @@ def test_fused_finalisation_is_bitwise_equal(P, monkeypatch):
             assert ra == rb, (list(info), ra, rb)
     finally:
         N.lib.stpi_set_variant(-1)
+
+
+def test_enqueued_chains_survive_graph_eviction(P):
+    """Chains enqueued without waiting stay queued behind a busy stream while
+    later calls capture more graphs than the cache holds; evicting a queued
+    graph must wait for it. Each result equals the direct (graph-free) run."""
+    f, _ = synth.blob_clip(6, 40, 72, 2, 8)
+    fd = torch.from_numpy(f).to(DEV)
+    kern = P.Kernel(2.0, 1.0, 4, 2)
+    s = torch.cuda.Stream()
+    ws = torch.empty(P.workspace_bytes(fd.shape, kern), dtype=torch.uint8, device=DEV)
+    xs = [torch.empty_like(fd) for _ in range(20)]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(100_000_000)  # keeps the chains below queued while they are captured
+    for i, xv in enumerate(xs):
+        P.power_iterate(fd, kern, iters=3 + i, x=xv, ws=ws, stream=s, wait=False)
+    torch.cuda.synchronize()
+    for i, xv in enumerate(xs):
+        ref, r = P.power_iterate(fd, kern, iters=3 + i)
+        torch.cuda.synchronize()
+        assert r["iters"] == 3 + i and torch.equal(ref, xv), i
+
+
+def test_first_residuals_and_rise_check(P):
+    """The result carries the residuals of the first two applications (as the
+    oracle's trajectory gives them); with the rise check a start near the
+    second eigenvector (its residual grows as the principal component takes
+    over) stops after two applications with flag bit 2, and a start near the
+    principal eigenvector runs on."""
+    shape = (2, 8, 10)
+    rng = np.random.default_rng(4)
+    f = rng.uniform(0.2, 1.0, shape)
+    k = P.Kernel(2.0, 1.0, 3, 1)
+    ok = OKf(k.sigma_s, k.sigma_t, k.r_s, k.r_t)
+    A = oracle.dense_matrix(f.astype(np.float32).astype(np.float64), ok)
+    w, V = np.linalg.eigh(A)
+    v1, v2 = V[:, -1], V[:, -2]
+    fd = to_dev(f, torch.float32)
+    x0_rise = (v2 + 0.05 * v1).reshape(shape)  # residuals 0.0154, 0.0202, ... (eigenvalue ratio 1.31)
+    _, info = oracle.iterate(f.astype(np.float32), ok, x0=x0_rise, iters=2)
+    assert info.residuals[1] > info.residuals[0]
+    x, r = P.power_iterate(fd, k, tol=1e-9, max_iters=50, x0=to_dev(x0_rise, torch.float32), rise_check=True)
+    torch.cuda.synchronize()
+    print("rise", r, info.residuals)
+    assert r["iters"] == 2 and r["flags"] & 4 and not r["converged"]
+    assert abs(r["r1"] - info.residuals[0]) <= 1e-4 * info.residuals[0] + 1e-6
+    assert abs(r["r2"] - info.residuals[1]) <= 1e-4 * info.residuals[1] + 1e-6
+    x0_good = (v1 + 1e-2 * v2).reshape(shape)
+    x, r = P.power_iterate(fd, k, tol=1e-6, max_iters=200, x0=to_dev(x0_good, torch.float32), rise_check=True)
+    torch.cuda.synchronize()
+    assert not (r["flags"] & 4) and r["converged"] and r["iters"] > 2
