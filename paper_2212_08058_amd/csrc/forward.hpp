@@ -203,8 +203,10 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     using CT = typename Compute<ST>::type;
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
     using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
-    static_assert(PIPE != 3 || (RS == 16 && sizeof(CT) == 4), "matrix-core variants: RS 16, float arithmetic");
-    __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR>::value : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
+    static_assert(PIPE != 3 || ((RS == 16 || RS == 8) && sizeof(CT) == 4),
+                  "matrix-core variants: RS 8 or 16 (the slab margin), float arithmetic");
+    constexpr int PAD = RS <= 8 ? 8 : 16;
+    __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR, PAD>::value : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
     __shared__ double red[NTHR / 64];
 
     const int nbx = (a.W + TW - 1) / TW, nby = (a.H + TH - 1) / TH;
@@ -242,15 +244,16 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
         e = e < -100 ? -100 : (e > 100 ? 100 : e);
         const float umul = (float)(scale * ldexp(1.0, 10 - e));
         op.scale = ldexpf(1.f, e - 10);
+        // space taps centred at 16 (the kernel's are centred at RS)
         __shared__ float tapl[2 * 16 + 1];
         if (threadIdx.x < 2 * 16 + 1) {
             float g = 0.f;
 #pragma unroll
-            for (int i = 0; i < 2 * 16 + 1; ++i) g = (int)threadIdx.x == i ? (float)a.taps.gs[i] : g;
+            for (int i = 0; i < 2 * RS + 1; ++i) g = (int)threadIdx.x == i + 16 - RS ? (float)a.taps.gs[i] : g;
             tapl[threadIdx.x] = g;
         }
         __syncthreads();
-        stencil_tile_mfma<CT, RT, TH, TW, NTHR>(op, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1,
+        stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(op, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1,
                                                d2);
     } else if constexpr (PIPE == 2)
         stencil_tile_flat<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1, d2);

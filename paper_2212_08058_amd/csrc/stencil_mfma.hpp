@@ -54,13 +54,17 @@ constexpr int mfma_pitch(int n) {
     return ((p / 8) % 2 == 1) ? p : p + 8;
 }
 
-template <int TH, int TW, int NTHR>
+// PAD (8 or 16) is the slab margin, at least the space radius. An output
+// block of 16 rows (columns) reads 16 + 2 PAD slab rows (columns), that is KB
+// K blocks of 32 (the last 16 of them zero weight when PAD = 16).
+template <int TH, int TW, int NTHR, int PAD>
 struct MfmaGeometry {
+    static constexpr int KB = (16 + 2 * PAD + 31) / 32;
     static constexpr int MB = TH / 16, NB = TW / 16;  // output blocks down / across
-    static constexpr int SR = TH + 32, SC = TW + 32;  // staged slab rows / columns
-    static constexpr int UK = TH + 48;                // U^T column length read by the y-pass
+    static constexpr int SR = TH + 2 * PAD, SC = TW + 2 * PAD;  // staged slab rows / columns
+    static constexpr int UK = TH - 16 + 32 * KB;      // U^T column length read by the y-pass
     static constexpr int UP = mfma_pitch(UK);
-    static constexpr int YW = TW + 48;                // Y row length read by the x-pass
+    static constexpr int YW = TW - 16 + 32 * KB;      // Y row length read by the x-pass
     static constexpr int YP = mfma_pitch(YW);
     static constexpr int UPL = SC * UP;               // halves per U plane
     static constexpr int YPL = TH * YP;               // halves per Y plane
@@ -73,24 +77,26 @@ struct MfmaGeometry {
     static constexpr int IPS = (NITEM + NTHR - 1) / NTHR;
     static constexpr int NPF = 8 * IPS;               // prefetched elements per thread
     static constexpr int NWAVE = NTHR / 64;
-    static constexpr int NYB = MB * (NB + 2);         // y-pass blocks
+    static constexpr int NYC = SC / 16;               // y-pass block columns
+    static constexpr int NYB = MB * NYC;              // y-pass blocks
     static constexpr int NXB = MB * NB;               // x-pass blocks
     static constexpr int YPW = (NYB + NWAVE - 1) / NWAVE;
     static constexpr int XPW = NXB / NWAVE;           // x-pass blocks per wavefront
     static_assert(TH % 16 == 0 && TW % 16 == 0, "tile of whole 16 x 16 blocks");
+    static_assert(PAD == 8 || PAD == 16, "slab margin 8 or 16");
     static_assert(NXB % NWAVE == 0, "x-pass blocks must split evenly over the wavefronts");
     static_assert(NB % XPW == 0, "a wavefront's x-pass blocks lie in one block row");
     static_assert(LDS_HALVES % 2 == 0 && LDS_HALVES * 2 <= 160 * 1024, "LDS");
 };
 
 // LDS floats of a tile loop kind (instantiates the geometry only for PIPE 3).
-template <int PIPE, int TH, int TW, int NTHR>
+template <int PIPE, int TH, int TW, int NTHR, int PAD>
 struct MfmaLds {
     static constexpr int value = 1;
 };
-template <int TH, int TW, int NTHR>
-struct MfmaLds<3, TH, TW, NTHR> {
-    static constexpr int value = MfmaGeometry<TH, TW, NTHR>::LDS_FLOATS;
+template <int TH, int TW, int NTHR, int PAD>
+struct MfmaLds<3, TH, TW, NTHR, PAD> {
+    static constexpr int value = MfmaGeometry<TH, TW, NTHR, PAD>::LDS_FLOATS;
 };
 
 // Staging item m of thread tid. When the items do not fill the last round,
@@ -110,21 +116,23 @@ __device__ __forceinline__ void split_half(float v, _Float16 &hi, _Float16 &lo) 
 // y-pass of one 16 x 16 block of Y: reads the U^T planes, writes the Y planes.
 template <class G>
 __device__ __forceinline__ void mfma_yblock(const _Float16 *U, _Float16 *Y, int b, int lane,
-                                            const half8_t (&thi)[2], const half8_t (&tlo)[2]) {
-    const int rb = b / (G::NB + 2), cb = b % (G::NB + 2);
+                                            const half8_t (&thi)[G::KB], const half8_t (&tlo)[G::KB]) {
+    const int rb = b / G::NYC, cb = b % G::NYC;
     const int li = lane & 15, lg = lane >> 4;
     const _Float16 *p = U + (16 * cb + li) * G::UP + 16 * rb + 8 * lg;
-    // one accumulator per K half: two dependency chains of three products
-    float4_t ac[2];
+    // one accumulator per K block: independent dependency chains of three products
+    float4_t ac[G::KB];
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
+    for (int kb = 0; kb < G::KB; ++kb) {
         const half8_t ah = *reinterpret_cast<const half8_t *>(p + 32 * kb);
         const half8_t al = *reinterpret_cast<const half8_t *>(p + G::UPL + 32 * kb);
         ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, thi[kb], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
         ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, tlo[kb], ac[kb], 0, 0, 0);
         ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], ac[kb], 0, 0, 0);
     }
-    const float4_t acc = ac[0] + ac[1];
+    float4_t acc = ac[0];
+#pragma unroll
+    for (int kb = 1; kb < G::KB; ++kb) acc += ac[kb];
     half4_t h, l;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -140,14 +148,14 @@ __device__ __forceinline__ void mfma_yblock(const _Float16 *U, _Float16 *Y, int 
 
 // x-pass of one 16 x 16 output block: 4 consecutive outputs of one row per lane.
 template <class G>
-__device__ __forceinline__ void mfma_xblock(const _Float16 *Y, int b, int lane, const half8_t (&thi)[2],
-                                            const half8_t (&tlo)[2], float (&v)[4]) {
+__device__ __forceinline__ void mfma_xblock(const _Float16 *Y, int b, int lane, const half8_t (&thi)[G::KB],
+                                            const half8_t (&tlo)[G::KB], float (&v)[4]) {
     const int rb = b / G::NB, ob = b % G::NB;
     const int li = lane & 15, lg = lane >> 4;
     const _Float16 *p = Y + (16 * rb + li) * G::YP + 16 * ob + 8 * lg;
-    float4_t ac[2];
+    float4_t ac[G::KB];
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
+    for (int kb = 0; kb < G::KB; ++kb) {
         const half8_t bh = *reinterpret_cast<const half8_t *>(p + 32 * kb);
         const half8_t bl = *reinterpret_cast<const half8_t *>(p + G::YPL + 32 * kb);
         ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bh, float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
@@ -155,7 +163,12 @@ __device__ __forceinline__ void mfma_xblock(const _Float16 *Y, int b, int lane, 
         ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bl, ac[kb], 0, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = ac[0][j] + ac[1][j];
+    for (int j = 0; j < 4; ++j) {
+        float t = ac[0][j];
+#pragma unroll
+        for (int kb = 1; kb < G::KB; ++kb) t += ac[kb][j];
+        v[j] = t;
+    }
 }
 
 // Streams one tile through frames [t0, t1) (reading [t0 - RT, t1 + RT) clipped
@@ -163,11 +176,11 @@ __device__ __forceinline__ void mfma_xblock(const _Float16 *Y, int b, int lane, 
 // f * x at staging and op.scale must be 2^-S. rs is the problem's space
 // radius (slab rows and columns beyond it are not read). lds holds
 // MfmaGeometry::LDS_FLOATS floats; tapl holds the 33 space taps centred at 16.
-template <class CT, int RT, int TH, int TW, int NTHR, class Op>
+template <class CT, int RT, int TH, int TW, int NTHR, int PAD, class Op>
 __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &tp, const float *tapl, float umul,
                                                   int rs, int T, int t0, int t1, int H, int W, int x0, int y0,
                                                   float *lds, double &d1, double &d2) {
-    using G = MfmaGeometry<TH, TW, NTHR>;
+    using G = MfmaGeometry<TH, TW, NTHR, PAD>;
     constexpr int NPF = G::NPF, IPS = G::IPS, NTS = 2 * RT + 1, XPW = G::XPW;
     constexpr uint32_t ESZ = Op::ESZ;
     const int tid = threadIdx.x;
@@ -177,13 +190,13 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
     _Float16 *const Y0 = U0 + 2 * G::UBUF;
 
     // band taps in the operand layout: lane l, element j of K block kb holds
-    // g(32 kb + 8 (l / 16) + j - 16 - l % 16)
-    half8_t thi[2], tlo[2];
+    // g(32 kb + 8 (l / 16) + j - PAD - l % 16)
+    half8_t thi[G::KB], tlo[G::KB];
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
+    for (int kb = 0; kb < G::KB; ++kb)
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int d = 32 * kb + 8 * (lane >> 4) + j - 16 - (lane & 15);
+            const int d = 32 * kb + 8 * (lane >> 4) + j - PAD - (lane & 15);
             const float g = (d >= -16 && d <= 16) ? tapl[d + 16] : 0.f;
             _Float16 h, l;
             split_half(g, h, l);
@@ -192,6 +205,7 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
         }
 
     // zero the U^T rows [SR, UK) and the Y columns [SC, YW) of both buffers
+    // (none when PAD = 8)
     for (int i = tid; i < 2 * 2 * G::SC * (G::UK - G::SR); i += NTHR) {
         const int k = i % (G::UK - G::SR), rest = i / (G::UK - G::SR);
         const int c = rest % G::SC, plane = rest / G::SC;  // plane: buffer * 2 + hi/lo
@@ -209,13 +223,13 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
     for (int m = 0; m < IPS; ++m) {
         const int it = stage_item<G, NTHR>(tid, m);
         const int c = it % G::SC, g = it / G::SC;
-        const int gx = x0 - 16 + c;
-        const bool colok = it < G::NITEM && c >= 16 - rs && c < TW + 16 + rs && (unsigned)gx < (unsigned)W;
+        const int gx = x0 - PAD + c;
+        const bool colok = it < G::NITEM && c >= PAD - rs && c < TW + PAD + rs && (unsigned)gx < (unsigned)W;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int r = 8 * g + j;
-            const int gy = y0 - 16 + r;
-            const bool ok = colok && r >= 16 - rs && r < TH + 16 + rs && (unsigned)gy < (unsigned)H;
+            const int gy = y0 - PAD + r;
+            const bool ok = colok && r >= PAD - rs && r < TH + PAD + rs && (unsigned)gy < (unsigned)H;
             poff[8 * m + j] = ok ? (uint32_t)(gy * W + gx) * ESZ : OOB;
         }
     }

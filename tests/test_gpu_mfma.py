@@ -60,7 +60,8 @@ class forced:
 def test_variants_are_compiled():
     from paper_2212_08058_amd import _native as N
     v32 = mfma_variants(N.STPI_F32)
-    assert v32 and all(info[0] == 16 for _, info in v32)
+    assert v32 and all(info[0] in (8, 16) for _, info in v32)
+    assert {info[0] for _, info in v32} == {8, 16}
     assert mfma_variants(N.STPI_BF16)
 
 
@@ -91,7 +92,7 @@ def test_step_matches_oracle(P, shape, kp):
     fd, xd = torch.from_numpy(f).to(DEV), torch.from_numpy(x).to(DEV)
     ran = 0
     for i, info in mfma_variants(N.STPI_F32):
-        if info[1] < kern.r_t:
+        if info[1] < kern.r_t or info[0] < kern.r_s:
             continue
         with forced(i):
             z, sums = P.step(fd, xd, kern, x_scale=0.7)
@@ -106,13 +107,14 @@ def test_step_matches_oracle(P, shape, kp):
     assert ran
 
 
+@pytest.mark.parametrize("kp", [(5.0, 2.0, 15, 5), (4.0, 1.5, 8, 3)])
 @pytest.mark.parametrize("kind", ["tiny", "huge", "signed", "decades"])
-def test_value_ranges(P, kind):
+def test_value_ranges(P, kind, kp):
     """The half-precision operands are scaled by a power of two from max |f x|:
     results keep float accuracy for inputs far from 1, of either sign, or
-    spread over many decades."""
+    spread over many decades (both slab margins)."""
     from paper_2212_08058_amd import _native as N
-    kern = P.Kernel(5.0, 2.0, 15, 5)
+    kern = P.Kernel(*kp)
     shape = (10, 50, 90)
     rng = np.random.default_rng(7)
     f = rng.uniform(0.05, 1.0, shape)
@@ -131,7 +133,7 @@ def test_value_ranges(P, kind):
     ref = scale * oracle.apply(f.astype(np.float64), x.astype(np.float64), OKf(kern))
     fd, xd = torch.from_numpy(f).to(DEV), torch.from_numpy(x).to(DEV)
     for i, info in mfma_variants(N.STPI_F32):
-        if info[1] < kern.r_t:
+        if info[1] < kern.r_t or info[0] < kern.r_s:
             continue
         with forced(i):
             z, _ = P.step(fd, xd, kern, x_scale=scale)
@@ -149,7 +151,7 @@ def test_iteration_chain_matches_oracle(P):
     xr, info = oracle.iterate(f, OKf(kern), iters=10)
     fd = torch.from_numpy(f).to(DEV)
     for i, vi in mfma_variants(N.STPI_F32):
-        if vi[1] < kern.r_t:
+        if vi[1] < kern.r_t or vi[0] < kern.r_s:
             continue
         with forced(i):
             x, r = P.power_iterate(fd, kern, iters=10)
@@ -185,7 +187,7 @@ def test_bf16_storage(P):
     ref = oracle.apply(f.double().numpy(), x.double().numpy(), OKf(kern))
     fd, xd = f.to(DEV), x.to(DEV)
     for i, vi in mfma_variants(N.STPI_BF16):
-        if vi[1] < kern.r_t:
+        if vi[1] < kern.r_t or vi[0] < kern.r_s:
             continue
         with forced(i):
             z, _ = P.step(fd, xd, kern)
@@ -218,7 +220,7 @@ def test_matches_plain_variant_at_full_frame(P):
     idx = np.random.default_rng(5).integers(0, f.size, 400)
     ref = oracle.apply_at(f, x, OKf(kern), idx)
     for i, vi in mfma_variants(N.STPI_F32):
-        if vi[1] < kern.r_t:
+        if vi[1] < kern.r_t or vi[0] < kern.r_s:
             continue
         with forced(i):
             z, s = P.step(fd, xd, kern)
