@@ -98,74 +98,162 @@ __device__ __forceinline__ bool inside(const Dims &d, int t, int y, int x) {
     return (unsigned)t < (unsigned)d.T && (unsigned)y < (unsigned)d.H && (unsigned)x < (unsigned)d.W;
 }
 
-// Layer 1 (1 -> 16), ReLU. f is FP32 and enters rounded to bfloat16.
+// Raw buffer loads over a channels-last activation volume: an out-of-range
+// byte offset reads 0, so the loads of the zero padding need no branch (and
+// the compiler no full memory wait where branches join). The host limits
+// activation volumes to 2^31 bytes.
+constexpr uint32_t OOB_OFF = 0xFFFFFFF0u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t act_rsrc(const short *base, const Dims &d) {
+    const int bytes = (int)((size_t)d.T * d.H * d.W * C * sizeof(short));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<short *>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ bf16x4 load_b64(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+    return __builtin_bit_cast(bf16x4, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+}
+__device__ __forceinline__ short load_b16(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+    return (short)__builtin_amdgcn_raw_buffer_load_b16(r, boff, 0, 0);
+}
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
+
+// Layer 1 (1 -> 16), ReLU. f is FP32 and enters rounded to bfloat16. One
+// v_mfma_f32_16x16x32_bf16 per 16 voxels of a row: A = W1 [co][tap] with the
+// 27 taps padded to K = 32 (lane l holds co = l % 16, taps 8 (l / 16) .. + 7),
+// B = the voxels' 27 neighbours (lane l: voxel l % 16, the same taps),
+// gathered with buffer loads whose out-of-range offsets read the zero padding.
 __global__ __launch_bounds__(256) void conv_in_kernel(Dims d, const float *f, const Prep *p, short *act) {
-    __shared__ float w[C][NT];
-    __shared__ float b[C];
-    for (int i = threadIdx.x; i < C * NT; i += blockDim.x) w[i / NT][i % NT] = p->w1[i / NT][i % NT];
-    if (threadIdx.x < C) b[threadIdx.x] = p->b1[threadIdx.x];
-    __syncthreads();
-    const size_t V = (size_t)d.T * d.H * d.W;
-    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H), t = (int)(v / ((size_t)d.W * d.H));
-        float in[NT];
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * (blockDim.x / 64);
+    const int n = lane % 16, kq = lane / 16;
+    bf16x8 aw;
 #pragma unroll
-        for (int tap = 0; tap < NT; ++tap) {
+    for (int j = 0; j < 8; ++j) {
+        const int tap = 8 * kq + j;
+        aw[j] = tap < NT ? bfbits(p->w1[n][tap]) : (short)0;  // the masters are already bfloat16 values
+    }
+    float bias[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bias[j] = p->b1[4 * kq + j];
+    const int bytes = (int)((size_t)d.T * d.H * d.W * sizeof(float));
+    const auto rf = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(f), (short)0, bytes, 0x00020000);
+    const int gx = (d.W + 15) / 16;
+    const int ngroups = d.T * d.H * gx;
+    for (int g = wave; g < ngroups; g += nwaves) {
+        const int xg = g % gx, y = (g / gx) % d.H, t = g / (gx * d.H);
+        const int x = xg * 16 + n;
+        bf16x8 bv;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int tap = 8 * kq + j;
             const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
-            in[tap] = inside(d, tt, yy, xx) ? bfr(f[((size_t)tt * d.H + yy) * d.W + xx]) : 0.0f;
+            const bool ok = tap < NT && inside(d, tt, yy, xx);
+            const uint32_t off = (uint32_t)(((size_t)tt * d.H + yy) * d.W + xx) * 4;
+            bv[j] = bfbits(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rf, ok ? off : OOB_OFF, 0, 0)));
         }
-        short o[C];
+        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, aw),
+                                                            __builtin_bit_cast(bf16v8, bv), f32x4{0.f, 0.f, 0.f, 0.f},
+                                                            0, 0, 0);
+        // lane holds pre-activation[co = 4 kq + j][voxel n]
+        if (x < d.W) {
+            const size_t v = ((size_t)t * d.H + y) * d.W + x;
+            bf16x4 o;
 #pragma unroll
-        for (int co = 0; co < C; ++co) {
-            float s = b[co];
-#pragma unroll
-            for (int tap = 0; tap < NT; ++tap) s = fmaf(w[co][tap], in[tap], s);
-            o[co] = bfbits(fmaxf(s, 0.0f));
+            for (int j = 0; j < 4; ++j) o[j] = bfbits(fmaxf(acc[j] + bias[j], 0.0f));
+            *reinterpret_cast<bf16x4 *>(act + v * C + 4 * kq) = o;
         }
-        bf16x4 *dst = reinterpret_cast<bf16x4 *>(act + v * C);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q] = bf16x4{o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]};
     }
 }
 
+// Lane n of each 16-lane row takes src from lane n + 1 (ROW_SHL1) or n - 1
+// (ROW_SHR1) of the same row; lanes whose source lies outside the row keep
+// `old` (the neighbouring tile's edge voxel).
+constexpr int DPP_ROW_SHL1 = 0x101, DPP_ROW_SHR1 = 0x111;
+template <int CTRL>
+__device__ __forceinline__ bf16x4 row_shift(bf16x4 src, bf16x4 old) {
+    union U {
+        bf16x4 v;
+        int i[2];
+    } s, o, r;
+    s.v = src;
+    o.v = old;
+    r.i[0] = __builtin_amdgcn_update_dpp(o.i[0], s.i[0], CTRL, 0xF, 0xF, false);
+    r.i[1] = __builtin_amdgcn_update_dpp(o.i[1], s.i[1], CTRL, 0xF, 0xF, false);
+    return r.v;
+}
+
+constexpr int CONV_RB = 4;  // output rows per wavefront
+
 // 16 -> 16 convolution on the matrix cores. mode 0: out = relu(conv + bias);
 // mode 1 (input gradient of a ReLU layer): out = conv(g, flipped W^T) masked
-// by mask > 0. One wavefront per 16 consecutive voxels of a row.
+// by mask > 0. One wavefront per 16 consecutive voxels of CONV_RB rows: each
+// input row (per frame offset) is loaded once, as 16 voxels plus the two edge
+// voxels, and feeds up to three output rows; the x-1 and x+1 taps take the
+// row's registers shifted by one lane (DPP), so every activation is read
+// from memory about (CONV_RB + 2) / CONV_RB * 3 times instead of 27. A
+// group's 3 (CONV_RB + 2) row loads are all issued before its MFMAs.
 template <int MODE>
 __global__ __launch_bounds__(256) void conv16_kernel(Dims d, const short *in, const bf16x4 (*A)[64],
                                                      const float *bias, const short *mask, short *out) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const int gx = (d.W + 15) / 16;
-    const int ngroups = d.T * d.H * gx;
+    const int gx = (d.W + 15) / 16, gy = (d.H + CONV_RB - 1) / CONV_RB;
+    const int ngroups = d.T * gy * gx;
     const int nwaves = gridDim.x * (blockDim.x / 64);
     const int n = lane % 16, kq = lane / 16;  // voxel column of B, channel quad
+    const auto rs = act_rsrc(in, d);
     bf16x4 a[NT];
 #pragma unroll
     for (int tap = 0; tap < NT; ++tap) a[tap] = A[tap][lane];
     for (int g = wave; g < ngroups; g += nwaves) {
-        const int xg = g % gx, y = (g / gx) % d.H, t = g / (gx * d.H);
-        const int x = xg * 16 + n;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int xg = g % gx, yb = (g / gx) % gy, t = g / (gx * gy);
+        const int x0 = xg * 16, y0 = yb * CONV_RB, x = x0 + n;
+        f32x4 acc[CONV_RB];
 #pragma unroll
-        for (int tap = 0; tap < NT; ++tap) {
-            const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
-            bf16x4 bv = {0, 0, 0, 0};
-            if (inside(d, tt, yy, xx))
-                bv = *reinterpret_cast<const bf16x4 *>(in + ((((size_t)tt * d.H + yy) * d.W + xx) * C + 4 * kq));
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[tap], bv, acc, 0, 0, 0);
+        for (int r = 0; r < CONV_RB; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // all the group's input rows are loaded first (rows and frames outside
+        // the volume read as zero), so their latencies overlap
+        constexpr int NR = 3 * (CONV_RB + 2);
+        bf16x4 b0[NR], bm[NR], bp[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int tt = t + k / (CONV_RB + 2) - 1, yy = y0 - 1 + k % (CONV_RB + 2);
+            const bool rowok = tt >= 0 && tt < d.T && yy >= 0 && yy < d.H;
+            const uint32_t row = (uint32_t)(((size_t)tt * d.H + yy) * d.W) * (C * 2) + 8 * kq;
+            b0[k] = load_b64(rs, rowok && x < d.W ? row + (uint32_t)x * (C * 2) : OOB_OFF);
+            bm[k] = load_b64(rs, rowok && x0 > 0 ? row + (uint32_t)(x0 - 1) * (C * 2) : OOB_OFF);
+            bp[k] = load_b64(rs, rowok && x0 + 16 < d.W ? row + (uint32_t)(x0 + 16) * (C * 2) : OOB_OFF);
         }
-        // lane holds out[co = 4 kq + j][voxel n]
-        if (x < d.W) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int dt = k / (CONV_RB + 2) - 1, ry = k % (CONV_RB + 2);
+            const bf16x4 bl = row_shift<DPP_ROW_SHR1>(b0[k], bm[k]);  // voxel x - 1
+            const bf16x4 br = row_shift<DPP_ROW_SHL1>(b0[k], bp[k]);  // voxel x + 1
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int r = ry - 1 - dy;  // output row fed by this input row through dy
+                if (r < 0 || r >= CONV_RB) continue;
+                const int tap = (dt + 1) * 9 + (dy + 1) * 3;
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[tap], bl, acc[r], 0, 0, 0);
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[tap + 1], b0[k], acc[r], 0, 0, 0);
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[tap + 2], br, acc[r], 0, 0, 0);
+            }
+        }
+        // lane holds out[co = 4 kq + j][voxel n] of each row
+#pragma unroll
+        for (int r = 0; r < CONV_RB; ++r) {
+            const int y = y0 + r;
+            if (y >= d.H || x >= d.W) continue;
             const size_t v = ((size_t)t * d.H + y) * d.W + x;
             bf16x4 o;
             if (MODE == 0) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) o[j] = bfbits(fmaxf(acc[j] + bias[4 * kq + j], 0.0f));
+                for (int j = 0; j < 4; ++j) o[j] = bfbits(fmaxf(acc[r][j] + bias[4 * kq + j], 0.0f));
             } else {
                 const bf16x4 mk = *reinterpret_cast<const bf16x4 *>(mask + v * C + 4 * kq);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) o[j] = bf2f(mk[j]) > 0.0f ? bfbits(acc[j]) : (short)0;
+                for (int j = 0; j < 4; ++j) o[j] = bf2f(mk[j]) > 0.0f ? bfbits(acc[r][j]) : (short)0;
             }
             *reinterpret_cast<bf16x4 *>(out + v * C + 4 * kq) = o;
         }
@@ -312,47 +400,74 @@ __global__ __launch_bounds__(256) void wgrad_kernel(Dims d, const void *a_, cons
 // so a wavefront's loads are contiguous runs of the channels-last volumes.
 // Operands are the stored bfloat16 values widened exactly to float, so the
 // products and FP32 sums are those of a bfloat16 matrix product with FP32
-// accumulation. Each wavefront writes its partial sums (layout as
-// wgrad_kernel's, one "block" per wavefront); wgrad_reduce sums them.
-__global__ __launch_bounds__(256) void wgrad16_kernel(Dims d, const short *a, const short *g, float *partials) {
+// accumulation. Each workgroup writes its partial sums (layout as
+// wgrad_kernel's); wgrad_reduce sums them.
+__global__ __launch_bounds__(256, 2) void wgrad16_kernel(Dims d, const short *a, const short *g, float *partials) {
     constexpr int NP = C * (C * NT + 1);
+    __shared__ float red[NP];
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wave = blockIdx.x * 4 + wid;
     const int nwaves = gridDim.x * 4;
     const int ch = lane % 16, kv = lane / 16;
     const size_t V = (size_t)d.T * d.H * d.W;
     const size_t nq = (V + 3) / 4;
+    const auto ra = act_rsrc(a, d), rg = act_rsrc(g, d);
     f32x4 acc[NT];
 #pragma unroll
     for (int tap = 0; tap < NT; ++tap) acc[tap] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.0f;
-    for (size_t q = wave; q < nq; q += nwaves) {
-        const size_t v = q * 4 + kv;
-        const bool vin = v < V;
-        const int x = vin ? (int)(v % d.W) : 0, y = vin ? (int)((v / d.W) % d.H) : 0;
-        const int t = vin ? (int)(v / ((size_t)d.W * d.H)) : 0;
-        const float gv = vin ? bf2f(g[v * C + ch]) : 0.0f;
-        bacc += gv;
+    // two quads of voxels per pass: their 56 loads are in flight together
+    for (size_t q0 = (size_t)wave * 2; q0 < nq; q0 += (size_t)nwaves * 2) {
+        float gv[2], av[2][NT];
 #pragma unroll
-        for (int tap = 0; tap < NT; ++tap) {
-            const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
-            const float av = vin && inside(d, tt, yy, xx) ? bf2f(a[(((size_t)tt * d.H + yy) * d.W + xx) * C + ch]) : 0.0f;
-            acc[tap] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, av, acc[tap], 0, 0, 0);
+        for (int h = 0; h < 2; ++h) {
+            const size_t v = (q0 + h) * 4 + kv;
+            const bool vin = v < V;
+            const int x = vin ? (int)(v % d.W) : 0, y = vin ? (int)((v / d.W) % d.H) : 0;
+            const int t = vin ? (int)(v / ((size_t)d.W * d.H)) : 0;
+            gv[h] = bf2f(load_b16(rg, vin ? (uint32_t)(v * C + ch) * 2 : OOB_OFF));
+#pragma unroll
+            for (int tap = 0; tap < NT; ++tap) {
+                const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
+                const uint32_t off = (uint32_t)((((size_t)tt * d.H + yy) * d.W + xx) * C + ch) * 2;
+                av[h][tap] = bf2f(load_b16(ra, vin && inside(d, tt, yy, xx) ? off : OOB_OFF));
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bacc += gv[h];
+#pragma unroll
+            for (int tap = 0; tap < NT; ++tap)
+                acc[tap] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[h], av[h][tap], acc[tap], 0, 0, 0);
         }
     }
-    // lane holds dW_tap[co = 4 kv + j][ci = ch]
-    float *out = partials + (size_t)wave * NP;
-#pragma unroll
-    for (int tap = 0; tap < NT; ++tap)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) out[(4 * kv + j) * (C * NT + 1) + ch * NT + tap] = acc[tap][j];
     // bias: lanes ch, ch + 16, ch + 32, ch + 48 hold the four voxel rows of channel ch
     float b = bacc + __shfl_xor(bacc, 16, 64);
     b += __shfl_xor(b, 32, 64);
-    if (kv == 0) out[ch * (C * NT + 1) + C * NT] = b;
+    // the workgroup's four wavefronts add into LDS in turn (lane holds
+    // dW_tap[co = 4 kv + j][ci = ch]), then one partial per workgroup
+    for (int w = 0; w < 4; ++w) {
+        if (wid == w) {
+#pragma unroll
+            for (int tap = 0; tap < NT; ++tap)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = (4 * kv + j) * (C * NT + 1) + ch * NT + tap;
+                    red[k] = (w == 0 ? 0.0f : red[k]) + acc[tap][j];
+                }
+            if (kv == 0) {
+                const int k = ch * (C * NT + 1) + C * NT;
+                red[k] = (w == 0 ? 0.0f : red[k]) + b;
+            }
+        }
+        __syncthreads();
+    }
+    float *out = partials + (size_t)blockIdx.x * NP;
+    for (int k = threadIdx.x; k < NP; k += 256) out[k] = red[k];
 }
 
-constexpr int WG16_BLOCKS = 256;  // x 4 wavefronts: wgrad16_kernel's partial sums
+constexpr int WG16_BLOCKS = 512;  // x 4 wavefronts (two per SIMD): one partial per workgroup
 
 // Sums the workgroup partials of one layer into the gradient buffer (same
 // layout as the masters): dW[co][ci][tap] at w_off, db[co] at b_off.
@@ -399,7 +514,7 @@ size_t stpi_net_workspace_bytes(const stpi_problem *p) {
     size_t b = 5 * ((V * C * 2 + 255) & ~(size_t)255);
     b += (V * 4 + 255) & ~(size_t)255;
     b += 4096 * 8;
-    b += (size_t)std::max(WG_BLOCKS, 4 * WG16_BLOCKS) * C * (C * NT + 1) * sizeof(float);
+    b += (size_t)std::max(WG_BLOCKS, WG16_BLOCKS) * C * (C * NT + 1) * sizeof(float);
     return b;
 }
 
@@ -414,6 +529,9 @@ int stpi_net_prepare(const float *master, void *prep, void *stream) {
 static int net_check(const stpi_problem *p, const void *ws, size_t ws_bytes) {
     int rc = validate_problem(p);
     if (rc) return rc;
+    if ((size_t)p->T * p->H * p->W * C * sizeof(short) >= ((size_t)1 << 31))
+        return fail(STPI_EUNSUPPORTED, "net volumes are limited to 2^31 bytes of activations (%d x %d x %d)", p->T,
+                    p->H, p->W);
     if (!ws || ws_bytes < stpi_net_workspace_bytes(p))
         return fail(STPI_EWORKSPACE, "net workspace needs %zu bytes", stpi_net_workspace_bytes(p));
     return STPI_OK;
@@ -446,7 +564,7 @@ static NetWs net_ws(const stpi_problem *p, void *ws) {
 }
 
 static int conv16_grid(const stpi_problem *p) {
-    const long groups = (long)p->T * p->H * ((p->W + 15) / 16);
+    const long groups = (long)p->T * ((p->H + CONV_RB - 1) / CONV_RB) * ((p->W + 15) / 16);
     const long blocks = (groups + 3) / 4;
     return (int)(blocks < 8192 ? blocks : 8192);
 }
@@ -461,7 +579,7 @@ int stpi_net_forward(const stpi_problem *p, const float *f, const void *prep, fl
     NetWs n = net_ws(p, ws);
     hipStream_t s = (hipStream_t)stream;
     const Dims d{p->T, p->H, p->W};
-    hipLaunchKernelGGL(conv_in_kernel, dim3(2048), dim3(256), 0, s, d, f, P, n.act1);
+    hipLaunchKernelGGL(conv_in_kernel, dim3(conv16_grid(p)), dim3(256), 0, s, d, f, P, n.act1);
     hipLaunchKernelGGL(conv16_kernel<0>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.act1, P->a2, P->b2,
                        (const short *)nullptr, n.act2);
     hipLaunchKernelGGL(conv16_kernel<0>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.act2, P->a3, P->b3,
@@ -493,14 +611,14 @@ int stpi_net_backward(const stpi_problem *p, const float *f, const void *prep, c
     hipLaunchKernelGGL(wgrad16_kernel, dim3(WG16_BLOCKS), dim3(256), 0, s, d, (const short *)n.act2, n.g_a,
                        n.wpart);
     hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s,
-                       4 * WG16_BLOCKS, n.wpart, grad, OFF_W3, OFF_B3);
+                       WG16_BLOCKS, n.wpart, grad, OFF_W3, OFF_B3);
     hipLaunchKernelGGL(conv16_kernel<1>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.g_a, P->a3d,
                        (const float *)nullptr, n.act2, n.g_b);  // g at pre2
     // layer 2
     hipLaunchKernelGGL(wgrad16_kernel, dim3(WG16_BLOCKS), dim3(256), 0, s, d, (const short *)n.act1, n.g_b,
                        n.wpart);
     hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s,
-                       4 * WG16_BLOCKS, n.wpart, grad, OFF_W2, OFF_B2);
+                       WG16_BLOCKS, n.wpart, grad, OFF_W2, OFF_B2);
     hipLaunchKernelGGL(conv16_kernel<1>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.g_b, P->a2d,
                        (const float *)nullptr, n.act1, n.g_a);  // g at pre1
     // layer 1
