@@ -302,11 +302,12 @@ __global__ void mse_kernel(size_t V, const float *y, const float *xs, double sca
     }
 }
 
-__global__ void mse_finalize(int nb, size_t V, const double *partials, double *loss) {
-    if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(256) void mse_finalize(int nb, size_t V, const double *partials, double *loss) {
+    __shared__ double red[256 / 64];
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partials[2 * b];
-    *loss = s / (double)V;
+    for (int b = threadIdx.x; b < nb; b += 256) s += partials[2 * b];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) *loss = s / (double)V;
 }
 
 // Input gradient of layer 4, masked by layer 3's ReLU:
@@ -342,56 +343,6 @@ __global__ __launch_bounds__(256) void out_bwd_kernel(Dims d, const float *gy, c
     }
 }
 
-// Weight and bias gradients of one layer: dW[co][ci][tap] = sum_v g[v][co] a[v + tap][ci],
-// db[co] = sum_v g[v][co]. a: layer input (CI channels; CI = 1 reads FP32 f rounded to
-// bfloat16), g: gradient at the layer's pre-activation (CO channels; CO = 1 reads FP32
-// g_y). Threads are (ci, co, lane) triples; each workgroup covers a strided set of
-// voxels and writes its partial sums: partials[block][co][ci][tap] and [block][co][ci = CI] (bias).
-template <int CI, int CO>
-__global__ __launch_bounds__(256) void wgrad_kernel(Dims d, const void *a_, const void *g_, float *partials) {
-    constexpr int VL = 256 / (CI * CO);
-    constexpr int NP = CO * (CI * NT + 1);
-    static_assert(CI * CO * VL == 256, "thread mapping");
-    __shared__ float red[256][NT + 1];
-    const int tid = threadIdx.x;
-    const int ci = tid % CI, co = (tid / CI) % CO, vl = tid / (CI * CO);
-    float acc[NT + 1];
-#pragma unroll
-    for (int k = 0; k <= NT; ++k) acc[k] = 0.0f;
-    const size_t V = (size_t)d.T * d.H * d.W;
-    for (size_t v = (size_t)blockIdx.x * VL + vl; v < V; v += (size_t)gridDim.x * VL) {
-        const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H), t = (int)(v / ((size_t)d.W * d.H));
-        float gv;
-        if (CO == 1)
-            gv = reinterpret_cast<const float *>(g_)[v];
-        else
-            gv = bf2f(reinterpret_cast<const short *>(g_)[v * CO + co]);
-        acc[NT] += gv;
-#pragma unroll
-        for (int tap = 0; tap < NT; ++tap) {
-            const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
-            float av = 0.0f;
-            if (inside(d, tt, yy, xx)) {
-                const size_t u = ((size_t)tt * d.H + yy) * d.W + xx;
-                av = CI == 1 ? bfr(reinterpret_cast<const float *>(a_)[u])
-                             : bf2f(reinterpret_cast<const short *>(a_)[u * CI + ci]);
-            }
-            acc[tap] = fmaf(gv, av, acc[tap]);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k <= NT; ++k) red[tid][k] = acc[k];
-    __syncthreads();
-    if (vl == 0) {
-        for (int l = 1; l < VL; ++l)
-#pragma unroll
-            for (int k = 0; k <= NT; ++k) acc[k] += red[tid + l * CI * CO][k];
-        float *out = partials + (size_t)blockIdx.x * NP + co * (CI * NT + 1);
-#pragma unroll
-        for (int tap = 0; tap < NT; ++tap) out[ci * NT + tap] = acc[tap];
-        if (ci == 0) out[CI * NT] = acc[NT];
-    }
-}
 
 // Weight and bias gradients of a 16 -> 16 layer on the matrix cores. For each
 // tap, dW_tap[co][ci] = sum_v g[v][co] a[v + tap][ci] is a (16 x V) x (V x 16)
@@ -400,8 +351,8 @@ __global__ __launch_bounds__(256) void wgrad_kernel(Dims d, const void *a_, cons
 // so a wavefront's loads are contiguous runs of the channels-last volumes.
 // Operands are the stored bfloat16 values widened exactly to float, so the
 // products and FP32 sums are those of a bfloat16 matrix product with FP32
-// accumulation. Each workgroup writes its partial sums (layout as
-// wgrad_kernel's); wgrad_reduce sums them.
+// accumulation. Each workgroup writes its partial sums ([co][ci * 27 + tap],
+// then the bias of co); wgrad_reduce sums them.
 __global__ __launch_bounds__(256, 2) void wgrad16_kernel(Dims d, const short *a, const short *g, float *partials) {
     constexpr int NP = C * (C * NT + 1);
     __shared__ float red[NP];
@@ -467,22 +418,119 @@ __global__ __launch_bounds__(256, 2) void wgrad16_kernel(Dims d, const short *a,
     for (int k = threadIdx.x; k < NP; k += 256) out[k] = red[k];
 }
 
+// Weight and bias gradients of the one-channel layers on the matrix cores
+// (v_mfma_f32_16x16x4f32, four voxels per instruction, taps in two blocks of
+// 16 columns):
+//   MODE 1 (layer 1): D[co][tap] = sum_v g[v][co] bf16(f[v + off(tap)]),
+//                     db1[co] = sum_v g[v][co]; X = g (channels-last), Z = f;
+//   MODE 4 (layer 4): D[ci][tap] = sum_u act3[u][ci] g_y[u - off(tap)]
+//                     (the same sum as over v = u - off), db4 = sum_v g_y[v];
+//                     X = act3, Z = g_y.
+// Lane l holds X[voxel l / 16][channel l % 16] (A operand) and Z at that
+// voxel shifted by tap 16 blk + l % 16 (B operand); terms whose shifted voxel
+// lies outside the volume read zero through out-of-range buffer offsets.
+// Partial sums per workgroup: [co][ci * 27 + tap] then the bias of co (CI x 27 + 1 per co).
+template <int MODE>
+__global__ __launch_bounds__(256, 2) void wgrad1_kernel(Dims d, const short *x16, const float *z1, float *partials) {
+    constexpr int NPR = MODE == 1 ? C * (NT + 1) : C * NT + 1;
+    __shared__ float red[NPR];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wave = blockIdx.x * 4 + wid;
+    const int nwaves = gridDim.x * 4;
+    const int c = lane % 16, kv = lane / 16;
+    const size_t V = (size_t)d.T * d.H * d.W;
+    const size_t nq = (V + 3) / 4;
+    const auto rx = act_rsrc(x16, d);
+    const auto rz = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(z1), (short)0, (int)(V * sizeof(float)),
+                                                      0x00020000);
+    int sdt[2], sdy[2], sdx[2];
+    bool tapok[2];
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const int tap = 16 * blk + c;
+        tapok[blk] = tap < NT;
+        const int s = MODE == 1 ? 1 : -1;  // layer 4 reads Z at u - off
+        sdt[blk] = s * (tap / 9 - 1);
+        sdy[blk] = s * ((tap / 3) % 3 - 1);
+        sdx[blk] = s * (tap % 3 - 1);
+    }
+    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    float bacc = 0.0f;
+    for (size_t q0 = (size_t)wave * 2; q0 < nq; q0 += (size_t)nwaves * 2) {
+        float xa[2], zb[2][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const size_t v = (q0 + h) * 4 + kv;
+            const bool vin = v < V;
+            const int x = vin ? (int)(v % d.W) : 0, y = vin ? (int)((v / d.W) % d.H) : 0;
+            const int t = vin ? (int)(v / ((size_t)d.W * d.H)) : 0;
+            xa[h] = bf2f(load_b16(rx, vin ? (uint32_t)(v * C + c) * 2 : OOB_OFF));
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk) {
+                const int tt = t + sdt[blk], yy = y + sdy[blk], xx = x + sdx[blk];
+                const bool ok = vin && tapok[blk] && inside(d, tt, yy, xx);
+                const uint32_t off = (uint32_t)(((size_t)tt * d.H + yy) * d.W + xx) * 4;
+                const float zv = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rz, ok ? off : OOB_OFF, 0, 0));
+                zb[h][blk] = MODE == 1 ? bfr(zv) : zv;
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bacc += MODE == 1 ? xa[h] : (c == 13 ? zb[h][0] : 0.0f);  // tap 13 is the centre
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk)
+                acc[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[h], zb[h][blk], acc[blk], 0, 0, 0);
+        }
+    }
+    // bias over the four voxel rows: lanes c, c + 16, c + 32, c + 48
+    float b = bacc + __shfl_xor(bacc, 16, 64);
+    b += __shfl_xor(b, 32, 64);
+    // lane holds D[channel 4 kv + j][tap 16 blk + c]; the four wavefronts add into LDS in turn
+    for (int w = 0; w < 4; ++w) {
+        if (wid == w) {
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (!tapok[blk]) continue;
+                    const int ch = 4 * kv + j, tap = 16 * blk + c;
+                    const int k = MODE == 1 ? ch * (NT + 1) + tap : ch * NT + tap;
+                    red[k] = (w == 0 ? 0.0f : red[k]) + acc[blk][j];
+                }
+            if (kv == 0 && (MODE == 1 || c == 13)) {
+                const int k = MODE == 1 ? c * (NT + 1) + NT : C * NT;
+                red[k] = (w == 0 ? 0.0f : red[k]) + b;
+            }
+        }
+        __syncthreads();
+    }
+    float *out = partials + (size_t)blockIdx.x * NPR;
+    for (int k = threadIdx.x; k < NPR; k += 256) out[k] = red[k];
+}
+
 constexpr int WG16_BLOCKS = 512;  // x 4 wavefronts (two per SIMD): one partial per workgroup
 
 // Sums the workgroup partials of one layer into the gradient buffer (same
-// layout as the masters): dW[co][ci][tap] at w_off, db[co] at b_off.
+// layout as the masters): dW[co][ci][tap] at w_off, db[co] at b_off. One
+// workgroup per entry: threads add strided partials in double, then the
+// fixed block tree.
 template <int CI, int CO>
-__global__ void wgrad_reduce(int nblocks, const float *partials, float *grad, int w_off, int b_off) {
+__global__ __launch_bounds__(256) void wgrad_reduce(int nblocks, const float *partials, float *grad, int w_off,
+                                                    int b_off) {
     constexpr int NP = CO * (CI * NT + 1);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= NP) return;
+    __shared__ double red[256 / 64];
+    const int i = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += (double)partials[(size_t)b * NP + i];
-    const int co = i / (CI * NT + 1), r = i % (CI * NT + 1);
-    if (r < CI * NT)
-        grad[w_off + co * CI * NT + r] = (float)s;
-    else
-        grad[b_off + co] = (float)s;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += (double)partials[(size_t)b * NP + i];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) {
+        const int co = i / (CI * NT + 1), r = i % (CI * NT + 1);
+        if (r < CI * NT)
+            grad[w_off + co * CI * NT + r] = (float)s;
+        else
+            grad[b_off + co] = (float)s;
+    }
 }
 
 // Start vector from the net output: x0 = max(y, 0) + eps (normalised by the iteration).
@@ -491,7 +539,7 @@ __global__ void warm_x0_kernel(size_t V, const float *y, float eps, float *x0) {
         x0[v] = fmaxf(y[v], 0.0f) + eps;
 }
 
-constexpr int WG_BLOCKS = 512;
+constexpr int WG1_BLOCKS = 2048;  // x 4 wavefronts: wgrad1_kernel's partial sums (448 floats each)
 
 }  // namespace net
 
@@ -514,7 +562,7 @@ size_t stpi_net_workspace_bytes(const stpi_problem *p) {
     size_t b = 5 * ((V * C * 2 + 255) & ~(size_t)255);
     b += (V * 4 + 255) & ~(size_t)255;
     b += 4096 * 8;
-    b += (size_t)std::max(WG_BLOCKS, WG16_BLOCKS) * C * (C * NT + 1) * sizeof(float);
+    b += std::max((size_t)WG1_BLOCKS * C * (NT + 1), (size_t)WG16_BLOCKS * C * (C * NT + 1)) * sizeof(float);
     return b;
 }
 
@@ -601,30 +649,29 @@ int stpi_net_backward(const stpi_problem *p, const float *f, const void *prep, c
     const Dims d{p->T, p->H, p->W};
     const size_t V = (size_t)p->T * p->H * p->W;
     hipLaunchKernelGGL(mse_kernel, dim3(2048), dim3(256), 0, s, V, y, x_star, std::sqrt((double)V), n.gy, n.lpart);
-    hipLaunchKernelGGL(mse_finalize, dim3(1), dim3(64), 0, s, 2048, V, n.lpart, loss);
+    hipLaunchKernelGGL(mse_finalize, dim3(1), dim3(256), 0, s, 2048, V, n.lpart, loss);
     // layer 4
-    hipLaunchKernelGGL((wgrad_kernel<C, 1>), dim3(WG_BLOCKS), dim3(256), 0, s, d, (const void *)n.act3,
-                       (const void *)n.gy, n.wpart);
-    hipLaunchKernelGGL((wgrad_reduce<C, 1>), dim3(2), dim3(256), 0, s, WG_BLOCKS, n.wpart, grad, OFF_W4, OFF_B4);
+    hipLaunchKernelGGL(wgrad1_kernel<4>, dim3(WG1_BLOCKS), dim3(256), 0, s, d, (const short *)n.act3,
+                       (const float *)n.gy, n.wpart);
+    hipLaunchKernelGGL((wgrad_reduce<C, 1>), dim3(C * NT + 1), dim3(256), 0, s, WG1_BLOCKS, n.wpart, grad, OFF_W4, OFF_B4);
     hipLaunchKernelGGL(out_bwd_kernel, dim3(2048), dim3(256), 0, s, d, n.gy, n.act3, P, n.g_a);  // g at pre3
     // layer 3
     hipLaunchKernelGGL(wgrad16_kernel, dim3(WG16_BLOCKS), dim3(256), 0, s, d, (const short *)n.act2, n.g_a,
                        n.wpart);
-    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s,
+    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3(C * (C * NT + 1)), dim3(256), 0, s,
                        WG16_BLOCKS, n.wpart, grad, OFF_W3, OFF_B3);
     hipLaunchKernelGGL(conv16_kernel<1>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.g_a, P->a3d,
                        (const float *)nullptr, n.act2, n.g_b);  // g at pre2
     // layer 2
     hipLaunchKernelGGL(wgrad16_kernel, dim3(WG16_BLOCKS), dim3(256), 0, s, d, (const short *)n.act1, n.g_b,
                        n.wpart);
-    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3((C * (C * NT + 1) + 255) / 256), dim3(256), 0, s,
+    hipLaunchKernelGGL((wgrad_reduce<C, C>), dim3(C * (C * NT + 1)), dim3(256), 0, s,
                        WG16_BLOCKS, n.wpart, grad, OFF_W2, OFF_B2);
     hipLaunchKernelGGL(conv16_kernel<1>, dim3(conv16_grid(p)), dim3(256), 0, s, d, n.g_b, P->a2d,
                        (const float *)nullptr, n.act1, n.g_a);  // g at pre1
     // layer 1
-    hipLaunchKernelGGL((wgrad_kernel<1, C>), dim3(WG_BLOCKS), dim3(256), 0, s, d, (const void *)f,
-                       (const void *)n.g_a, n.wpart);
-    hipLaunchKernelGGL((wgrad_reduce<1, C>), dim3(2), dim3(256), 0, s, WG_BLOCKS, n.wpart, grad, OFF_W1, OFF_B1);
+    hipLaunchKernelGGL(wgrad1_kernel<1>, dim3(WG1_BLOCKS), dim3(256), 0, s, d, (const short *)n.g_a, f, n.wpart);
+    hipLaunchKernelGGL((wgrad_reduce<1, C>), dim3(C * (NT + 1)), dim3(256), 0, s, WG1_BLOCKS, n.wpart, grad, OFF_W1, OFF_B1);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? STPI_OK : hip_fail(e, "net backward");
 }
