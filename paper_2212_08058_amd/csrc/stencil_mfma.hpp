@@ -1,8 +1,8 @@
 // Matrix-core form of the step's two spatial passes (space radius up to 16).
 //
 // A 1D Gaussian pass over a tile is a product with a banded Toeplitz matrix,
-// so both spatial passes of the separable filter (Eq. 3's spatial factor,
-// applied along y then x) run as v_mfma_f32_16x16x32_f16 products. To keep
+// so both spatial passes of the separable filter (Sec. 4.3's 1D passes,
+// along y then x) run as v_mfma_f32_16x16x32_f16 products. To keep
 // float accuracy, every operand is split into two half-precision parts,
 // a = a_hi + a_lo with a_hi = fp16(a) and a_lo = fp16(a - a_hi) (about 22
 // significant bits), and each product is formed from the three terms that
@@ -11,8 +11,8 @@
 //
 // Range. The staged input is u' = f x_stored scale 2^S, where scale makes the
 // iterate unit and 2^S is chosen on the device from a bound B >= |f x scale|
-// so that |u'| < 2^10; the y-pass output is then below 33 * 2^10 (the taps are
-// <= 1), inside half precision. The output picks up 2^-S in the epilogue's
+// so that |u'| < 2^10; the y-pass output is then below (2 PAD + 1) 2^10 <= 33 *
+// 2^10 (the taps are <= 1), inside half precision. The output picks up 2^-S in the epilogue's
 // scale, so z is the same as in the plain form. Values far below the largest
 // one lose relative precision (half precision subnormals), but never more
 // than 2^-24 * 2^10 / 2^S in absolute terms.
@@ -21,21 +21,23 @@
 // frames as the plain tile loop does (three-stage pipeline, one barrier per
 // phase, the same t-ring and epilogue; the epilogue's loads are issued at the
 // start of the phase). Per frame:
-//   stage:  u' on the (TH + 32) x (TW + 32) slab around the tile, split into
+//   stage:  u' on the (TH + 2 PAD) x (TW + 2 PAD) slab around the tile (PAD =
+//           8 or 16, at least the space radius), split into
 //           hi and lo planes stored column-major (U^T[c][k], k = slab row),
 //           each thread writing 8 consecutive rows of one column (16 bytes);
 //   y-pass: for each 16 x 16 block of Y (16 tile rows x 16 slab columns),
-//           Y^T = sum_kb U^T[cols][32 kb .. 32 kb + 32) * Bband_kb, giving
+//           Y^T = sum_kb U^T[cols][32 kb .. 32 kb + 32) * Bband_kb (KB = 2
+//           K blocks of 32 for PAD = 16, one for PAD = 8), giving
 //           each lane 4 consecutive columns of one row, stored row-major in
 //           hi and lo planes;
 //   x-pass: for each 16 x 16 output block, Out^T = sum_kb Bband_kb^T *
 //           Y^T[32 kb ..], again 4 consecutive columns of one row per lane,
 //           which feed the t-ring (2 RT + 1 register slots) and the epilogue.
-// Both band matrices hold g(32 kb + k - 16 - i) at (row i, col k) in the
+// Both band matrices hold g(32 kb + k - PAD - i) at (row i, col k) in the
 // operand layout, so one set of tap registers serves as the y-pass B operand
 // and the x-pass A operand. Rows and columns of the slab beyond the space
-// radius are staged as zeros; the 16 extra U rows and Y columns that the
-// last K block of the bottom / right blocks reads are zero once for all.
+// radius are staged as zeros; with PAD = 16 the 16 extra U rows and Y columns
+// that the last K block of the bottom / right blocks reads are zeroed once.
 #pragma once
 
 #include "stencil.hpp"

@@ -181,6 +181,8 @@ def warm_start_experiment(n_train=2000, n_eval=200, epochs=2, train_shape=(16, 2
         cosd["two_level_net"].append(1.0 - float(torch.sum(xbuf.double() * xref)))
         if i < 0:
             continue  # first pass: graph capture and allocations
+        if (i + 1) % 25 == 0:
+            log(f"  evaluated {i + 1} of {n_eval} clips")
         coarse_it.append(ci)
         for m, (it, t, fb) in runs.items():
             iters[m].append(it)
