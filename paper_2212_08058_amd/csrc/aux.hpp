@@ -95,26 +95,31 @@ __global__ void train_init_kernel(size_t n, ST *x, double *norm) {
 template <class ST>
 __global__ void bound_kernel(size_t n, const ST *f, const ST *x, uint32_t *out) {
     __shared__ float red[AUX_THREADS / 64];
-    // four independent maxima per thread keep four loads in flight
-    float m[4] = {0.f, 0.f, 0.f, 0.f};
-    const size_t stride = (size_t)gridDim.x * AUX_THREADS;
-    size_t i = (size_t)blockIdx.x * AUX_THREADS + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
+    constexpr int VEC = 16 / (int)sizeof(ST);
+    float r = 0.f;
+    const size_t stride = (size_t)gridDim.x * AUX_THREADS, tid = (size_t)blockIdx.x * AUX_THREADS + threadIdx.x;
+    size_t head = 0;
+    if ((((uintptr_t)f | (uintptr_t)x) & 15) == 0) {
+        // 16-byte chunks
+        const size_t nv = n / VEC;
+        for (size_t i = tid; i < nv; i += stride) {
+            Chunk16<ST> cf, cx;
+            cf.u = reinterpret_cast<const uint4 *>(f)[i];
+            if (x) cx.u = reinterpret_cast<const uint4 *>(x)[i];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float v = fabsf((float)ld(f + i + k * stride));
-            if (x) v *= fabsf((float)ld(x + i + k * stride));
-            m[k] = v > m[k] ? v : m[k];
+            for (int e = 0; e < VEC; ++e) {
+                float v = fabsf((float)ld(&cf.e[e]));
+                if (x) v *= fabsf((float)ld(&cx.e[e]));
+                r = v > r ? v : r;
+            }
         }
+        head = nv * VEC;
     }
-    for (; i < n; i += stride) {
+    for (size_t i = head + tid; i < n; i += stride) {
         float v = fabsf((float)ld(f + i));
         if (x) v *= fabsf((float)ld(x + i));
-        m[0] = v > m[0] ? v : m[0];
+        r = v > r ? v : r;
     }
-    float r = m[0];
-#pragma unroll
-    for (int k = 1; k < 4; ++k) r = m[k] > r ? m[k] : r;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const float w = __shfl_xor(r, o, 64);

@@ -45,13 +45,34 @@ __global__ void sumsq_kernel(const ST *x, size_t n, double *partials) {
 }
 
 // x <- scale * (current iterate), written into the caller's buffer.
+// 16 bytes of stored elements, for streaming passes.
+template <class ST>
+union Chunk16 {
+    uint4 u;
+    ST e[16 / sizeof(ST)];
+};
+
 template <class ST>
 __global__ void normalize_kernel(ST *x, const ST *buf1, size_t n, const DevState *s) {
     using CT = typename Compute<ST>::type;
+    constexpr int VEC = 16 / (int)sizeof(ST);
     const ST *src = s->cur ? buf1 : x;
     const CT scale = (CT)s->scale;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        st(x + i, scale * ld(src + i));
+    const size_t stride = (size_t)gridDim.x * blockDim.x, tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t head = 0;
+    if ((((uintptr_t)x | (uintptr_t)src) & 15) == 0) {
+        // 16-byte chunks (each thread reads and writes the same chunk, so x may be src)
+        const size_t nv = n / VEC;
+        for (size_t i = tid; i < nv; i += stride) {
+            Chunk16<ST> c;
+            c.u = reinterpret_cast<const uint4 *>(src)[i];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) st(&c.e[e], scale * ld(&c.e[e]));
+            reinterpret_cast<uint4 *>(x)[i] = c.u;
+        }
+        head = nv * VEC;
+    }
+    for (size_t i = head + tid; i < n; i += stride) st(x + i, scale * ld(src + i));
 }
 
 }  // namespace stpi

@@ -140,28 +140,40 @@ __global__ __launch_bounds__(256) void conv_in_kernel(Dims d, const float *f, co
     const auto rf = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(f), (short)0, bytes, 0x00020000);
     const int gx = (d.W + 15) / 16;
     const int ngroups = d.T * d.H * gx;
-    for (int g = wave; g < ngroups; g += nwaves) {
-        const int xg = g % gx, y = (g / gx) % d.H, t = g / (gx * d.H);
-        const int x = xg * 16 + n;
-        bf16x8 bv;
+    constexpr int GB = 4;  // groups whose gathers are in flight together
+    for (int g0 = wave * GB; g0 < ngroups; g0 += nwaves * GB) {
+        bf16x8 bv[GB];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int tap = 8 * kq + j;
-            const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
-            const bool ok = tap < NT && inside(d, tt, yy, xx);
-            const uint32_t off = (uint32_t)(((size_t)tt * d.H + yy) * d.W + xx) * 4;
-            bv[j] = bfbits(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rf, ok ? off : OOB_OFF, 0, 0)));
+        for (int h = 0; h < GB; ++h) {
+            const int g = g0 + h < ngroups ? g0 + h : ngroups - 1;
+            const int xg = g % gx, y = (g / gx) % d.H, t = g / (gx * d.H);
+            const int x = xg * 16 + n;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int tap = 8 * kq + j;
+                const int tt = t + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
+                const bool ok = tap < NT && inside(d, tt, yy, xx);
+                const uint32_t off = (uint32_t)(((size_t)tt * d.H + yy) * d.W + xx) * 4;
+                bv[h][j] = bfbits(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rf, ok ? off : OOB_OFF, 0, 0)));
+            }
         }
-        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, aw),
-                                                            __builtin_bit_cast(bf16v8, bv), f32x4{0.f, 0.f, 0.f, 0.f},
-                                                            0, 0, 0);
-        // lane holds pre-activation[co = 4 kq + j][voxel n]
-        if (x < d.W) {
-            const size_t v = ((size_t)t * d.H + y) * d.W + x;
-            bf16x4 o;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) o[j] = bfbits(fmaxf(acc[j] + bias[j], 0.0f));
-            *reinterpret_cast<bf16x4 *>(act + v * C + 4 * kq) = o;
+        for (int h = 0; h < GB; ++h) {
+            const int g = g0 + h;
+            if (g >= ngroups) break;
+            const int xg = g % gx, y = (g / gx) % d.H, t = g / (gx * d.H);
+            const int x = xg * 16 + n;
+            f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, aw),
+                                                                __builtin_bit_cast(bf16v8, bv[h]),
+                                                                f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            // lane holds pre-activation[co = 4 kq + j][voxel n]
+            if (x < d.W) {
+                const size_t v = ((size_t)t * d.H + y) * d.W + x;
+                bf16x4 o;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o[j] = bfbits(fmaxf(acc[j] + bias[j], 0.0f));
+                *reinterpret_cast<bf16x4 *>(act + v * C + 4 * kq) = o;
+            }
         }
     }
 }
@@ -189,12 +201,13 @@ constexpr int CONV_RB = 4;  // output rows per wavefront
 // mode 1 (input gradient of a ReLU layer): out = conv(g, flipped W^T) masked
 // by mask > 0. One wavefront per 16 consecutive voxels of CONV_RB rows: each
 // input row (per frame offset) is loaded once, as 16 voxels plus the two edge
-// voxels, and feeds up to three output rows; the x-1 and x+1 taps take the
+// voxels (one load: lane 0 takes x0 - 1, lane 15 x0 + 16), and feeds up to
+// three output rows; the x-1 and x+1 taps take the
 // row's registers shifted by one lane (DPP), so every activation is read
 // from memory about (CONV_RB + 2) / CONV_RB * 3 times instead of 27. A
 // group's 3 (CONV_RB + 2) row loads are all issued before its MFMAs.
 template <int MODE>
-__global__ __launch_bounds__(256) void conv16_kernel(Dims d, const short *in, const bf16x4 (*A)[64],
+__global__ __launch_bounds__(256, 3) void conv16_kernel(Dims d, const short *in, const bf16x4 (*A)[64],
                                                      const float *bias, const short *mask, short *out) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
@@ -215,21 +228,24 @@ __global__ __launch_bounds__(256) void conv16_kernel(Dims d, const short *in, co
         // all the group's input rows are loaded first (rows and frames outside
         // the volume read as zero), so their latencies overlap
         constexpr int NR = 3 * (CONV_RB + 2);
-        bf16x4 b0[NR], bm[NR], bp[NR];
+        // b0: the lane's voxel; be: the row's edge voxel the shifts bring in
+        // (x0 - 1 for lane 0, x0 + 16 for lane 15; other lanes never use it)
+        const int xe = n == 0 ? x0 - 1 : x0 + 16;
+        const bool eok = xe >= 0 && xe < d.W;
+        bf16x4 b0[NR], be[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int tt = t + k / (CONV_RB + 2) - 1, yy = y0 - 1 + k % (CONV_RB + 2);
             const bool rowok = tt >= 0 && tt < d.T && yy >= 0 && yy < d.H;
             const uint32_t row = (uint32_t)(((size_t)tt * d.H + yy) * d.W) * (C * 2) + 8 * kq;
             b0[k] = load_b64(rs, rowok && x < d.W ? row + (uint32_t)x * (C * 2) : OOB_OFF);
-            bm[k] = load_b64(rs, rowok && x0 > 0 ? row + (uint32_t)(x0 - 1) * (C * 2) : OOB_OFF);
-            bp[k] = load_b64(rs, rowok && x0 + 16 < d.W ? row + (uint32_t)(x0 + 16) * (C * 2) : OOB_OFF);
+            be[k] = load_b64(rs, rowok && eok ? row + (uint32_t)xe * (C * 2) : OOB_OFF);
         }
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int dt = k / (CONV_RB + 2) - 1, ry = k % (CONV_RB + 2);
-            const bf16x4 bl = row_shift<DPP_ROW_SHR1>(b0[k], bm[k]);  // voxel x - 1
-            const bf16x4 br = row_shift<DPP_ROW_SHL1>(b0[k], bp[k]);  // voxel x + 1
+            const bf16x4 bl = row_shift<DPP_ROW_SHR1>(b0[k], be[k]);  // voxel x - 1 (lane 0 keeps be)
+            const bf16x4 br = row_shift<DPP_ROW_SHL1>(b0[k], be[k]);  // voxel x + 1 (lane 15 keeps be)
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy) {
                 const int r = ry - 1 - dy;  // output row fed by this input row through dy
