@@ -167,9 +167,8 @@ def main():
 
     # dominant kernel alone, HIP events on its own stream
     log("timing the step kernel")
-    z = torch.empty_like(f)
-    xs = x.clone()
-    kern_ms = P.time_step(f, xs, kern, z=z, reps=args.kernel_reps, ws=ws, stream=stream)
+    xs = torch.empty_like(f)
+    kern_ms, product = P.time_chain_step(f, kern, x=xs, reps=args.kernel_reps, ws=ws, stream=stream)
     bytes_per_voxel = 3 * elem
     flops_per_voxel = 2 * (2 * (2 * kern.r_s + 1) + (2 * kern.r_t + 1)) + 6
     hbm_gbs = bytes_per_voxel * Nvox / (kern_ms * 1e-3) / 1e9
@@ -197,6 +196,7 @@ def main():
             "parallelism": "single GPU",
             "tile": dict(zip(("r_s", "r_t", "TH", "TW", "threads", "RY", "QX", "min_waves"), list(vinfo)[:8]),
                          loop=LOOP_KIND.get(vinfo[8], str(vinfo[8])),
+                         chain_form="product" if product else "plain",
                          segments=P.launch_shape(f.shape, kern, dtype)["segments"]),
         },
         "roofline": {},
@@ -214,7 +214,7 @@ def main():
                            "hbm": hbm}
     prof = profiled_traffic(f"fwd_step_{T}x{H}x{W}_{args.dtype}")
     ctype = "float" if args.dtype == "f32" else "stpi::bf16"
-    sig = f"fwd_step_kernel<{ctype}, " + ", ".join(str(v) for v in vinfo) + ">"
+    sig = f"fwd_step_kernel<{ctype}, " + ", ".join(str(v) for v in vinfo) + (", true>" if product else ", false>")
     if prof is not None and sig not in prof["kernel"]:
         prof = None  # the counters were taken on another tile variant
     if prof is not None:
@@ -240,8 +240,9 @@ def main():
             P.power_iterate(fb, kern, iters=iters, x=xb, ws=wsb, stream=stream)
         torch.cuda.synchronize()
         dtb = (time.perf_counter() - t0) / args.steps
-        kb = P.time_step(fb, xb.clone(), kern, z=torch.empty_like(fb), reps=args.kernel_reps, ws=wsb, stream=stream)
+        kb, pfb = P.time_chain_step(fb, kern, x=torch.empty_like(fb), reps=args.kernel_reps, ws=wsb, stream=stream)
         out["bf16"] = {"value": Nvox * iters / dtb, "ms_per_step": dtb * 1e3, "kernel_ms": kb,
+                       "chain_form": "product" if pfb else "plain",
                        "hbm_gbs": 6 * Nvox / (kb * 1e-3) / 1e9,
                        "alu_tflops": flops_per_voxel * Nvox / (kb * 1e-3) / 1e12}
     if "copy" in extras:

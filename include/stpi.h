@@ -121,6 +121,14 @@ int stpi_step(const stpi_problem *p, const void *f, const void *x, double x_scal
  * and no status is read back. */
 int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int max_iters, double tol,
                  void *ws, size_t ws_bytes, stpi_result *out, void *stream);
+/* On a matrix-core variant (stpi_variant_info PIPE 3) a chain of one or more
+ * steps runs in product form: the buffers hold w = f .* x * 2^-2e (e from
+ * max |f| < 2^e), so each step stages one volume instead of two, and the
+ * iterate is w / (f 2^-2e), 0 where f = 0 (which A x is anyway). The final
+ * pass forms x from it. Results agree with the plain form to float rounding;
+ * after a failed first step (zero or non-finite status) x holds the start
+ * masked by f != 0. STPI_NO_PRODUCT=1 in the environment selects the plain
+ * form. */
 
 /* ---- kernel variants ------------------------------------------------------
  * Each storage type has a list of compiled step kernels (radii RS >= r_s,
@@ -155,6 +163,17 @@ int stpi_set_variant(int index);
  * benchmark and the autotuner. */
 int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z, void *ws, size_t ws_bytes,
                    int variant, int reps, void *stream, double *avg_ms);
+
+/* Average duration in milliseconds of one step of an iteration chain, as
+ * stpi_iterate runs it (the step kernel with its fused finalisation; on a
+ * matrix-core variant the product form, see stpi_iterate), measured with HIP
+ * events on `stream` around `reps` back-to-back steps of a fixed-count chain
+ * from the uniform start. f: device volume of p->dtype; x: a device volume of
+ * p->dtype used as scratch (overwritten); ws as for stpi_iterate. variant: as
+ * for stpi_time_step. *product_form (if not NULL) receives 1 when the product
+ * form ran. Synchronises `stream`. Used by the benchmark. */
+int stpi_time_chain_step(const stpi_problem *p, const void *f, void *x, void *ws, size_t ws_bytes, int variant,
+                         int reps, void *stream, double *avg_ms, int *product_form);
 
 /* ---- batched clips --------------------------------------------------------
  * Many clips of different length and frame size iterated together, all with

@@ -68,6 +68,8 @@ PROTOTYPES = [
     ("stpi_set_variant", ctypes.c_int, [ctypes.c_int]),
     ("stpi_time_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _sz, ctypes.c_int, ctypes.c_int, _vp,
                                       ctypes.POINTER(ctypes.c_double)]),
+    ("stpi_time_chain_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _sz, ctypes.c_int, ctypes.c_int, _vp,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     ("stpi_batch_plan", ctypes.c_int, [ctypes.POINTER(Clip), ctypes.c_int, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
     ("stpi_batch_workspace_bytes", _sz, [_vp]),

@@ -180,3 +180,22 @@ def time_step(f: torch.Tensor, x: torch.Tensor, k: Kernel, z: torch.Tensor | Non
     N.check(N.lib.stpi_time_step(ctypes.byref(p), f.data_ptr(), x.data_ptr(), z.data_ptr(), ws.data_ptr(),
                                  ws.numel(), int(variant), int(reps), _stream_ptr(stream), ctypes.byref(ms)))
     return ms.value
+
+
+def time_chain_step(f: torch.Tensor, k: Kernel, x: torch.Tensor | None = None, reps: int = 20, variant: int = -1,
+                    ws: torch.Tensor | None = None, stream=None) -> tuple[float, bool]:
+    """Average duration in ms of one step of an iteration chain as power_iterate
+    runs it (stpi_time_chain_step, HIP events), and whether it ran in product
+    form. x is scratch (overwritten)."""
+    _check_volume("f", f)
+    if x is None:
+        x = torch.empty_like(f)
+    _check_volume("x", x, f.shape, f.dtype)
+    ws = _workspace(f.shape, k, f.dtype, f.device, ws)
+    p = problem_for(f.shape, k, f.dtype)
+    ms = ctypes.c_double()
+    pf = ctypes.c_int()
+    N.check(N.lib.stpi_time_chain_step(ctypes.byref(p), f.data_ptr(), x.data_ptr(), ws.data_ptr(), ws.numel(),
+                                       int(variant), int(reps), _stream_ptr(stream), ctypes.byref(ms),
+                                       ctypes.byref(pf)))
+    return ms.value, bool(pf.value)

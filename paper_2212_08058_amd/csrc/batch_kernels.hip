@@ -31,6 +31,7 @@ __global__ void batch_init_kernel(DevState *states, const ClipDesc *clips, int n
     s->ubound = 0u;
     s->first_res[0] = s->first_res[1] = 0.0;
     s->check_rise = 0;
+    s->pform = 0;
 }
 
 __global__ void batch_state_from_norm_kernel(const double *partials, DevState *states, BatchCtl *ctl) {

@@ -75,4 +75,54 @@ __global__ void normalize_kernel(ST *x, const ST *buf1, size_t n, const DevState
     for (size_t i = head + tid; i < n; i += stride) st(x + i, scale * ld(src + i));
 }
 
+// Product-form chain from the caller's start x: buffer 1 <- w = f x g (as
+// stored; g = 2^-2e from the bound on |f| in the state), and the state points
+// at it. x itself is first overwritten by the first step.
+template <class ST>
+__global__ void to_product_kernel(const ST *f, const ST *x, ST *w, size_t n, DevState *s) {
+    using CT = typename Compute<ST>::type;
+    const CT g = (CT)ldexp(1.0, -2 * bound_exponent(__uint_as_float(s->ubound), PRODUCT_ELIM));
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(w + i, (ld(f + i) * ld(x + i)) * g);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s->cur = 1;
+        s->pform = 1;
+    }
+}
+
+// Final pass of a product-form chain: x <- scale * (current iterate), the
+// iterate being w / (f g) (0 where f = 0), computed in double as the step's
+// sums are; before any step of a uniform start it is the constant 1.
+template <class ST>
+__global__ void from_product_kernel(ST *x, const ST *buf1, const ST *f, size_t n, const DevState *s) {
+    using CT = typename Compute<ST>::type;
+    constexpr int VEC = 16 / (int)sizeof(ST);
+    const size_t stride = (size_t)gridDim.x * blockDim.x, tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s->pform == 2) {
+        const CT c = (CT)s->scale;
+        for (size_t i = tid; i < n; i += stride) st(x + i, c);
+        return;
+    }
+    const ST *src = s->cur ? buf1 : x;
+    const double m = s->scale * ldexp(1.0, 2 * bound_exponent(__uint_as_float(s->ubound), PRODUCT_ELIM));
+    auto one = [&](CT wv, CT fv) -> CT {
+        return fv != CT(0) ? (CT)((double)wv / (double)fv * m) : CT(0);
+    };
+    size_t head = 0;
+    if ((((uintptr_t)x | (uintptr_t)src | (uintptr_t)f) & 15) == 0) {
+        // 16-byte chunks (each thread reads and writes the same chunk, so x may be src)
+        const size_t nv = n / VEC;
+        for (size_t i = tid; i < nv; i += stride) {
+            Chunk16<ST> c, cf;
+            c.u = reinterpret_cast<const uint4 *>(src)[i];
+            cf.u = reinterpret_cast<const uint4 *>(f)[i];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) st(&c.e[e], one(ld(&c.e[e]), ld(&cf.e[e])));
+            reinterpret_cast<uint4 *>(x)[i] = c.u;
+        }
+        head = nv * VEC;
+    }
+    for (size_t i = head + tid; i < n; i += stride) st(x + i, one(ld(src + i), ld(f + i)));
+}
+
 }  // namespace stpi

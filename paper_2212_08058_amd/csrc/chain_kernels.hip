@@ -5,7 +5,7 @@
 
 namespace stpi {
 
-__global__ void state_init_kernel(DevState *s, double scale, double tol, int max_iters, int check_rise) {
+__global__ void state_init_kernel(DevState *s, double scale, double tol, int max_iters, int check_rise, int pform) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         s->scale = scale;
         s->residual = 0.0;
@@ -22,6 +22,7 @@ __global__ void state_init_kernel(DevState *s, double scale, double tol, int max
         s->ubound = 0u;
         s->first_res[0] = s->first_res[1] = 0.0;
         s->check_rise = check_rise;
+        s->pform = pform;
     }
 }
 
@@ -186,8 +187,9 @@ hipError_t launch_adamw(int dtype, int64_t n, void *w, const void *g, void *m, v
     return hipGetLastError();
 }
 
-hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, int check_rise, hipStream_t st) {
-    hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, st, s, scale, tol, max_iters, check_rise);
+hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, int check_rise, int pform,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, st, s, scale, tol, max_iters, check_rise, pform);
     return hipGetLastError();
 }
 

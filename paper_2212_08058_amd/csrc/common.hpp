@@ -60,7 +60,10 @@ struct DevState {
     uint32_t ubound;   // float bits of max |f| (matrix-core step variants)
     double first_res[2];  // residuals after the chain's first and second steps
     int32_t check_rise;   // 1: stop after the second step if its residual is above the first's
-    int32_t pad_;
+    // 0: the buffers hold the iterate itself. Product form (matrix-core chain
+    // steps): 1: the current buffer holds w = f x g (see FwdOpP), 2: uniform
+    // start, no step taken yet (the iterate is the constant 1, w = f itself).
+    int32_t pform;
 };
 
 static_assert(sizeof(DevState) <= 256, "the iteration state lives in a 256-byte workspace slot");
@@ -68,6 +71,16 @@ static_assert(sizeof(DevState) <= 256, "the iteration state lives in a 256-byte 
 constexpr uint32_t FLAG_ZERO = 1u;
 constexpr uint32_t FLAG_NONFINITE = 2u;
 constexpr uint32_t FLAG_ROSE = 4u;  // stopped by the check_rise rule (not an error)
+
+// Exponent e of a bound (bound < 2^e, from frexp), clamped to [-lim, lim];
+// 0 for a zero or non-finite bound.
+__device__ __forceinline__ int bound_exponent(float bound, int lim) {
+    int e = 0;
+    if (bound > 0.f && bound <= 3.0e38f) (void)frexpf(bound, &e);
+    return e < -lim ? -lim : (e > lim ? lim : e);
+}
+// Product-form chains keep 2^(+-2e) normal floats.
+constexpr int PRODUCT_ELIM = 60;
 
 // Workgroup size and summation order of the per-step reduction of partial
 // sums: thread i < FINAL_THREADS adds entries i, i + FINAL_THREADS, ... in
@@ -97,6 +110,7 @@ __device__ __forceinline__ void step_finalize(DevState *s, double p1, double p2)
     s->scale = 1.0 / nz;
     s->cur ^= 1;
     s->iters += 1;
+    if (s->pform == 2) s->pform = 1;
     if (s->iters <= 2) s->first_res[s->iters - 1] = s->residual;
     if (s->check_rise && s->iters == 2 && !(s->first_res[1] <= s->first_res[0])) {
         s->flags |= FLAG_ROSE;

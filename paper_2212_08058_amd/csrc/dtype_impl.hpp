@@ -34,9 +34,22 @@ hipError_t bound_impl(size_t n, const void *f, const void *x, uint32_t *out, hip
     return hipGetLastError();
 }
 
+hipError_t to_product_impl(const void *f, const void *x, void *buf1, size_t n, DevState *st_, hipStream_t s) {
+    hipLaunchKernelGGL(to_product_kernel<ST_>, dim3(1024), dim3(256), 0, s, (const ST_ *)f, (const ST_ *)x,
+                       (ST_ *)buf1, n, st_);
+    return hipGetLastError();
+}
+
+hipError_t from_product_impl(void *x, const void *buf1, const void *f, size_t n, const DevState *st_, hipStream_t s) {
+    hipLaunchKernelGGL(from_product_kernel<ST_>, dim3(1024), dim3(256), 0, s, (ST_ *)x, (const ST_ *)buf1,
+                       (const ST_ *)f, n, st_);
+    return hipGetLastError();
+}
+
 #define STPI_VARIANT_ENTRY(RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE) \
     {RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, &launch_fwd<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>, \
-     &fwd_blocks_per_cu<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>},
+     &fwd_blocks_per_cu<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>,                                 \
+     product_launcher<ST_, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>()},
 
 const Variant kVariants[] = {STPI_VARIANTS(STPI_VARIANT_ENTRY)};
 
@@ -120,7 +133,7 @@ hipError_t batch_normalize_impl(void *x, const void *buf1, const ClipDesc *clips
 
 const DtypeOps kOps = {sizeof(ST_),       kVariants,        (int)(sizeof(kVariants) / sizeof(kVariants[0])),
                        &fill_ones_impl,   &sumsq_impl,      &normalize_impl,
-                       &bound_impl,
+                       &bound_impl,        &to_product_impl, &from_product_impl,
                        kAdj,              kNAdj,            &combine_fwd_impl,
                        &combine_bwd_impl, &scale_impl,      &dot_impl,
                        &train_init_impl,  &max_impl,        &bce_impl,

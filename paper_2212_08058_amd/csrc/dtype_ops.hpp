@@ -16,6 +16,9 @@ struct DtypeOps {
     hipError_t (*normalize)(void *x, const void *buf1, size_t n, const DevState *s, hipStream_t);
     // *out = max(*out, max |f| or max |f x|) as float bits (matrix-core step variants)
     hipError_t (*bound)(size_t n, const void *f, const void *x, uint32_t *out, hipStream_t);
+    // product-form chains: start (w = f x g into buf1) and final pass (x = unit iterate)
+    hipError_t (*to_product)(const void *f, const void *x, void *buf1, size_t n, DevState *s, hipStream_t);
+    hipError_t (*from_product)(void *x, const void *buf1, const void *f, size_t n, const DevState *s, hipStream_t);
     // differentiation path (null where a storage type does not provide it)
     const AdjVariant *adj_variants;
     int nadj;

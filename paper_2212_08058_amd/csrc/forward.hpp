@@ -28,10 +28,13 @@ struct FwdLaunch {
 };
 
 // One variant of the step kernel: compiled radii and tile.
+using FwdLaunchFn = hipError_t (*)(const FwdLaunch &, hipStream_t);
+
 struct Variant {
     int RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE;
-    hipError_t (*launch)(const FwdLaunch &, hipStream_t);
+    FwdLaunchFn launch;
     int (*blocks_per_cu)();  // resident workgroups per CU (occupancy query)
+    FwdLaunchFn launch_p;    // product-form chain step (see FwdOpP); null where not compiled
 };
 
 template <class ST>
@@ -193,18 +196,126 @@ struct FwdOp {
     }
 };
 
+// Product form of a chain step (matrix-core tile loop only). The buffers hold
+// w = f x g instead of the iterate x, with g = 2^-2e a power of two from the
+// bound max |f| < 2^e (so w stays in range whatever the scale of f). A step
+// then stages one array, w (times a power of two: w scale 2^(10 + e) =
+// f x_unit 2^(10 - e)), instead of f and x, and its epilogue reads f and w at
+// the outputs as the plain form reads f and x. It stores
+// w_new = (f (2^-S acc)) f g, and the iterate it leaves is defined as
+// x_new = w_new / (f g) (0 where f = 0): p1 = sum x_prev x_new and
+// p2 = sum x_new^2 are taken on that vector, in double (a reciprocal of f
+// per output), so the cosine, the norm and the next step's staged operand
+// all refer to the same vector. The emitted sums leave out the powers of two
+// 1/g: the caller multiplies d1 by ginv_in ginv_out and d2 by ginv_out^2.
+// ginv_in = 1 / g of the input: 1 on the first step of a uniform start, whose
+// input is f itself (w of the constant 1, up to g).
+// 1 / f in double from the hardware reciprocal and one Newton step (far below
+// float rounding, which is all the sums below need: both products of an output
+// use the same value); 0 for f = 0.
+__device__ __forceinline__ double recip_or_zero(float fv) {
+    const double fd = (double)fv;
+    double r = __builtin_amdgcn_rcp(fd);
+    r = fma(r, fma(-fd, r, 1.0), r);
+    return fv != 0.f ? r : 0.0;
+}
+
+template <class ST>
+struct FwdOpP {
+    using CT = float;
+    using IO = BufIO<ST>;
+    static constexpr uint32_t ESZ = IO::SZ;
+    const ST *f;
+    const ST *src;  // w of the current iterate (or f)
+    ST *dst;        // w of the next
+    CT scale;       // 2^-S, undoes the staging prescale
+    CT gout;        // g
+    double ginv_in, ginv_out;
+    size_t plane;
+    uint32_t pbytes;
+
+    template <int NPF>
+    struct Raw {
+        CT u[NPF];
+    };
+    template <int NPF>
+    __device__ __forceinline__ void fetch(int t, const uint32_t (&off)[NPF], Raw<NPF> &raw) const {
+        const auto ru = make_rsrc(src + (size_t)t * plane, pbytes);
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) raw.u[k] = IO::load(ru, off[k]);
+    }
+    template <int NPF>
+    __device__ __forceinline__ CT input(const Raw<NPF> &raw, int k) const {
+        return raw.u[k];
+    }
+    template <int IPT, int QX>
+    struct OutRaw {
+        CT f[IPT][QX], u[IPT][QX];
+    };
+    template <int IPT, int QX>
+    __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw) const {
+        const auto rf = make_rsrc(f + (size_t)t * plane, pbytes);
+        const auto ru = make_rsrc(src + (size_t)t * plane, pbytes);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            if constexpr (QX == 4) {
+                if (off[i][3] != OOB) {
+                    IO::load4(rf, off[i][0], raw.f[i]);
+                    IO::load4(ru, off[i][0], raw.u[i]);
+                    continue;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                raw.f[i][q] = IO::load(rf, off[i][q]);
+                raw.u[i][q] = IO::load(ru, off[i][q]);
+            }
+        }
+    }
+    template <int IPT, int QX>
+    __device__ __forceinline__ void emit_frame(int t, const CT (&acc)[IPT][QX], const OutRaw<IPT, QX> &raw,
+                                               const uint32_t (&off)[IPT][QX], double &d1, double &d2) const {
+        const auto rw = make_rsrc(dst + (size_t)t * plane, pbytes);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            CT w[QX];
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                const CT fv = raw.f[i][q];
+                const CT z = scale * (fv * acc[i][q]);
+                w[q] = (z * fv) * gout;
+                const double r = recip_or_zero(fv);
+                const double xn = (double)IO::rounded(w[q]) * r;
+                const double xp = (double)raw.u[i][q] * r;
+                d2 = fma(xn, xn, d2);
+                d1 = fma(xp, xn, d1);
+            }
+            if constexpr (QX == 4) {
+                if (off[i][3] != OOB) {
+                    IO::store4(rw, off[i][0], w);
+                    continue;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < QX; ++q) IO::store(rw, off[i][q], w[q]);
+        }
+    }
+};
+
 // OCC: minimum waves per SIMD the register allocation must allow (1 = no limit;
 // with NTHR = 512, OCC = 4 lets two workgroups share a CU).
 // PIPE: 1 selects the software-pipelined tile loop (stencil_tile_pipe), 2 its
 // straight-line form (stencil_tile_flat), 3 the matrix-core tile loop
 // (stencil_tile_mfma; RS = 16, any space radius up to 16).
-template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>
+// PF: product-form chain step (PIPE 3, iterate mode only).
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE, bool PF>
 __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     using CT = typename Compute<ST>::type;
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
     using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
     static_assert(PIPE != 3 || ((RS == 16 || RS == 8) && sizeof(CT) == 4),
                   "matrix-core variants: RS 8 or 16 (the slab margin), float arithmetic");
+    static_assert(!PF || PIPE == 3, "the product form runs on the matrix-core tile loop");
     constexpr int PAD = RS <= 8 ? 8 : 16;
     __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR, PAD>::value : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
     __shared__ double red[NTHR / 64];
@@ -236,14 +347,6 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     double d1 = 0.0, d2 = 0.0;
     const int x0 = (tile % nbx) * TW, y0 = (tile / nbx) * TH;
     if constexpr (PIPE == 3) {
-        // staging multiplier scale 2^S with |f x scale 2^S| < 2^10, output scale 2^-S
-        float bound = __uint_as_float(*a.ubound);
-        if (!a.state) bound *= (float)fabs(scale);
-        int e = 0;
-        if (bound > 0.f && bound <= 3.0e38f) (void)frexpf(bound, &e);
-        e = e < -100 ? -100 : (e > 100 ? 100 : e);
-        const float umul = (float)(scale * ldexp(1.0, 10 - e));
-        op.scale = ldexpf(1.f, e - 10);
         // space taps centred at 16 (the kernel's are centred at RS)
         __shared__ float tapl[2 * 16 + 1];
         if (threadIdx.x < 2 * 16 + 1) {
@@ -253,8 +356,34 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
             tapl[threadIdx.x] = g;
         }
         __syncthreads();
-        stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(op, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1,
-                                               d2);
+        // staging multiplier umul = scale 2^S with |f x scale 2^S| < 2^10, output scale 2^-S
+        float bound = __uint_as_float(*a.ubound);
+        if constexpr (PF) {
+            const int e = bound_exponent(bound, PRODUCT_ELIM);
+            const bool first = a.state->pform == 2;
+            FwdOpP<ST> pp;
+            pp.f = a.f;
+            pp.src = first ? a.f : op.src;
+            pp.dst = op.dst;
+            pp.scale = ldexpf(1.f, e - 10);
+            pp.gout = ldexpf(1.f, -2 * e);
+            pp.ginv_out = ldexp(1.0, 2 * e);
+            pp.ginv_in = first ? 1.0 : pp.ginv_out;
+            pp.plane = op.plane;
+            pp.pbytes = op.pbytes;
+            const float umul = (float)(scale * ldexp(1.0, 10 - e) * pp.ginv_in);
+            stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(pp, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0,
+                                                   lds, d1, d2);
+            d1 *= pp.ginv_in * pp.ginv_out;
+            d2 *= pp.ginv_out * pp.ginv_out;
+        } else {
+            if (!a.state) bound *= (float)fabs(scale);
+            const int e = bound_exponent(bound, 100);
+            const float umul = (float)(scale * ldexp(1.0, 10 - e));
+            op.scale = ldexpf(1.f, e - 10);
+            stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(op, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0,
+                                                   lds, d1, d2);
+        }
     } else if constexpr (PIPE == 2)
         stencil_tile_flat<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1, d2);
     else if constexpr (PIPE == 1)
@@ -303,7 +432,7 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     }
 }
 
-template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE, bool PF = false>
 hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     using CT = typename Compute<ST>::type;
     FwdArgs<ST> a;
@@ -325,6 +454,7 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     for (int d = 1; d <= 16; ++d)
         if (L.gs[16 + d] != 0.0) a.rs = d;
     if (PIPE == 3 && !L.ubound) return hipErrorInvalidValue;
+    if (PF && (!L.state || L.vout)) return hipErrorInvalidValue;
     // L holds taps centred at index 16 (space) and 8 (time), zero beyond the
     // problem's radii; the kernel wants them centred at its compiled RS, RT.
     for (int i = 0; i < 2 * 16 + 1; ++i) a.taps.gs[i] = CT(0);
@@ -333,8 +463,8 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     for (int d = -RT; d <= RT; ++d) a.taps.gt[d + RT] = (CT)L.gt[d + 8];
     const int nunits = ((L.W + TW - 1) / TW) * ((L.H + TH - 1) / TH) * a.nseg;
     const int per = (nunits + NUM_XCD - 1) / NUM_XCD;
-    hipLaunchKernelGGL((fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>), dim3(per * NUM_XCD), dim3(NTHR), 0,
-                       stream, a);
+    hipLaunchKernelGGL((fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, PF>), dim3(per * NUM_XCD),
+                       dim3(NTHR), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -347,9 +477,18 @@ template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, in
 int fwd_blocks_per_cu() {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE>, NTHR, 0) != hipSuccess)
+            &n, fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, false>, NTHR, 0) != hipSuccess)
         n = 1;
     return n > 0 ? n : 1;
+}
+
+// The product-form launcher of a variant (matrix-core variants only).
+template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>
+constexpr FwdLaunchFn product_launcher() {
+    if constexpr (PIPE == 3)
+        return &launch_fwd<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, true>;
+    else
+        return nullptr;
 }
 
 }  // namespace stpi

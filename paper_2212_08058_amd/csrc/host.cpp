@@ -201,10 +201,12 @@ struct GraphKey {
     double tol;
     const Variant *v;
     hipStream_t s;
-    int part;  // ChainPart
+    int part;   // ChainPart
+    int pform;  // product-form chain
     bool operator==(const GraphKey &o) const {
         return std::memcmp(&p, &o.p, sizeof(p)) == 0 && f == o.f && x == o.x && ws == o.ws && init == o.init &&
-               max_iters == o.max_iters && tol == o.tol && v == o.v && s == o.s && part == o.part;
+               max_iters == o.max_iters && tol == o.tol && v == o.v && s == o.s && part == o.part &&
+               pform == o.pform;
     }
 };
 struct GraphEntry {
@@ -229,6 +231,13 @@ static bool graphs_enabled() {
     return !(e && e[0] == '1');
 }
 
+// Chains on a matrix-core variant run in product form (one staged array per
+// step) unless STPI_NO_PRODUCT=1; a chain of no steps keeps the plain form.
+int chain_pform(const Variant *v, int max_iters) {
+    const char *e = std::getenv("STPI_NO_PRODUCT");
+    return v && v->launch_p && max_iters > 0 && !(e && e[0] == '1') ? 1 : 0;
+}
+
 int forced_variant() { return g_forced_variant; }
 void set_forced_variant(int v) { g_forced_variant = v; }
 
@@ -244,24 +253,24 @@ struct ChainArgs {
     double *partials;
     int init, max_iters;
     double tol;
+    int pform;
 };
 
 int enqueue_chain_part(const ChainArgs &a, int part, hipStream_t s) {
     switch (part) {
         case CHAIN_ALL:
             return enqueue_iteration(a.p, a.ops, a.v, a.f, a.x, a.buf1, a.state, a.partials, a.init, a.max_iters,
-                                     a.tol, s);
+                                     a.tol, s, a.pform);
         case CHAIN_HEAD: {
-            const int rc =
-                enqueue_chain_init(a.p, a.ops, a.x, a.state, a.partials, a.init, a.max_iters, a.tol, s, a.v, a.f);
-            return rc ? rc : enqueue_chain_steps(a.p, a.v, a.f, a.x, a.buf1, a.state, a.partials, CHAIN_CHUNK, s);
+            const int rc = enqueue_chain_init(a.p, a.ops, a.x, a.state, a.partials, a.init, a.max_iters, a.tol, s,
+                                              a.v, a.f, a.buf1, a.pform);
+            return rc ? rc
+                      : enqueue_chain_steps(a.p, a.v, a.f, a.x, a.buf1, a.state, a.partials, CHAIN_CHUNK, s, a.pform);
         }
         case CHAIN_CHUNK_PART:
-            return enqueue_chain_steps(a.p, a.v, a.f, a.x, a.buf1, a.state, a.partials, CHAIN_CHUNK, s);
-        default: {
-            const hipError_t e = a.ops->normalize(a.x, a.buf1, (size_t)a.p->T * a.p->H * a.p->W, a.state, s);
-            return e == hipSuccess ? STPI_OK : hip_fail(e, "normalize");
-        }
+            return enqueue_chain_steps(a.p, a.v, a.f, a.x, a.buf1, a.state, a.partials, CHAIN_CHUNK, s, a.pform);
+        default:
+            return enqueue_chain_tail(a.p, a.ops, a.f, a.x, a.buf1, a.state, s, a.pform);
     }
 }
 
@@ -440,7 +449,8 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
     // chain of CHAIN_CHUNK steps, the host checking the stop flag one chunk
     // behind so the device never waits for it.
     const bool chunked = tol > 0.0 && max_iters > 2 * CHAIN_CHUNK;
-    ChainArgs ca{p, ops, v, f, x, buf1, state, partials, init, max_iters, tol};
+    const int pform = chain_pform(v, max_iters);
+    ChainArgs ca{p, ops, v, f, x, buf1, state, partials, init, max_iters, tol, pform};
     const bool use_graphs = s != nullptr && graphs_enabled();
     auto run = [&](int part) -> int {
         if (!use_graphs) return enqueue_chain_part(ca, part, s);
@@ -456,6 +466,7 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
         key.v = v;
         key.s = s;
         key.part = part;
+        key.pform = pform;
         return launch_cached_graph(key, [&] { return enqueue_chain_part(ca, part, s); }, s);
     };
     if (!chunked) {
@@ -546,6 +557,51 @@ int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z,
     return STPI_OK;
 }
 
+int stpi_time_chain_step(const stpi_problem *p, const void *f, void *x, void *ws, size_t ws_bytes, int variant,
+                         int reps, void *stream, double *avg_ms, int *product_form) {
+    clear_error();
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    if (!f || !x || !avg_ms) return fail(STPI_EINVAL, "NULL buffer");
+    if (f == x) return fail(STPI_EINVAL, "x must not alias f");
+    if (reps < 1) return fail(STPI_EINVAL, "reps must be >= 1");
+    const WsLayout L = layout_for(p);
+    if (!ws || ws_bytes < L.total) return fail(STPI_EWORKSPACE, "workspace needs %zu bytes", L.total);
+    const Variant *v = choose_variant(p, variant >= 0 ? variant : forced_variant());
+    if (!v) return fail(STPI_EUNSUPPORTED, "no eligible kernel variant");
+    hipStream_t s = (hipStream_t)stream;
+    const DtypeOps *ops = ops_for(p->dtype);
+    DevState *state = (DevState *)((char *)ws + L.state_off);
+    double *partials = (double *)((char *)ws + L.partials_off);
+    void *buf1 = (char *)ws + L.buf_off;
+    // a fixed-count chain long enough that no timed step finds it done
+    const int total = reps + 2;
+    const int pform = chain_pform(v, total);
+    if (product_form) *product_form = pform;
+    rc = enqueue_chain_init(p, ops, x, state, partials, 1, total, 0.0, s, v, f, buf1, pform);
+    if (!rc) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, 1, s, pform);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event create");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "event create");
+    }
+    e = hipEventRecord(e0, s);
+    if (e == hipSuccess) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, reps, s, pform);
+    if (e == hipSuccess && !rc) e = hipEventRecord(e1, s);
+    if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "timed launches");
+    *avg_ms = (double)ms / reps;
+    return STPI_OK;
+}
+
 int stpi_variant_count(int dtype) {
     const DtypeOps *ops = ops_for(dtype);
     return ops ? ops->nvariants : 0;
@@ -600,16 +656,18 @@ namespace stpi {
 // Enqueues start vector, max_iters (step, finalise) pairs and the final
 // normalisation. No host synchronisation.
 int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevState *state, double *partials,
-                       int init, int max_iters, double tol, hipStream_t s, const Variant *v,
-                       const void *f) {
+                       int init, int max_iters, double tol, hipStream_t s, const Variant *v, const void *f,
+                       void *buf1, int pform) {
     const size_t N = (size_t)p->T * p->H * p->W;
     hipError_t e;
     if (init == 1) {
-        if ((e = ops->fill_ones(x, N, s)) != hipSuccess) return hip_fail(e, "fill");
-        if ((e = launch_state_init(state, 1.0 / std::sqrt((double)N), tol, max_iters, 0, s)) != hipSuccess)
+        // product form: the first step stages f itself, the constant start is never stored
+        if (!pform && (e = ops->fill_ones(x, N, s)) != hipSuccess) return hip_fail(e, "fill");
+        if ((e = launch_state_init(state, 1.0 / std::sqrt((double)N), tol, max_iters, 0, pform ? 2 : 0, s)) !=
+            hipSuccess)
             return hip_fail(e, "init");
     } else {
-        if ((e = launch_state_init(state, 1.0, tol, max_iters, init == 2 ? 1 : 0, s)) != hipSuccess)
+        if ((e = launch_state_init(state, 1.0, tol, max_iters, init == 2 ? 1 : 0, 0, s)) != hipSuccess)
             return hip_fail(e, "init");
         if ((e = ops->sumsq(x, N, partials, s)) != hipSuccess) return hip_fail(e, "norm");
         if ((e = launch_state_from_norm(partials, NORM_BLOCKS_HOST, state, s)) != hipSuccess)
@@ -618,12 +676,22 @@ int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevS
     // matrix-core steps scale their operands by max |f| (the iterate is unit)
     if (v && v->PIPE == 3 && (e = ops->bound(N, f, nullptr, &state->ubound, s)) != hipSuccess)
         return hip_fail(e, "operand bound");
+    if (pform && init != 1 && (e = ops->to_product(f, x, buf1, N, state, s)) != hipSuccess)
+        return hip_fail(e, "product-form start");
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init");
     return STPI_OK;
 }
 
+int enqueue_chain_tail(const stpi_problem *p, const DtypeOps *ops, const void *f, void *x, void *buf1,
+                       DevState *state, hipStream_t s, int pform) {
+    const size_t N = (size_t)p->T * p->H * p->W;
+    const hipError_t e =
+        pform ? ops->from_product(x, buf1, f, N, state, s) : ops->normalize(x, buf1, N, state, s);
+    return e == hipSuccess ? STPI_OK : hip_fail(e, "normalize");
+}
+
 int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, void *x, void *buf1, DevState *state,
-                        double *partials, int steps, hipStream_t s) {
+                        double *partials, int steps, hipStream_t s, int pform) {
     hipError_t e;
     FwdLaunch FL;
     std::memset(&FL, 0, sizeof(FL));
@@ -642,8 +710,10 @@ int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, 
     // workgroups of FINAL_THREADS or more finalise the step themselves (the
     // last one to finish), saving a launch per step
     FL.fuse = v->NTHR >= FINAL_THREADS && !fusion_disabled() ? 1 : 0;
+    const FwdLaunchFn launch = pform ? v->launch_p : v->launch;
+    if (!launch) return fail(STPI_EUNSUPPORTED, "variant has no product-form step");
     for (int k = 0; k < steps; ++k) {
-        if ((e = v->launch(FL, s)) != hipSuccess) return hip_fail(e, "step kernel launch");
+        if ((e = launch(FL, s)) != hipSuccess) return hip_fail(e, "step kernel launch");
         if (!FL.fuse && (e = launch_finalize(partials, nb, state, s)) != hipSuccess)
             return hip_fail(e, "finalize launch");
     }
@@ -652,12 +722,10 @@ int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, 
 
 int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
                       void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,
-                      hipStream_t s) {
-    int rc = enqueue_chain_init(p, ops, x, state, partials, init, max_iters, tol, s, v, f);
-    if (!rc) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, max_iters, s);
-    if (rc) return rc;
-    const hipError_t e = ops->normalize(x, buf1, (size_t)p->T * p->H * p->W, state, s);
-    return e == hipSuccess ? STPI_OK : hip_fail(e, "normalize");
+                      hipStream_t s, int pform) {
+    int rc = enqueue_chain_init(p, ops, x, state, partials, init, max_iters, tol, s, v, f, buf1, pform);
+    if (!rc) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, max_iters, s, pform);
+    return rc ? rc : enqueue_chain_tail(p, ops, f, x, buf1, state, s, pform);
 }
 
 }  // namespace stpi

@@ -33,19 +33,25 @@ int segments_for(const Variant &v, const stpi_problem *p);
 constexpr int STPI_NSEG_MAX = 8;  // frame segments per tile at most
 WsLayout layout_for(const stpi_problem *p);
 constexpr int CHAIN_CHUNK = 16;  // steps per replayed chain segment in long tolerance runs
+// pform: run the chain in product form (chain_pform decides).
+int chain_pform(const Variant *v, int max_iters);
 int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevState *state, double *partials,
-                       int init, int max_iters, double tol, hipStream_t s, const Variant *v, const void *f);
+                       int init, int max_iters, double tol, hipStream_t s, const Variant *v, const void *f,
+                       void *buf1, int pform);
 int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, void *x, void *buf1, DevState *state,
-                        double *partials, int steps, hipStream_t s);
+                        double *partials, int steps, hipStream_t s, int pform);
+int enqueue_chain_tail(const stpi_problem *p, const DtypeOps *ops, const void *f, void *x, void *buf1,
+                       DevState *state, hipStream_t s, int pform);
 int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
                       void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,
-                      hipStream_t s);
+                      hipStream_t s, int pform);
 
 // Variant selection overrides (autotuner and tests).
 int forced_variant();
 int tuned_variant(const stpi_problem *p);
 
-hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, int check_rise, hipStream_t st);
+hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iters, int check_rise, int pform,
+                             hipStream_t st);
 hipError_t launch_state_from_norm(const double *partials, int n, DevState *s, hipStream_t st);
 hipError_t launch_clear_word(uint32_t *w, hipStream_t st);
 hipError_t launch_finalize(const double *partials, int n, DevState *s, hipStream_t st);

@@ -230,3 +230,136 @@ def test_matches_plain_variant_at_full_frame(P):
         print("full frame variant", i, vi[:5], f"vs plain {d:.3e}, sampled vs oracle {e:.3e}")
         assert d <= 1e-5 and e <= 1e-5
         assert abs(float(s[0]) / float(sp[0]) - 1.0) <= 2e-5
+
+
+class plain_form:
+    """Selects the plain chain form (both operands staged) for the duration."""
+
+    def __enter__(self):
+        import os
+        self.old = os.environ.get("STPI_NO_PRODUCT")
+        os.environ["STPI_NO_PRODUCT"] = "1"
+
+    def __exit__(self, *a):
+        import os
+        if self.old is None:
+            del os.environ["STPI_NO_PRODUCT"]
+        else:
+            os.environ["STPI_NO_PRODUCT"] = self.old
+
+
+PRODUCT_CASES = [
+    ((5, 37, 70), (2.0, 1.0, 4, 2)),
+    ((13, 40, 131), (4.0, 1.5, 8, 3)),
+    ((12, 35, 150), (5.0, 2.0, 15, 5)),
+    ((2, 129, 67), (3.0, 1.0, 6, 3)),
+    ((1, 1, 1), (1.0, 1.0, 2, 1)),
+    ((3, 18, 20), (2.0, 1.0, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("shape,kp", PRODUCT_CASES)
+@pytest.mark.parametrize("start", ["uniform", "x0"])
+def test_product_form_chain_matches_oracle(P, shape, kp, start):
+    """Chains on the matrix-core variants run in product form (the buffers hold
+    f x 2^-2e): per variant, the result, lambda and the last residual match the
+    oracle's power iteration, from the uniform start and from a given x0."""
+    from paper_2212_08058_amd import _native as N
+    kern = P.Kernel(*kp)
+    rng = np.random.default_rng(sum(shape) + 1)
+    f = rng.uniform(0.05, 1.0, shape).astype(np.float32)
+    x0 = rng.uniform(0.1, 1.0, shape).astype(np.float32) if start == "x0" else None
+    xr, info = oracle.iterate(f, OKf(kern), x0=x0, iters=6)
+    fd = torch.from_numpy(f).to(DEV)
+    ran = 0
+    for i, vi in mfma_variants(N.STPI_F32):
+        if vi[1] < kern.r_t or vi[0] < kern.r_s:
+            continue
+        x = None if x0 is None else torch.from_numpy(x0).to(DEV)
+        with forced(i):
+            ms, pf = P.time_chain_step(fd, kern, reps=1)
+            assert pf
+            xg, r = P.power_iterate(fd, kern, iters=6, x0=x)
+            torch.cuda.synchronize()
+        err = rel_l2(xg.double().cpu().numpy(), xr)
+        print(shape, kp, start, "variant", i, vi[:5], f"rel L2 {err:.3e}", r["residual"], info.residuals[-1])
+        assert r["iters"] == 6 and err <= 1e-5, (i, err)
+        assert abs(r["lambda_"] - info.lambdas[-1]) <= 1e-5 * info.lambdas[-1]
+        assert abs(r["residual"] - info.residuals[-1]) <= 1e-4 * info.residuals[-1] + 1e-6
+        ran += 1
+    assert ran
+
+
+@pytest.mark.parametrize("kind", ["tiny", "huge", "holes", "signed"])
+def test_product_form_value_ranges(P, kind):
+    """The power-of-two factor 2^-2e keeps w = f x in range for f far from 1;
+    voxels with f = 0 (where A x is 0) and f of both signs are exact cases."""
+    kern = P.Kernel(5.0, 2.0, 15, 5)
+    shape = (10, 50, 90)
+    rng = np.random.default_rng(9)
+    f = rng.uniform(0.05, 1.0, shape)
+    if kind == "tiny":
+        f = f * 1e-12
+    elif kind == "huge":
+        f = f * 1e8
+    elif kind == "holes":
+        f[rng.uniform(size=shape) < 0.4] = 0.0
+        f[:, 10:20, :] = 0.0
+    else:
+        f = rng.uniform(-1.0, 1.0, shape)
+    f = f.astype(np.float32)
+    xr, info = oracle.iterate(f, OKf(kern), iters=8)
+    fd = torch.from_numpy(f).to(DEV)
+    assert P.launch_shape(f.shape, kern)["variant"] >= 0
+    _, pf = P.time_chain_step(fd, kern, reps=1)
+    x, r = P.power_iterate(fd, kern, iters=8)
+    torch.cuda.synchronize()
+    err = rel_l2(x.double().cpu().numpy(), xr)
+    print(kind, "product form", pf, f"rel L2 {err:.3e}", r["lambda_"], info.lambdas[-1])
+    assert pf and err <= 1e-5
+    assert abs(r["lambda_"] - info.lambdas[-1]) <= 1e-5 * abs(info.lambdas[-1])
+    if kind == "holes":
+        assert torch.all(x[torch.from_numpy(f).to(DEV) == 0] == 0)
+
+
+def test_product_form_agrees_with_plain_form(P):
+    """Tolerance runs in the two forms: same stopping step, residuals and
+    vectors equal to float rounding (warm start with the rise check too)."""
+    kern = P.Kernel(4.0, 1.5, 8, 3)
+    f, _ = synth.blob_clip(16, 120, 216, 3, 8)
+    fd = torch.from_numpy(f).to(DEV)
+    xp, rp = P.power_iterate(fd, kern, tol=1e-4, max_iters=300)
+    with plain_form():
+        _, pf = P.time_chain_step(fd, kern, reps=1)
+        assert not pf
+        xq, rq = P.power_iterate(fd, kern, tol=1e-4, max_iters=300)
+    torch.cuda.synchronize()
+    print("tolerance runs", rp["iters"], rq["iters"], rp["residual"], rq["residual"])
+    assert abs(rp["iters"] - rq["iters"]) <= 1 and rp["converged"] and rq["converged"]
+    assert float((xp.double() - xq.double()).norm()) <= 1e-4
+    # a warm start x0 close to the answer, with the rise check
+    x0 = (xq + 0.05 * torch.rand_like(xq)).contiguous()
+    xw, rw = P.power_iterate(fd, kern, tol=1e-4, max_iters=300, x0=x0.clone(), rise_check=True)
+    with plain_form():
+        xv, rv = P.power_iterate(fd, kern, tol=1e-4, max_iters=300, x0=x0.clone(), rise_check=True)
+    torch.cuda.synchronize()
+    print("warm runs", rw["iters"], rv["iters"], (rw["r1"], rw["r2"]), (rv["r1"], rv["r2"]))
+    assert abs(rw["iters"] - rv["iters"]) <= 1
+    assert abs(rw["r1"] - rv["r1"]) <= 1e-5 and abs(rw["r2"] - rv["r2"]) <= 1e-5
+    assert float((xw.double() - xv.double()).norm()) <= 1e-4
+
+
+def test_product_form_zero_steps_and_failures(P):
+    """A chain of no steps keeps the plain form (x is the normalised start);
+    f = 0 fails on the first step in either form."""
+    from paper_2212_08058_amd import StpiError
+    kern = P.Kernel(5.0, 2.0, 15, 5)
+    rng = np.random.default_rng(4)
+    f = rng.uniform(0.05, 1.0, (4, 40, 60)).astype(np.float32)
+    x0 = rng.uniform(0.1, 1.0, f.shape).astype(np.float32)
+    x, r = P.power_iterate(torch.from_numpy(f).to(DEV), kern, iters=0, x0=torch.from_numpy(x0).to(DEV))
+    assert r["iters"] == 0
+    np.testing.assert_allclose(x.double().cpu().numpy(), x0 / np.linalg.norm(x0.astype(np.float64)), rtol=1e-6)
+    with pytest.raises(StpiError) as ei:
+        P.power_iterate(torch.zeros((2, 40, 60), device=DEV), kern, iters=3)
+    assert ei.value.status == 3
