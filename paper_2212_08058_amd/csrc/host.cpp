@@ -76,10 +76,14 @@ static double variant_cost(const Variant &v, const stpi_problem *p) {
     const double gx = std::ceil((double)p->W / v.TW), gy = std::ceil((double)p->H / v.TH);
     const double cover = gx * v.TW * gy * v.TH / ((double)p->W * p->H);
     if (v.PIPE == 3) {
-        // matrix-core spatial passes: bound by memory traffic and latency, not
-        // by the space radius; in the units of the tap count above, measured
-        // at 480 x 854 frames as 42 plus two per temporal tap
-        return (42.0 + 2.0 * (2.0 * v.RT + 1)) * cover;
+        // matrix-core spatial passes (chains in product form): bound by memory
+        // traffic and latency, not by the space radius; in the units of the
+        // tap count below, measured at 480 x 854 frames as 42 (margin 16) or
+        // 30 (margin 8) plus two per temporal tap, 10% less where two
+        // workgroups share a CU
+        const double base = v.RS > 8 ? 42.0 : 30.0;
+        const double occ = v.blocks_per_cu() >= 2 ? 0.9 : 1.0;
+        return (base + 2.0 * (2.0 * v.RT + 1)) * cover * occ;
     }
     const double taps = (2.0 * v.RS + 1) * (1.0 + 2.0 * v.RS / v.TW) + (2.0 * v.RS + 1) + (2.0 * v.RT + 1);
     return taps * cover;
