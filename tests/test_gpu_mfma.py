@@ -363,3 +363,37 @@ def test_product_form_zero_steps_and_failures(P):
     with pytest.raises(StpiError) as ei:
         P.power_iterate(torch.zeros((2, 40, 60), device=DEV), kern, iters=3)
     assert ei.value.status == 3
+
+
+@pytest.mark.parametrize("kp", [(5.0, 2.0, 15, 5), (4.0, 1.5, 8, 3)])
+def test_product_form_full_frame(P, kp):
+    """At 16 x 480 x 854 (full frames, the default variant of each radius) a
+    product-form chain agrees with the plain-form chain to float rounding, and
+    sampled outputs of its last step match the oracle applied to the GPU's
+    previous iterate."""
+    from paper_2212_08058_amd import _native as N
+    kern = P.Kernel(*kp)
+    f, _ = synth.blob_clip(16, 480, 854, 5, 6)
+    fd = torch.from_numpy(f).to(DEV)
+    shape = P.launch_shape(f.shape, kern)
+    info = (ctypes.c_int * 9)()
+    N.lib.stpi_variant_info(N.STPI_F32, shape["variant"], info)
+    assert info[8] == 3, list(info)  # the matrix-core loop is the default at both radii
+    x4, _ = P.power_iterate(fd, kern, iters=4)
+    x5, r5 = P.power_iterate(fd, kern, iters=5)
+    with plain_form():
+        xq, rq = P.power_iterate(fd, kern, iters=5)
+    torch.cuda.synchronize()
+    d = rel_l2(x5.double().cpu().numpy(), xq.double().cpu().numpy())
+    print(kp, "variant", list(info), f"product vs plain {d:.3e}", r5["lambda_"], rq["lambda_"])
+    assert d <= 1e-5
+    assert abs(r5["lambda_"] - rq["lambda_"]) <= 1e-5 * rq["lambda_"]
+    assert abs(r5["residual"] - rq["residual"]) <= 1e-4 * rq["residual"] + 1e-6
+    # x5 = A x4 / ||A x4||: sampled outputs against the oracle's A applied to x4
+    idx = np.random.default_rng(8).integers(0, f.size, 300)
+    x4n = x4.double().cpu().numpy()
+    ref = oracle.apply_at(f, x4n, OKf(kern), idx) / r5["lambda_"]
+    got = x5.double().reshape(-1)[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    e = rel_l2(got, ref)
+    print("sampled vs oracle", f"{e:.3e}")
+    assert e <= 1e-5
