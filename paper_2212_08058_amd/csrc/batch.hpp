@@ -49,19 +49,34 @@ struct BatchArgs {
     BatchCtl *ctl;
     double *partials;  // [ntiles][2]
     int ntiles, nclips;
+    int rs;  // the problem's space radius (matrix-core variants)
     Taps<CT> taps;
 };
 
-// PIPE: 1 runs each tile through the software-pipelined tile loop.
+// PIPE: 1 runs each tile through the software-pipelined tile loop, 3 through
+// the matrix-core tile loop in product form (see FwdOpP: every clip's
+// buffers hold f x g, with g from the clip's own bound on |f|).
 template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int PIPE>
 __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
     using CT = typename Compute<ST>::type;
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
     using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
-    __shared__ CT lds[PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS];
+    constexpr int PAD = RS <= 8 ? 8 : 16;
+    static_assert(PIPE != 3 || ((RS == 16 || RS == 8) && sizeof(CT) == 4), "matrix-core batch variants");
+    __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR, PAD>::value : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
     __shared__ double red[NTHR / 64];
     __shared__ int s_tile;
+    __shared__ float tapl[2 * 16 + 1];  // matrix-core variants: space taps centred at 16
     if (a.ctl->done_clips >= (uint32_t)a.nclips) return;
+    if constexpr (PIPE == 3) {
+        if (threadIdx.x < 2 * 16 + 1) {
+            float g = 0.f;
+#pragma unroll
+            for (int i = 0; i < 2 * RS + 1; ++i) g = (int)threadIdx.x == i + 16 - RS ? (float)a.taps.gs[i] : g;
+            tapl[threadIdx.x] = g;
+        }
+        __syncthreads();
+    }
     // Every branch of the tile loop is wave-uniform (readfirstlane values, the
     // wave index), and no branch in it depends on the lane. With the plain
     // form (thread 0 fetches the next tile into LDS, everyone reads it back)
@@ -100,7 +115,26 @@ __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
             op.pbytes = (uint32_t)(op.plane * sizeof(ST));
             const int T = __builtin_amdgcn_readfirstlane(cd.T);
             const int H = __builtin_amdgcn_readfirstlane(cd.H), W = __builtin_amdgcn_readfirstlane(cd.W);
-            if constexpr (PIPE)
+            if constexpr (PIPE == 3) {
+                // the single-clip product-form step's arithmetic, on this clip's state
+                const int e = bound_exponent(__uint_as_float(st_->ubound), PRODUCT_ELIM);
+                const bool first = __builtin_amdgcn_readfirstlane(st_->pform) == 2;
+                FwdOpP<ST> pp;
+                pp.f = op.f;
+                pp.src = first ? op.f : op.src;
+                pp.dst = op.dst;
+                pp.scale = ldexpf(1.f, e - 10);
+                pp.gout = ldexpf(1.f, -2 * e);
+                pp.ginv_out = ldexp(1.0, 2 * e);
+                pp.ginv_in = first ? 1.0 : pp.ginv_out;
+                pp.plane = op.plane;
+                pp.pbytes = op.pbytes;
+                const float umul = (float)(st_->scale * ldexp(1.0, 10 - e) * pp.ginv_in);
+                stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(pp, a.taps, tapl, umul, a.rs, T, 0, T, H, W, tx0, ty0,
+                                                       lds, d1, d2);
+                d1 *= pp.ginv_in * pp.ginv_out;
+                d2 *= pp.ginv_out * pp.ginv_out;
+            } else if constexpr (PIPE)
                 stencil_tile_pipe<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, T, 0, T, H, W, tx0, ty0, lds, d1, d2);
             else
                 stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, T, 0, T, H, W, tx0, ty0, lds, d1, d2);
@@ -137,6 +171,7 @@ __device__ __forceinline__ void finalize_state(DevState *s, double p1, double p2
         s->scale = 1.0 / nz;
         s->cur ^= 1;
         s->iters += 1;
+        if (s->pform == 2) s->pform = 1;
         if (s->iters <= 2) s->first_res[s->iters - 1] = s->residual;
         if (s->tol > 0.0 && s->residual < s->tol) {
             s->converged = 1;
@@ -189,6 +224,9 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t stream) {
     a.partials = L.partials;
     a.ntiles = L.ntiles;
     a.nclips = L.nclips;
+    a.rs = 0;
+    for (int d = 1; d <= 16; ++d)
+        if (L.gs[16 + d] != 0.0) a.rs = d;
     for (int i = 0; i < 2 * 16 + 1; ++i) a.taps.gs[i] = CT(0);
     for (int i = 0; i < 2 * 8 + 1; ++i) a.taps.gt[i] = CT(0);
     for (int d = -RS; d <= RS; ++d) a.taps.gs[d + RS] = (CT)L.gs[d + 16];
@@ -234,6 +272,64 @@ __global__ void batch_sumsq_kernel(const ST *x, const ClipDesc *clips, double *p
     if (threadIdx.x == 0) {
         partials[2 * ((size_t)blockIdx.y * BATCH_NORM_BLOCKS + blockIdx.x)] = s;
         partials[2 * ((size_t)blockIdx.y * BATCH_NORM_BLOCKS + blockIdx.x) + 1] = 0.0;
+    }
+}
+
+// states[clip].ubound = max |f| over the clip (float bits: non-negative
+// floats order as their bit patterns), for the matrix-core variants.
+template <class ST>
+__global__ void batch_bound_kernel(const ST *f, const ClipDesc *clips, DevState *states) {
+    __shared__ float red[256 / 64];
+    const ClipDesc cd = clips[blockIdx.y];
+    const size_t n = (size_t)cd.T * cd.H * cd.W;
+    float m = 0.f;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        m = fmaxf(m, fabsf((float)ld(f + cd.offset + i)));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256 / 64; ++i) m = fmaxf(m, red[i]);
+        atomicMax(&states[blockIdx.y].ubound, __float_as_uint(m));
+    }
+}
+
+// Product-form start from the caller's x, per clip: buffer 1 <- f x g.
+template <class ST>
+__global__ void batch_to_product_kernel(const ST *f, const ST *x, ST *w, const ClipDesc *clips, DevState *states) {
+    using CT = typename Compute<ST>::type;
+    const ClipDesc cd = clips[blockIdx.y];
+    DevState *s = states + blockIdx.y;
+    const CT g = (CT)ldexp(1.0, -2 * bound_exponent(__uint_as_float(s->ubound), PRODUCT_ELIM));
+    const size_t n = (size_t)cd.T * cd.H * cd.W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(w + cd.offset + i, (ld(f + cd.offset + i) * ld(x + cd.offset + i)) * g);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s->cur = 1;
+        s->pform = 1;
+    }
+}
+
+// Final pass of a product-form batch, per clip (as from_product_kernel).
+template <class ST>
+__global__ void batch_from_product_kernel(ST *x, const ST *buf1, const ST *f, const ClipDesc *clips,
+                                          const DevState *states) {
+    using CT = typename Compute<ST>::type;
+    const ClipDesc cd = clips[blockIdx.y];
+    const DevState *s = states + blockIdx.y;
+    const size_t n = (size_t)cd.T * cd.H * cd.W;
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    if (s->pform == 2) {
+        const CT c = (CT)s->scale;
+        for (size_t i = i0; i < n; i += stride) st(x + cd.offset + i, c);
+        return;
+    }
+    const ST *src = (s->cur ? buf1 : x) + cd.offset;
+    const double m = s->scale * ldexp(1.0, 2 * bound_exponent(__uint_as_float(s->ubound), PRODUCT_ELIM));
+    for (size_t i = i0; i < n; i += stride) {
+        const CT fv = ld(f + cd.offset + i);
+        st(x + cd.offset + i, fv != CT(0) ? (CT)((double)ld(src + i) / (double)fv * m) : CT(0));
     }
 }
 

@@ -7,7 +7,7 @@ namespace stpi {
 // Per-clip start: uniform (scale 1/sqrt(N_clip)) or the caller's vector
 // (scale from the per-clip sum of squares, computed afterwards).
 __global__ void batch_init_kernel(DevState *states, const ClipDesc *clips, int nclips, double tol, int max_iters,
-                                  int uniform, BatchCtl *ctl) {
+                                  int uniform, int pform, BatchCtl *ctl) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c == 0) {
         ctl->next_tile = 0u;
@@ -31,7 +31,7 @@ __global__ void batch_init_kernel(DevState *states, const ClipDesc *clips, int n
     s->ubound = 0u;
     s->first_res[0] = s->first_res[1] = 0.0;
     s->check_rise = 0;
-    s->pform = 0;
+    s->pform = uniform && pform ? 2 : 0;
 }
 
 __global__ void batch_state_from_norm_kernel(const double *partials, DevState *states, BatchCtl *ctl) {
@@ -74,9 +74,9 @@ __global__ void batch_finalize_kernel(const double *partials, const ClipDesc *cl
 }
 
 hipError_t launch_batch_init(DevState *states, const ClipDesc *clips, int nclips, double tol, int max_iters,
-                             int uniform, BatchCtl *ctl, hipStream_t st) {
+                             int uniform, int pform, BatchCtl *ctl, hipStream_t st) {
     hipLaunchKernelGGL(batch_init_kernel, dim3((nclips + 63) / 64), dim3(64), 0, st, states, clips, nclips, tol,
-                       max_iters, uniform, ctl);
+                       max_iters, uniform, pform, ctl);
     return hipGetLastError();
 }
 

@@ -39,6 +39,12 @@ struct DtypeOps {
     hipError_t (*batch_sumsq)(const void *x, const ClipDesc *clips, int nclips, double *partials, hipStream_t);
     hipError_t (*batch_normalize)(void *x, const void *buf1, const ClipDesc *clips, const DevState *states,
                                   int nclips, hipStream_t);
+    // matrix-core batch variants (product form): per-clip bound, start and final pass
+    hipError_t (*batch_bound)(const void *f, const ClipDesc *clips, DevState *states, int nclips, hipStream_t);
+    hipError_t (*batch_to_product)(const void *f, const void *x, void *buf1, const ClipDesc *clips, DevState *states,
+                                   int nclips, hipStream_t);
+    hipError_t (*batch_from_product)(void *x, const void *buf1, const void *f, const ClipDesc *clips,
+                                     const DevState *states, int nclips, hipStream_t);
 };
 
 const DtypeOps *dtype_ops_f32();

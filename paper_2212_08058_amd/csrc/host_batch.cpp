@@ -63,7 +63,7 @@ static const BatchVariant *choose_batch_variant(const stpi_problem *proto, const
             for (int i = 0; i < ops->nbatch; ++i) {
                 const BatchVariant &b = ops->batch_variants[i];
                 if (b.RS == fv.RS && b.RT == fv.RT && b.TH == fv.TH && b.TW == fv.TW && b.NTHR == fv.NTHR &&
-                    b.RY == fv.RY && b.QX == fv.QX && b.PIPE == (fv.PIPE ? 1 : 0))
+                    b.RY == fv.RY && b.QX == fv.QX && b.PIPE == (fv.PIPE == 3 ? 3 : (fv.PIPE ? 1 : 0)))
                     return &b;
             }
         }
@@ -74,9 +74,13 @@ static const BatchVariant *choose_batch_variant(const stpi_problem *proto, const
         const BatchVariant &b = ops->batch_variants[i];
         if (b.RS < proto->r_s || b.RT < proto->r_t) continue;
         double cost = 0.0;
+        // the single-clip model (matrix-core variants: product form, see variant_cost)
+        const double taps = b.PIPE == 3 ? ((b.RS > 8 ? 42.0 : 30.0) + 2.0 * (2.0 * b.RT + 1)) *
+                                              (b.blocks_per_cu() >= 2 ? 0.9 : 1.0)
+                                        : (2.0 * b.RS + 1) * (1.0 + 2.0 * b.RS / b.TW) + (2.0 * b.RS + 1) +
+                                              (2.0 * b.RT + 1);
         for (const auto &c : clips) {
             const double gx = std::ceil((double)c.W / b.TW), gy = std::ceil((double)c.H / b.TH);
-            const double taps = (2.0 * b.RS + 1) * (1.0 + 2.0 * b.RS / b.TW) + (2.0 * b.RS + 1) + (2.0 * b.RT + 1);
             cost += gx * gy * b.TW * b.TH * (double)c.T * taps;
         }
         if (cost < best_cost) {
@@ -97,22 +101,34 @@ static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int ini
     double *partials = (double *)(w + P->ws_partials_off);
     void *buf1 = w + P->ws_buf_off;
     hipError_t e;
+    // matrix-core variants run every step in product form (a chain of no steps never launches one)
+    const int pform = P->v->PIPE == 3 && max_iters > 0 ? 1 : 0;
+    auto tail = [&]() -> hipError_t {
+        return pform ? ops->batch_from_product(x, buf1, f, P->d_clips, states, P->nclips, s)
+                     : ops->batch_normalize(x, buf1, P->d_clips, states, P->nclips, s);
+    };
     if (part == 3) {
-        if ((e = ops->batch_normalize(x, buf1, P->d_clips, states, P->nclips, s)) != hipSuccess)
-            return hip_fail(e, "batch normalize");
+        if ((e = tail()) != hipSuccess) return hip_fail(e, "batch normalize");
         return STPI_OK;
     }
     if (part <= 1) {
-        if ((e = launch_batch_init(states, P->d_clips, P->nclips, tol, max_iters, init, ctl, s)) != hipSuccess)
+        if ((e = launch_batch_init(states, P->d_clips, P->nclips, tol, max_iters, init, pform, ctl, s)) != hipSuccess)
             return hip_fail(e, "batch init");
         if (init == 1) {
-            if ((e = ops->batch_fill(x, P->d_clips, P->nclips, s)) != hipSuccess) return hip_fail(e, "batch fill");
+            // product form: the first step stages f itself
+            if (!pform && (e = ops->batch_fill(x, P->d_clips, P->nclips, s)) != hipSuccess)
+                return hip_fail(e, "batch fill");
         } else {
             if ((e = ops->batch_sumsq(x, P->d_clips, P->nclips, partials, s)) != hipSuccess)
                 return hip_fail(e, "batch norm");
             if ((e = launch_batch_state_from_norm(partials, states, P->nclips, ctl, s)) != hipSuccess)
                 return hip_fail(e, "batch norm finalize");
         }
+        if (P->v->PIPE == 3 && (e = ops->batch_bound(f, P->d_clips, states, P->nclips, s)) != hipSuccess)
+            return hip_fail(e, "batch operand bound");
+        if (pform && init != 1 &&
+            (e = ops->batch_to_product(f, x, buf1, P->d_clips, states, P->nclips, s)) != hipSuccess)
+            return hip_fail(e, "batch product-form start");
     }
     BatchLaunch BL;
     std::memset(&BL, 0, sizeof(BL));
@@ -134,8 +150,7 @@ static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int ini
         if ((e = launch_batch_finalize(partials, P->d_clips, states, P->nclips, ctl, s)) != hipSuccess)
             return hip_fail(e, "batch finalize");
     }
-    if (part == 0 && (e = ops->batch_normalize(x, buf1, P->d_clips, states, P->nclips, s)) != hipSuccess)
-        return hip_fail(e, "batch normalize");
+    if (part == 0 && (e = tail()) != hipSuccess) return hip_fail(e, "batch normalize");
     return STPI_OK;
 }
 

@@ -180,3 +180,58 @@ def test_pipelined_batch_variant(P, tmp_path):
                 assert torch.equal(xs, xv), f.shape
     finally:
         B.autotune_clear()
+
+
+@pytest.mark.parametrize("kp,tile", [((4.0, 1.5, 8, 3), "8 3 32 64"), ((5.0, 2.0, 15, 5), "16 5 32 128")])
+def test_batch_matrix_core_product_form(P, tmp_path, kp, tile):
+    """The matrix-core batch variants run in product form (every clip's buffers
+    hold f x g with its own g). A tuned entry for the dominant frame size steers
+    the plan to them, so ragged small clips are covered: per-clip results from
+    the uniform start and from given starts match the oracle, and a clip with
+    f = 0 fails alone."""
+    Pm, B = P
+    kern = Pm.Kernel(*kp)
+    shapes = [(9, 40, 70), (3, 17, 23), (1, 64, 80), (12, 31, 33), (1, 1, 1), (7, 70, 140)]
+    fs = _clips(shapes, seed=50)
+    fs[1] = fs[1] * 1e-6  # a clip on another scale (its own power of two)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = tmp_path / "tune.txt"
+    path.write_text(f"{arch} 0 {kern.r_s} {kern.r_t} 70 140 {tile} 512 16 4 1 3 1.0\n")
+    B.autotune_clear()
+    B.autotune_load(str(path))
+    try:
+        _batch_product_form_checks(Pm, B, kern, shapes, fs)
+    finally:
+        B.autotune_clear()
+
+
+def _batch_product_form_checks(Pm, B, kern, shapes, fs):
+    plan = B.BatchPlan(shapes, kern)
+    info = plan.info()
+    print(info)
+    assert info["PIPE"] == 3
+    f_flat = plan.pack([torch.from_numpy(f).to(DEV) for f in fs])
+    x_flat, res = plan.iterate(f_flat, max_iters=6, tol=0.0)
+    for f, xv, r in zip(fs, plan.views(x_flat), res):
+        xr, oi = oracle.iterate(f, okf(kern), iters=6)
+        err = float(np.linalg.norm(xv.double().cpu().numpy() - xr) / np.linalg.norm(xr))
+        print(f.shape, "uniform", f"{err:.3e}")
+        assert r["iters"] == 6 and err < 1e-5, (f.shape, err)
+        assert abs(r["lambda_"] - oi.lambdas[-1]) < 1e-5 * oi.lambdas[-1]
+    rng = np.random.default_rng(3)
+    x0 = [rng.uniform(0.1, 1, s).astype(np.float32) for s in shapes]
+    x_flat = plan.pack([torch.from_numpy(v).to(DEV) for v in x0])
+    x_flat, res = plan.iterate(f_flat, x_flat, init=0, max_iters=5, tol=0.0)
+    for f, v0, xv in zip(fs, x0, plan.views(x_flat)):
+        xr, _ = oracle.iterate(f, okf(kern), x0=v0, iters=5)
+        err = float(np.linalg.norm(xv.double().cpu().numpy() - xr) / np.linalg.norm(xr))
+        print(f.shape, "x0", f"{err:.3e}")
+        assert err < 1e-5, (f.shape, err)
+    fz = list(fs)
+    fz[2] = np.zeros_like(fs[2])
+    f_flat = plan.pack([torch.from_numpy(f).to(DEV) for f in fz])
+    x_flat, res = plan.iterate(f_flat, max_iters=50, tol=1e-4, check=False)
+    assert res[2]["status"] == 3 and not res[2]["converged"]
+    for k in (0, 3, 5):
+        xr, oi = oracle.iterate(fz[k], okf(kern), tol=1e-4, cap=50)
+        assert abs(res[k]["iters"] - oi.iters) <= 1, (k, res[k]["iters"], oi.iters)
