@@ -203,7 +203,8 @@ int stpi_batch_plan(const stpi_clip *clips, int nclips, float sigma_s, float sig
 /* Device workspace stpi_batch_iterate needs (0 for NULL). */
 size_t stpi_batch_workspace_bytes(const stpi_plan *plan);
 /* info[0..10] = nclips, ntiles, persistent grid size, RS, RT, TH, TW, NTHR, RY, QX,
- * PIPE (1: software-pipelined tile loop). */
+ * PIPE (0: plain tile loop, 1: software-pipelined, 3: matrix-core, whose chains
+ * run in product form as stpi_iterate describes, per clip). */
 int stpi_batch_info(const stpi_plan *plan, int32_t info[11]);
 /* Power iteration of every clip (as stpi_iterate, per clip): x_flat is in/out,
  * init = 1 overwrites each clip with the uniform start, init = 0 uses x_flat.
