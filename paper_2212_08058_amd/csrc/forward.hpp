@@ -196,29 +196,28 @@ struct FwdOp {
     }
 };
 
+// 1 / f from the hardware reciprocal (about one ulp); 0 for f = 0 and for
+// subnormal f (whose outputs are negligible).
+__device__ __forceinline__ float recip_or_zero(float fv) {
+    return fabsf(fv) >= 1.17549435e-38f ? __builtin_amdgcn_rcpf(fv) : 0.f;
+}
+
 // Product form of a chain step (matrix-core tile loop only). The buffers hold
 // w = f x g instead of the iterate x, with g = 2^-2e a power of two from the
 // bound max |f| < 2^e (so w stays in range whatever the scale of f). A step
 // then stages one array, w (times a power of two: w scale 2^(10 + e) =
 // f x_unit 2^(10 - e)), instead of f and x, and its epilogue reads f and w at
 // the outputs as the plain form reads f and x. It stores
-// w_new = (f (2^-S acc)) f g, and the iterate it leaves is defined as
-// x_new = w_new / (f g) (0 where f = 0): p1 = sum x_prev x_new and
-// p2 = sum x_new^2 are taken on that vector, in double (a reciprocal of f
-// per output), so the cosine, the norm and the next step's staged operand
-// all refer to the same vector. The emitted sums leave out the powers of two
-// 1/g: the caller multiplies d1 by ginv_in ginv_out and d2 by ginv_out^2.
-// ginv_in = 1 / g of the input: 1 on the first step of a uniform start, whose
-// input is f itself (w of the constant 1, up to g).
-// 1 / f in double from the hardware reciprocal and one Newton step (far below
-// float rounding, which is all the sums below need: both products of an output
-// use the same value); 0 for f = 0.
-__device__ __forceinline__ double recip_or_zero(float fv) {
-    const double fd = (double)fv;
-    double r = __builtin_amdgcn_rcp(fd);
-    r = fma(r, fma(-fd, r, 1.0), r);
-    return fv != 0.f ? r : 0.0;
-}
+// w_new = (f (2^-S acc)) f g; the iterate is w / (f g) (0 where f = 0). The
+// sums are taken on its float image x~ = fl(w rcp(f)) / g: p2 = sum x~_new^2
+// and p1 = sum x~_prev x~_new, products exact in double. The next step forms
+// x~_prev from the same stored w and f, so it is bitwise this step's x~_new:
+// the scale, the cosine and the norm all refer to one vector, which differs
+// from the staged iterate by float rounding per element (the residual keeps
+// float-level accuracy near convergence). The emitted sums leave out the
+// powers of two 1/g: the caller multiplies d1 by ginv_in ginv_out and d2 by
+// ginv_out^2. ginv_in = 1 / g of the input: 1 on the first step of a uniform
+// start, whose input is f itself (w of the constant 1, up to g).
 
 template <class ST>
 struct FwdOpP {
@@ -284,9 +283,9 @@ struct FwdOpP {
                 const CT fv = raw.f[i][q];
                 const CT z = scale * (fv * acc[i][q]);
                 w[q] = (z * fv) * gout;
-                const double r = recip_or_zero(fv);
-                const double xn = (double)IO::rounded(w[q]) * r;
-                const double xp = (double)raw.u[i][q] * r;
+                const CT r = recip_or_zero(fv);
+                const double xn = (double)(IO::rounded(w[q]) * r);
+                const double xp = (double)(raw.u[i][q] * r);
                 d2 = fma(xn, xn, d2);
                 d1 = fma(xp, xn, d1);
             }
