@@ -397,3 +397,33 @@ def test_product_form_full_frame(P, kp):
     e = rel_l2(got, ref)
     print("sampled vs oracle", f"{e:.3e}")
     assert e <= 1e-5
+
+
+def test_product_form_bf16_chain(P):
+    """BF16 storage in product form (w = f x g stored in bfloat16): the chain
+    matches the oracle iterating on the bfloat16-rounded f to the storage
+    precision, and the plain form to the same bar."""
+    from paper_2212_08058_amd import _native as N
+    kern = P.Kernel(5.0, 2.0, 15, 5)
+    rng = np.random.default_rng(12)
+    f = torch.from_numpy(rng.uniform(0.05, 1.0, (9, 70, 133)).astype(np.float32)).to(torch.bfloat16)
+    fd = f.to(DEV)
+    xr, info = oracle.iterate(f.double().numpy(), OKf(kern), iters=6)
+    ran = 0
+    for i, vi in mfma_variants(N.STPI_BF16):
+        if vi[1] < kern.r_t or vi[0] < kern.r_s:
+            continue
+        with forced(i):
+            _, pf = P.time_chain_step(fd, kern, reps=1)
+            x, r = P.power_iterate(fd, kern, iters=6)
+            with plain_form():
+                xq, _ = P.power_iterate(fd, kern, iters=6)
+            torch.cuda.synchronize()
+        err = rel_l2(x.double().cpu().numpy(), xr)
+        errq = rel_l2(xq.double().cpu().numpy(), xr)
+        print("bf16 variant", i, vi[:5], "product form", pf, f"rel L2 {err:.3e}, plain form {errq:.3e}",
+              r["lambda_"], info.lambdas[-1])
+        assert pf and err <= 2.0 ** -8 and errq <= 2.0 ** -8
+        assert abs(r["lambda_"] - info.lambdas[-1]) <= 2.0 ** -8 * info.lambdas[-1]
+        ran += 1
+    assert ran
