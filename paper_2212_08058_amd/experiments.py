@@ -203,7 +203,7 @@ def warm_start_experiment(n_train=2000, n_eval=200, epochs=2, train_shape=(16, 2
     out["coarse"]["tol"] = coarse_tol
 
     if batched:
-        # batched: plain (uniform) vs two-level + net_tl starts, all evaluation clips in one plan
+        # batched: plain (uniform) vs two-level and two-level + net_tl starts, all evaluation clips in one plan
         plan = B.BatchPlan([eval_shape] * n_eval, kern)
         f_flat = plan.pack(eval_fs)
         x_flat = plan.empty(device)
@@ -215,30 +215,31 @@ def warm_start_experiment(n_train=2000, n_eval=200, epochs=2, train_shape=(16, 2
         _, res_p = plan.iterate(f_flat, x_flat, max_iters=cap, tol=tol, ws=bws, stream=s, check=False)
         _sync()
         t_bp = time.perf_counter() - t0
-        for rep in range(2):  # first repetition captures the graphs
-            _sync()
-            t0 = time.perf_counter()
-            with torch.cuda.stream(s):
-                for f, xv in zip(eval_fs, plan.views(x_flat)):
-                    u0 = tl.start(f, s)
-                    xv.copy_(nets["net_tl"].x0(tl.net_input(u0)))
-            # fallback rule per clip: two single steps, restart from uniform where r2 > r1
-            _, r1 = plan.iterate(f_flat, x_flat, init=0, max_iters=1, tol=0.0, ws=bws, stream=s, check=False)
-            _, r2 = plan.iterate(f_flat, x_flat, init=0, max_iters=1, tol=0.0, ws=bws, stream=s, check=False)
-            nfb = 0
-            with torch.cuda.stream(s):
-                for a, b, xv in zip(r1, r2, plan.views(x_flat)):
-                    if not (b["residual"] <= a["residual"]):
-                        xv.fill_(1.0)
-                        nfb += 1
-            _, res_w = plan.iterate(f_flat, x_flat, init=0, max_iters=cap - 2, tol=tol, ws=bws, stream=s,
-                                    check=False)
-            _sync()
-            t_bw = time.perf_counter() - t0
-        out["batched"] = dict(plain_seconds=t_bp, warm_seconds=t_bw, ratio_vs_batched_plain=t_bp / t_bw,
-                              ratio_vs_single_plain=sum(times["plain"]) / t_bw, fallbacks=nfb,
-                              plain_iters_median=float(np.median([r["iters"] for r in res_p])),
-                              warm_iters_median=float(np.median([r["iters"] for r in res_w])) + 2,
-                              unconverged_plain=sum(not r["converged"] for r in res_p),
-                              unconverged_warm=sum(not r["converged"] for r in res_w))
+        out["batched"] = dict(plain_seconds=t_bp, plain_iters_median=float(np.median([r["iters"] for r in res_p])),
+                              unconverged_plain=sum(not r["converged"] for r in res_p))
+        for mode in ("two_level", "two_level_net"):
+            for rep in range(2):  # first repetition captures the graphs
+                _sync()
+                t0 = time.perf_counter()
+                with torch.cuda.stream(s):
+                    for f, xv in zip(eval_fs, plan.views(x_flat)):
+                        u0 = tl.start(f, s)
+                        xv.copy_(nets["net_tl"].x0(tl.net_input(u0)) if mode == "two_level_net" else u0)
+                # fallback rule per clip: two single steps, restart from uniform where r2 > r1
+                _, r1 = plan.iterate(f_flat, x_flat, init=0, max_iters=1, tol=0.0, ws=bws, stream=s, check=False)
+                _, r2 = plan.iterate(f_flat, x_flat, init=0, max_iters=1, tol=0.0, ws=bws, stream=s, check=False)
+                nfb = 0
+                with torch.cuda.stream(s):
+                    for a, b, xv in zip(r1, r2, plan.views(x_flat)):
+                        if not (b["residual"] <= a["residual"]):
+                            xv.fill_(1.0)
+                            nfb += 1
+                _, res_w = plan.iterate(f_flat, x_flat, init=0, max_iters=cap - 2, tol=tol, ws=bws, stream=s,
+                                        check=False)
+                _sync()
+                t_bw = time.perf_counter() - t0
+            out["batched"][mode] = dict(seconds=t_bw, ratio_vs_batched_plain=t_bp / t_bw,
+                                        ratio_vs_single_plain=sum(times["plain"]) / t_bw, fallbacks=nfb,
+                                        iters_median=float(np.median([r["iters"] for r in res_w])) + 2,
+                                        unconverged=sum(not r["converged"] for r in res_w))
     return out
