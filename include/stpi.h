@@ -216,8 +216,9 @@ int stpi_batch_iterate(stpi_plan *plan, const void *f_flat, void *x_flat, int in
 void stpi_plan_destroy(stpi_plan *plan);
 
 /* ---- autotuner -------------------------------------------------------------
- * stpi_autotune times every compiled variant eligible for `p` (reps launches
- * each, HIP events, on temporary device buffers it allocates and frees),
+ * stpi_autotune times every compiled variant eligible for `p` as a step of an
+ * iteration chain (stpi_time_chain_step, reps steps each, on temporary device
+ * buffers it allocates and frees),
  * records the fastest for (device arch, dtype, r_s, r_t, H, W), and writes the
  * whole table to cache_path (if not NULL). Later calls for that key use the
  * recorded variant. Synchronises the device. */

@@ -121,23 +121,22 @@ int stpi_autotune(const stpi_problem *p, const char *cache_path, int reps, int32
     const size_t N = (size_t)p->T * p->H * p->W;
     const size_t bytes = N * ops->elem;
     const size_t wsb = stpi_workspace_bytes(p);
-    void *f = nullptr, *x = nullptr, *z = nullptr, *ws = nullptr;
+    void *f = nullptr, *x = nullptr, *ws = nullptr;
     hipError_t e = hipMalloc(&f, bytes);
     if (e == hipSuccess) e = hipMalloc(&x, bytes);
-    if (e == hipSuccess) e = hipMalloc(&z, bytes);
     if (e == hipSuccess) e = hipMalloc(&ws, wsb);
     if (e == hipSuccess) e = ops->fill_ones(f, N, nullptr);
-    if (e == hipSuccess) e = ops->fill_ones(x, N, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     int best = -1;
     double best_t = 1e300;
     if (e == hipSuccess) {
+        // each variant as an iteration chain runs it (its product form where it has one)
         for (int i = 0; i < ops->nvariants && rc == STPI_OK; ++i) {
             const Variant &v = ops->variants[i];
             if (v.RS < p->r_s || v.RT < p->r_t) continue;
             double ms = 0.0;
-            rc = stpi_time_step(p, f, x, z, ws, wsb, i, 1, nullptr, &ms);  // warm-up
-            if (rc == STPI_OK) rc = stpi_time_step(p, f, x, z, ws, wsb, i, reps, nullptr, &ms);
+            rc = stpi_time_chain_step(p, f, x, ws, wsb, i, 1, nullptr, &ms, nullptr);  // warm-up
+            if (rc == STPI_OK) rc = stpi_time_chain_step(p, f, x, ws, wsb, i, reps, nullptr, &ms, nullptr);
             if (rc == STPI_OK && ms < best_t) {
                 best_t = ms;
                 best = i;
@@ -146,7 +145,6 @@ int stpi_autotune(const stpi_problem *p, const char *cache_path, int reps, int32
     }
     if (f) (void)hipFree(f);
     if (x) (void)hipFree(x);
-    if (z) (void)hipFree(z);
     if (ws) (void)hipFree(ws);
     if (e != hipSuccess) return hip_fail(e, "autotune buffers");
     if (rc) return rc;
