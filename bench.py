@@ -111,8 +111,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(clips shard across GPUs without per-iteration communication; see the design notes). "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(clips would shard across GPUs without per-iteration communication). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
