@@ -71,6 +71,13 @@ def test_invalid_calls_fail_before_any_launch(native):
     big = _prob(native, r_s=20)
     rc = native.lib.stpi_iterate(ctypes.byref(big), 16, 32, 1, 1, 0.0, 64, 1 << 30, ctypes.byref(res), None)
     assert rc == native.STPI_EUNSUPPORTED
+    # the chain-step timer validates before touching the device
+    ms, pf = ctypes.c_double(), ctypes.c_int()
+    tc = native.lib.stpi_time_chain_step
+    assert tc(ctypes.byref(p), None, 32, 64, 1 << 30, -1, 5, None, ctypes.byref(ms), None) == native.STPI_EINVAL
+    assert tc(ctypes.byref(p), 16, 16, 64, 1 << 30, -1, 5, None, ctypes.byref(ms), None) == native.STPI_EINVAL
+    assert tc(ctypes.byref(p), 16, 32, 64, 1 << 30, -1, 0, None, ctypes.byref(ms), ctypes.byref(pf)) == native.STPI_EINVAL
+    assert tc(ctypes.byref(p), 16, 32, 64, 0, -1, 5, None, ctypes.byref(ms), None) == native.STPI_EWORKSPACE
 
 
 def test_grid_transfer_rejects_bad_arguments(native):
