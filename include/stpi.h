@@ -13,7 +13,7 @@
  * Gaussian affinity in its first-order form (Sec. 3, Eq. 2) with alpha = 0 and
  * the unary feature taken as f; the neighbourhood sum of Eq. 4 is evaluated as
  * the first 3D convolution term of Eq. 7, split into three 1D passes (the
- * separable filter of Sec. 4.3), followed by the global L2 normalisation of
+ * separable filter of Sec. 4, "Computational complexity"), followed by the global L2 normalisation of
  * Eq. 8. The kernel is not normalised: G_ii = 1.
  *
  * Conventions for every entry point:
@@ -303,7 +303,7 @@ int stpi_adamw(int64_t n, int dtype, void *w, const void *g, void *m, void *v, v
  * between objects far apart; an iteration on a coarse grid (cheap: sy^2 st
  * times fewer voxels) resolves them, and its eigenvector, carried back to the
  * full grid, starts the full iteration. Not part of the paper; its own warm
- * start reuses the previous sub-window's solution (Sec. 4.4).
+ * start reuses the previous sub-window's solution (Sec. 4, "Online vs Offline processing").
  * Coarse size: Tc = ceil(T / st), Hc = ceil(H / sy), Wc = ceil(W / sy). */
 /* out[tc][yc][xc] = mean of in[t][y][x] over the voxels of block
  * [tc st, (tc+1) st) x [yc sy, (yc+1) sy) x [xc sy, (xc+1) sy) inside the
@@ -322,7 +322,7 @@ int stpi_upsample(int T, int H, int W, int sy, int st, int mode, int dtype, cons
 /* ---- learned warm start ------------------------------------------------------
  * A small 3D convolutional network predicts the start vector of the iteration
  * from f (the paper's own warm start is the previous sub-window's solution,
- * Sec. 4.4; here a network trained on eigenvectors of the plain method plays
+ * Sec. 4, "Online vs Offline processing"; here a network trained on eigenvectors of the plain method plays
  * that role). Four 'same' 3x3x3 convolutions with zero padding and bias,
  * 1 -> 16 -> 16 -> 16 -> 1 channels, ReLU between layers; bfloat16 weights and
  * activations, FP32 accumulation; the 16 -> 16 layers run on the matrix cores.

@@ -26,7 +26,7 @@ What it computes, each function citing the passage it restates:
 * ``downsample``/``upsample``/``coarse_kernel``: grid transfer for the
   two-level start (box average; nearest-cell or cell-centred trilinear
   prolongation) and the coarse filter. Not from the paper (its warm start is
-  the previous sub-window's solution, Sec. 4.4): restated from the textbook
+  the previous sub-window's solution, Sec. 4, "Online vs Offline processing"): restated from the textbook
   definitions, each per output voxel.
 
 Readings of points the paper leaves open (unnormalised Gaussian with G(0)=1,

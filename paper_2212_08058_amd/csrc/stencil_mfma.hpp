@@ -1,7 +1,7 @@
 // Matrix-core form of the step's two spatial passes (space radius up to 16).
 //
 // A 1D Gaussian pass over a tile is a product with a banded Toeplitz matrix,
-// so both spatial passes of the separable filter (Sec. 4.3's 1D passes,
+// so both spatial passes of the separable filter (the 1D passes of Sec. 4, "Computational complexity",
 // along y then x) run as v_mfma_f32_16x16x32_f16 products. To keep
 // float accuracy, every operand is split into two half-precision parts,
 // a = a_hi + a_lo with a_hi = fp16(a) and a_lo = fp16(a - a_hi) (about 22

@@ -240,4 +240,14 @@ def test_channel_training_full_size(P):
     a = torch.softmax(w.detach(), 0).cpu().numpy()
     print("losses", losses, "softmax weights", a)
     assert all(b < a_ for a_, b in zip(losses, losses[1:]))
-    assert abs(a.sum() - 1.0) < 1e-12
+    # the weights the library learned lower the FP64 oracle's own objective
+    # (the BCE reading prefers the salt-and-pepper channels 3-7 on this stack,
+    # so the weights are checked against the objective, not against the paper's
+    # clean-channel preference, which belongs to its Focal-Dice objective)
+    w_end = w.detach().cpu().numpy()
+    l_end, _, _ = oracle.loss_and_grad(fc.astype(np.float64), w_end, gt, okf(kern), c["iters"])
+    print(f"oracle loss at the learned weights {l_end:.6f} vs {lref:.6f} at the start")
+    assert l_end < lref
+    with torch.no_grad():
+        l_gpu = float(learn.bce(learn.spectral_iterate(fcd, w.detach(), kern, c["iters"], c["ckpt"]), gtd))
+    assert abs(l_gpu - l_end) < 1e-4 * l_end

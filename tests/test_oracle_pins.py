@@ -475,3 +475,74 @@ def test_upsample_multiplies_by_field(oracle_mod):
 def test_coarse_kernel_units(oracle_mod):
     k = oracle_mod.coarse_kernel(oracle_mod.Kernel(4.0, 1.5, 8, 3), 4, 2)
     assert (k.sigma_s, k.sigma_t, k.r_s, k.r_t) == (1.0, 0.75, 2, 2)
+
+
+# ---- pins for the training tape, the bf16 net mirror and the net loss ----------
+
+@pytest.mark.parametrize("x0", [None, "random"])
+def test_forward_train_matches_iterate_trajectory(x0):
+    """forward_train's tape is the plain iteration: its iterates and norms are
+    iterate(keep=True)'s trajectory and lambdas (which the dense Perron,
+    Kronecker and sine pins fix), and each saved v is G (f x_k), checked
+    against scipy's zero-padded correlation (Eq. 4 split as f * (G * (f x)))."""
+    rng = np.random.default_rng(21)
+    k = Kernel(1.7, 0.9, 3, 2)
+    f = _rand_volume(rng, 5, 9, 11)
+    start = None if x0 is None else rng.uniform(0.1, 1.0, f.shape)
+    tape = oracle.forward_train(f, k, 6, x0=start)
+    _, info, traj = oracle.iterate(f, k, x0=start, iters=6, keep=True)
+    assert len(tape["xs"]) == len(traj) == 7
+    for a, b in zip(tape["xs"], traj):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(tape["ns"], info.lambdas, rtol=1e-13, atol=0)
+    G3 = np.einsum("a,b,c->abc", _g1(k.r_t, k.sigma_t), _g1(k.r_s, k.sigma_s), _g1(k.r_s, k.sigma_s))
+    for j, v in enumerate(tape["vs"]):
+        ref = ndimage.correlate(f * traj[j], G3, mode="constant", cval=0.0)
+        np.testing.assert_allclose(v, ref, rtol=1e-12, atol=1e-14)
+        # x_{k+1} = f v / ||f v||
+        np.testing.assert_allclose(tape["xs"][j + 1], f * v / np.linalg.norm(f * v), rtol=0, atol=1e-14)
+
+
+def test_net_forward_bf16_mirror_against_torch():
+    """The bf16 mirror rounds the weights and every layer's input activation to
+    bfloat16 (torch's own float32 -> bfloat16 cast) and convolves in FP64 with
+    unrounded outputs, bias added in FP64, ReLU between layers."""
+    import torch
+    rng = np.random.default_rng(22)
+    chans = oracle.NET_CHANNELS
+    params = [(rng.standard_normal((chans[i + 1], chans[i], 3, 3, 3)) * 0.3, rng.standard_normal(chans[i + 1]) * 0.1)
+              for i in range(4)]
+    f = rng.uniform(0, 1, (3, 6, 7))
+    y, _ = oracle.net_forward(f, params, bf16=True)
+
+    def q(a):  # torch bfloat16 rounding, back to float64
+        return a.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    h = torch.tensor(f)[None, None]
+    for li, (w, b) in enumerate(params):
+        h = torch.nn.functional.conv3d(q(h), q(torch.tensor(w)), torch.tensor(b), padding=1)
+        if li < 3:
+            h = torch.relu(h)
+    np.testing.assert_allclose(y, h[0, 0].numpy(), rtol=1e-12, atol=1e-12)
+    # the mirror differs from the unrounded net (so the rounding is really applied)
+    y_exact, _ = oracle.net_forward(f, params, bf16=False)
+    assert np.max(np.abs(y - y_exact)) > 1e-4
+
+
+def test_net_loss_and_warm_start_against_torch():
+    """net_loss is torch's mse_loss against x* sqrt(N), with torch's gradient;
+    warm_start_x0 is torch's normalize(relu(y) + eps)."""
+    import torch
+    rng = np.random.default_rng(23)
+    y = rng.standard_normal((3, 5, 4))
+    xs = rng.uniform(0, 1, y.shape)
+    xs /= np.linalg.norm(xs)
+    loss, g = oracle.net_loss(y, xs)
+    yt = torch.tensor(y, requires_grad=True)
+    lt = torch.nn.functional.mse_loss(yt, torch.tensor(xs) * math.sqrt(y.size))
+    lt.backward()
+    assert abs(loss - lt.item()) <= 1e-14 * max(1.0, lt.item())
+    np.testing.assert_allclose(g, yt.grad.numpy(), rtol=1e-13, atol=1e-16)
+    x0 = oracle.warm_start_x0(y, eps=1e-3)
+    ref = torch.nn.functional.normalize((torch.relu(torch.tensor(y)) + 1e-3).reshape(-1), dim=0).reshape(y.shape)
+    np.testing.assert_allclose(x0, ref.numpy(), rtol=1e-14, atol=1e-16)
