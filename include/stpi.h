@@ -105,6 +105,24 @@ size_t stpi_workspace_bytes(const stpi_problem *p);
 int stpi_step(const stpi_problem *p, const void *f, const void *x, double x_scale, void *z,
               double *d_sums, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): stpi_step
+ * without a workspace argument. Same arguments, results and errors as
+ * stpi_step; the block partial sums and the operand-bound word live in a
+ * library-owned device array of STPI_NOALLOC_SCRATCH_BYTES per GPU, held
+ * until the process ends. The call allocates nothing (no hipMalloc, no
+ * library allocation). Problems whose launch needs more scratch than that
+ * (stpi_step_noalloc_scratch_bytes(p) > STPI_NOALLOC_SCRATCH_BYTES, frames
+ * of tens of millions of pixels) get STPI_EUNSUPPORTED before any launch.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * device (different streams, or host threads without ordering) race and
+ * must be serialised by the caller. The array keeps the last call's
+ * contents; the call clears what must start at zero itself. */
+#define STPI_NOALLOC_SCRATCH_BYTES (1 << 20)
+size_t stpi_step_noalloc_scratch_bytes(const stpi_problem *p);
+int stpi_step_noalloc(const stpi_problem *p, const void *f, const void *x, double x_scale, void *z,
+                      double *d_sums, void *stream);
+
 /* Power iteration (Eq. 4 + Eq. 8, outer loop of Alg. 1).
  * x (device, in/out): with init = 1 it is overwritten by the uniform start
  * 1/sqrt(N); with init = 0 it holds the caller's start (normalised first,

@@ -59,6 +59,8 @@ PROTOTYPES = [
     ("stpi_version", ctypes.c_char_p, []),
     ("stpi_workspace_bytes", _sz, [_PP]),
     ("stpi_step", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_step_noalloc_scratch_bytes", _sz, [_PP]),
+    ("stpi_step_noalloc", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     ("stpi_iterate", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _sz, _RP, _vp]),
     ("stpi_variant_count", ctypes.c_int, [ctypes.c_int]),
     ("stpi_variant_info", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
@@ -104,6 +106,7 @@ PROTOTYPES = [
 
 AUX_WS_BYTES = 512 * 1024
 MAX_CHANNELS = 64
+STPI_NOALLOC_SCRATCH_BYTES = 1 << 20
 
 
 class StpiError(RuntimeError):

@@ -85,6 +85,21 @@ def step(f: torch.Tensor, x: torch.Tensor, k: Kernel, x_scale: float = 1.0, z: t
     return z, sums
 
 
+def step_noalloc(f: torch.Tensor, x: torch.Tensor, k: Kernel, x_scale: float, z: torch.Tensor,
+                 sums: torch.Tensor, stream=None):
+    """stpi_step_noalloc: stpi_step with the library's per-device scratch
+    instead of a workspace; z and sums (2 device doubles) are the caller's."""
+    _check_volume("f", f)
+    _check_volume("x", x, f.shape, f.dtype)
+    _check_volume("z", z, f.shape, f.dtype)
+    if sums.dtype != torch.float64 or sums.numel() < 2 or not sums.is_cuda:
+        raise ValueError("sums must be a device float64 tensor of 2 elements")
+    p = problem_for(f.shape, k, f.dtype)
+    N.check(N.lib.stpi_step_noalloc(ctypes.byref(p), f.data_ptr(), x.data_ptr(), float(x_scale), z.data_ptr(),
+                                    sums.data_ptr(), _stream_ptr(stream)))
+    return z, sums
+
+
 def power_iterate(f: torch.Tensor, k: Kernel, iters: int | None = None, tol: float | None = None,
                   max_iters: int = 1000, x0: torch.Tensor | None = None, x: torch.Tensor | None = None,
                   ws: torch.Tensor | None = None, stream=None, check: bool = True, wait: bool = True,

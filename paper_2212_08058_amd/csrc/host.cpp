@@ -425,6 +425,97 @@ int stpi_step(const stpi_problem *p, const void *f, const void *x, double x_scal
     return STPI_OK;
 }
 
+}  // extern "C"
+
+namespace stpi {
+
+// Scratch of stpi_step_noalloc: the operand-bound word (first 256 bytes) and
+// the step kernel's per-workgroup partial sums. Each device holds its own copy
+// for the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (the array's name on the host is
+// a stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[STPI_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static void *g_scratch_ptr[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// The scratch address on the current device (looked up once per device).
+static int scratch_for_current_device(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(STPI_EUNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(STPI_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return STPI_OK;
+}
+
+}  // namespace stpi
+
+extern "C" {
+
+size_t stpi_step_noalloc_scratch_bytes(const stpi_problem *p) {
+    if (validate_problem(p) != STPI_OK) return 0;
+    const Variant *v = choose_variant(p, forced_variant());
+    if (!v) return 0;
+    return 256 + (size_t)grid_blocks(*v, p) * 2 * sizeof(double);
+}
+
+int stpi_step_noalloc(const stpi_problem *p, const void *f, const void *x, double x_scale, void *z, double *d_sums,
+                      void *stream) {
+    clear_error();
+    int rc = validate_problem(p);
+    if (rc) return rc;
+    if (!f || !x || !z || !d_sums) return fail(STPI_EINVAL, "NULL buffer");
+    if (z == f || z == x) return fail(STPI_EINVAL, "z must not alias f or x");
+    if (!std::isfinite(x_scale)) return fail(STPI_EINVAL, "x_scale must be finite");
+    const Variant *v = choose_variant(p, forced_variant());
+    if (!v) return fail(STPI_EUNSUPPORTED, "no compiled kernel for radii (%d, %d)", p->r_s, p->r_t);
+    const int nunits = grid_blocks(*v, p);
+    const size_t need = 256 + (size_t)nunits * 2 * sizeof(double);
+    if (need > (size_t)STPI_NOALLOC_SCRATCH_BYTES)
+        return fail(STPI_EUNSUPPORTED, "frame %dx%d needs %zu bytes of step scratch, above the %d-byte limit", p->H,
+                    p->W, need, STPI_NOALLOC_SCRATCH_BYTES);
+    void *scr = nullptr;
+    if ((rc = scratch_for_current_device(&scr)) != STPI_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    FwdLaunch FL;
+    std::memset(&FL, 0, sizeof(FL));
+    FL.f = f;
+    FL.buf0 = const_cast<void *>(x);
+    FL.buf1 = z;
+    FL.state = nullptr;
+    FL.x_scale = x_scale;
+    FL.partials = (double *)((char *)scr + 256);
+    FL.T = p->T;
+    FL.H = p->H;
+    FL.W = p->W;
+    FL.nseg = segments_for(*v, p);
+    make_taps(p, FL.gs, FL.gt);
+    hipError_t e = hipSuccess;
+    if (v->PIPE == 3) {
+        // the bound word is cleared by a kernel and raised by the bound pass
+        uint32_t *w = (uint32_t *)scr;
+        FL.ubound = w;
+        e = launch_clear_word(w, s);
+        if (e == hipSuccess) e = ops_for(p->dtype)->bound((size_t)p->T * p->H * p->W, f, x, w, s);
+        if (e != hipSuccess) return hip_fail(e, "operand bound");
+    }
+    e = v->launch(FL, s);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+    e = launch_step_sums(FL.partials, nunits, x_scale, d_sums, s);
+    if (e != hipSuccess) return hip_fail(e, "step sums launch");
+    return STPI_OK;
+}
+
 int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int max_iters, double tol, void *ws,
                  size_t ws_bytes, stpi_result *out, void *stream) {
     clear_error();
