@@ -117,23 +117,29 @@ __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
             const int H = __builtin_amdgcn_readfirstlane(cd.H), W = __builtin_amdgcn_readfirstlane(cd.W);
             if constexpr (PIPE == 3) {
                 // the single-clip product-form step's arithmetic, on this clip's state
-                const int e = bound_exponent(__uint_as_float(st_->ubound), PRODUCT_ELIM);
+                const float fb = __uint_as_float(st_->ubound);
+                const int e = bound_exponent(fb, PRODUCT_ELIM);
                 const bool first = __builtin_amdgcn_readfirstlane(st_->pform) == 2;
                 FwdOpP<ST> pp;
                 pp.f = op.f;
                 pp.src = first ? op.f : op.src;
                 pp.dst = op.dst;
-                pp.scale = ldexpf(1.f, e - 10);
                 pp.gout = ldexpf(1.f, -2 * e);
                 pp.ginv_out = ldexp(1.0, 2 * e);
                 pp.ginv_in = first ? 1.0 : pp.ginv_out;
                 pp.plane = op.plane;
                 pp.pbytes = op.pbytes;
-                const float umul = (float)(st_->scale * ldexp(1.0, 10 - e) * pp.ginv_in);
+                // staging power of two from the input's own maximum (as the single-clip step)
+                const float win = first ? fb : __uint_as_float(st_->wmax[cur]);
+                const int ein = bound_exponent((float)((double)win * st_->scale * pp.ginv_in), 100);
+                pp.scale = ldexpf(1.f, ein - 10);
+                const float umul = (float)(st_->scale * ldexp(1.0, 10 - ein) * pp.ginv_in);
                 stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(pp, a.taps, tapl, umul, a.rs, T, 0, T, H, W, tx0, ty0,
                                                        lds, d1, d2);
                 d1 *= pp.ginv_in * pp.ginv_out;
                 d2 *= pp.ginv_out * pp.ginv_out;
+                const float m = block_max<NTHR>(pp.wmax, reinterpret_cast<float *>(red));
+                if (threadIdx.x == 0 && m > 0.f) atomicMax(&a.states[clip].wmax[cur ^ 1], __float_as_uint(m));
             } else if constexpr (PIPE)
                 stencil_tile_pipe<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, T, 0, T, H, W, tx0, ty0, lds, d1, d2);
             else
@@ -169,6 +175,7 @@ __device__ __forceinline__ void finalize_state(DevState *s, double p1, double p2
         s->lambda = nz;
         s->residual = sqrt(fmax(0.0, 2.0 - 2.0 * c));
         s->scale = 1.0 / nz;
+        s->wmax[s->cur] = 0u;  // the buffer just read is the next step's output
         s->cur ^= 1;
         s->iters += 1;
         if (s->pform == 2) s->pform = 1;
@@ -299,12 +306,19 @@ __global__ void batch_bound_kernel(const ST *f, const ClipDesc *clips, DevState 
 template <class ST>
 __global__ void batch_to_product_kernel(const ST *f, const ST *x, ST *w, const ClipDesc *clips, DevState *states) {
     using CT = typename Compute<ST>::type;
+    __shared__ float red[256 / 64];
     const ClipDesc cd = clips[blockIdx.y];
     DevState *s = states + blockIdx.y;
     const CT g = (CT)ldexp(1.0, -2 * bound_exponent(__uint_as_float(s->ubound), PRODUCT_ELIM));
     const size_t n = (size_t)cd.T * cd.H * cd.W;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        st(w + cd.offset + i, (ld(f + cd.offset + i) * ld(x + cd.offset + i)) * g);
+    float m = 0.f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const CT v = (ld(f + cd.offset + i) * ld(x + cd.offset + i)) * g;
+        st(w + cd.offset + i, v);
+        m = fmaxf(m, fabsf((float)stored_value(w + cd.offset + i, v)));
+    }
+    m = block_max<256>(m, red);
+    if (threadIdx.x == 0 && m > 0.f) atomicMax(&s->wmax[1], __float_as_uint(m));
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         s->cur = 1;
         s->pform = 1;

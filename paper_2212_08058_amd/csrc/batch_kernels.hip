@@ -29,6 +29,7 @@ __global__ void batch_init_kernel(DevState *states, const ClipDesc *clips, int n
     s->converged = 0;
     s->arrive = 0u;
     s->ubound = 0u;
+    s->wmax[0] = s->wmax[1] = 0u;
     s->first_res[0] = s->first_res[1] = 0.0;
     s->check_rise = 0;
     s->pform = uniform && pform ? 2 : 0;

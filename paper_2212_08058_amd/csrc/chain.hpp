@@ -78,12 +78,20 @@ __global__ void normalize_kernel(ST *x, const ST *buf1, size_t n, const DevState
 // Product-form chain from the caller's start x: buffer 1 <- w = f x g (as
 // stored; g = 2^-2e from the bound on |f| in the state), and the state points
 // at it. x itself is first overwritten by the first step.
+// Also collects max |w| into the state (the first step's staging bound).
 template <class ST>
 __global__ void to_product_kernel(const ST *f, const ST *x, ST *w, size_t n, DevState *s) {
     using CT = typename Compute<ST>::type;
+    __shared__ float red[256 / 64];
     const CT g = (CT)ldexp(1.0, -2 * bound_exponent(__uint_as_float(s->ubound), PRODUCT_ELIM));
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        st(w + i, (ld(f + i) * ld(x + i)) * g);
+    float m = 0.f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const CT v = (ld(f + i) * ld(x + i)) * g;
+        st(w + i, v);
+        m = fmaxf(m, fabsf((float)stored_value(w + i, v)));
+    }
+    m = block_max<256>(m, red);
+    if (threadIdx.x == 0 && m > 0.f) atomicMax(&s->wmax[1], __float_as_uint(m));
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         s->cur = 1;
         s->pform = 1;

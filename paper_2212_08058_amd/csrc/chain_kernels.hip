@@ -20,10 +20,18 @@ __global__ void state_init_kernel(DevState *s, double scale, double tol, int max
         s->converged = 0;
         s->arrive = 0u;
         s->ubound = 0u;
+        s->wmax[0] = s->wmax[1] = 0u;
         s->first_res[0] = s->first_res[1] = 0.0;
         s->check_rise = check_rise;
         s->pform = pform;
     }
+}
+
+// Empties the partial-sum slots of a chain whose steps finalise themselves.
+__global__ void partials_empty_kernel(double *partials, int n) {
+    uint64_t *w = reinterpret_cast<uint64_t *>(partials);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n; i += gridDim.x * blockDim.x)
+        __hip_atomic_store(w + i, PARTIAL_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void clear_word_kernel(uint32_t *w) {
@@ -195,6 +203,11 @@ hipError_t launch_state_init(DevState *s, double scale, double tol, int max_iter
 
 hipError_t launch_state_from_norm(const double *partials, int n, DevState *s, hipStream_t st) {
     hipLaunchKernelGGL(state_from_norm_kernel, dim3(1), dim3(CHAIN_THREADS), 0, st, partials, n, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_partials_empty(double *partials, int n, hipStream_t st) {
+    hipLaunchKernelGGL(partials_empty_kernel, dim3((2 * n + 255) / 256), dim3(256), 0, st, partials, n);
     return hipGetLastError();
 }
 

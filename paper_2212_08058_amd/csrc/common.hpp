@@ -64,6 +64,10 @@ struct DevState {
     // steps): 1: the current buffer holds w = f x g (see FwdOpP), 2: uniform
     // start, no step taken yet (the iterate is the constant 1, w = f itself).
     int32_t pform;
+    // Product form: float bits of max |w| over buffer 0 / buffer 1 (the
+    // buffer a step writes collects it; the step's finalisation clears the
+    // entry of the buffer it read, which the next step writes).
+    uint32_t wmax[2];
 };
 
 static_assert(sizeof(DevState) <= 256, "the iteration state lives in a 256-byte workspace slot");
@@ -81,6 +85,18 @@ __device__ __forceinline__ int bound_exponent(float bound, int lim) {
 }
 // Product-form chains keep 2^(+-2e) normal floats.
 constexpr int PRODUCT_ELIM = 60;
+
+// An empty partial-sum slot of a step whose last workgroup finalises it: a
+// signalling-NaN pattern that arithmetic never produces (its NaNs are quiet).
+// Each workgroup overwrites its slot with an agent-scope atomic store; the last
+// workgroup reads every slot until it no longer holds this pattern (so it sees
+// the stored value by the coherence of that one location, without a cache
+// write-back) and puts the pattern back for the next step.
+constexpr uint64_t PARTIAL_EMPTY = 0x7ff4dead5a17ab1eull;
+// Reads of one slot before the wait is abandoned (never reached in practice:
+// the arrival counter is only bumped after the slot's store has completed).
+constexpr int PARTIAL_SPIN_LIMIT = 1 << 20;
+constexpr uint32_t FLAG_SYNC = 8u;  // a partial sum never arrived (see PARTIAL_SPIN_LIMIT)
 
 // Workgroup size and summation order of the per-step reduction of partial
 // sums: thread i < FINAL_THREADS adds entries i, i + FINAL_THREADS, ... in
@@ -108,6 +124,7 @@ __device__ __forceinline__ void step_finalize(DevState *s, double p1, double p2)
     s->lambda = nz;
     s->residual = sqrt(fmax(0.0, 2.0 - 2.0 * c));
     s->scale = 1.0 / nz;
+    s->wmax[s->cur] = 0u;  // the buffer just read is the next step's output
     s->cur ^= 1;
     s->iters += 1;
     if (s->pform == 2) s->pform = 1;
@@ -140,6 +157,38 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
         for (int i = 0; i < NW; ++i) s += lds[i];
     }
     return s;  // valid in thread 0 only
+}
+
+// Maximum of a non-negative float over a workgroup (valid in thread 0).
+template <int NTHR>
+__device__ __forceinline__ float block_max(float v, float *lds) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    constexpr int NW = NTHR / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    float m = 0.f;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i) m = fmaxf(m, lds[i]);
+    }
+    return m;
+}
+
+// Reads partial-sum slot i of a step finalised by its last workgroup (see
+// PARTIAL_EMPTY) and empties it again; *late is set if it never arrived.
+__device__ __forceinline__ double take_partial(double *slot, bool *late) {
+    uint64_t *w = reinterpret_cast<uint64_t *>(slot);
+    uint64_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int k = 0; v == PARTIAL_EMPTY && k < PARTIAL_SPIN_LIMIT; ++k) {
+        __builtin_amdgcn_s_sleep(1);
+        v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (v == PARTIAL_EMPTY) *late = true;
+    __hip_atomic_store(w, PARTIAL_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)v);
 }
 
 }  // namespace stpi

@@ -218,6 +218,12 @@ __device__ __forceinline__ float recip_or_zero(float fv) {
 // powers of two 1/g: the caller multiplies d1 by ginv_in ginv_out and d2 by
 // ginv_out^2. ginv_in = 1 / g of the input: 1 on the first step of a uniform
 // start, whose input is f itself (w of the constant 1, up to g).
+// Staging range: the staged values are w s ginv_in 2^(10 - e_in) with e_in the
+// exponent of a bound on |w s ginv_in| taken from max |w| of the input buffer
+// (collected by the step that wrote it; max |f| for the uniform start), so
+// the largest staged value lies in [2^9, 2^10) whatever the scale of the
+// iterate, and the split's half-precision parts keep their full precision
+// for every value within 2^14 of it.
 
 template <class ST>
 struct FwdOpP {
@@ -232,6 +238,7 @@ struct FwdOpP {
     double ginv_in, ginv_out;
     size_t plane;
     uint32_t pbytes;
+    mutable float wmax = 0.f;  // max |w_new| stored by this thread (the next step's staging bound)
 
     template <int NPF>
     struct Raw {
@@ -284,7 +291,9 @@ struct FwdOpP {
                 const CT z = scale * (fv * acc[i][q]);
                 w[q] = (z * fv) * gout;
                 const CT r = recip_or_zero(fv);
-                const double xn = (double)(IO::rounded(w[q]) * r);
+                const CT wr = IO::rounded(w[q]);
+                wmax = fmaxf(wmax, fabsf(wr));
+                const double xn = (double)(wr * r);
                 const double xp = (double)(raw.u[i][q] * r);
                 d2 = fma(xn, xn, d2);
                 d1 = fma(xp, xn, d1);
@@ -360,21 +369,27 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
         if constexpr (PF) {
             const int e = bound_exponent(bound, PRODUCT_ELIM);
             const bool first = a.state->pform == 2;
+            const int cur = a.state->cur;
             FwdOpP<ST> pp;
             pp.f = a.f;
             pp.src = first ? a.f : op.src;
             pp.dst = op.dst;
-            pp.scale = ldexpf(1.f, e - 10);
             pp.gout = ldexpf(1.f, -2 * e);
             pp.ginv_out = ldexp(1.0, 2 * e);
             pp.ginv_in = first ? 1.0 : pp.ginv_out;
             pp.plane = op.plane;
             pp.pbytes = op.pbytes;
-            const float umul = (float)(scale * ldexp(1.0, 10 - e) * pp.ginv_in);
+            // staging power of two from the input's own maximum
+            const float win = first ? bound : __uint_as_float(a.state->wmax[cur]);
+            const int ein = bound_exponent((float)((double)win * scale * pp.ginv_in), 100);
+            pp.scale = ldexpf(1.f, ein - 10);
+            const float umul = (float)(scale * ldexp(1.0, 10 - ein) * pp.ginv_in);
             stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(pp, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0,
                                                    lds, d1, d2);
             d1 *= pp.ginv_in * pp.ginv_out;
             d2 *= pp.ginv_out * pp.ginv_out;
+            const float m = block_max<NTHR>(pp.wmax, reinterpret_cast<float *>(red));
+            if (threadIdx.x == 0 && m > 0.f) atomicMax(&a.state->wmax[cur ^ 1], __float_as_uint(m));
         } else {
             if (!a.state) bound *= (float)fabs(scale);
             const int e = bound_exponent(bound, 100);
@@ -395,9 +410,10 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     if (threadIdx.x == 0) {
         if (a.fuse) {
             // Publish the two sums device-wide: agent-scope stores write through
-            // the XCD's L2, the wait makes sure they are done before this
-            // workgroup is counted in. Only these values cross workgroups, so no
-            // full L2 write-back is needed (the kernel boundary orders the rest).
+            // the XCD's L2 into slots the last workgroup polls (PARTIAL_EMPTY);
+            // the wait makes sure they are done before this workgroup is counted
+            // in. Only these values cross workgroups, so no full L2 write-back is
+            // needed (the kernel boundary orders the rest).
             __hip_atomic_store(&a.partials[2 * unit], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.partials[2 * unit + 1], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0);
@@ -417,14 +433,21 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
         // agent-scope loads read the published sums past the local L2
         const int n = nbx * nby * a.nseg;
         double p1 = 0.0, p2 = 0.0;
+        bool late = false;
         if (threadIdx.x < FINAL_THREADS)
             for (int i = threadIdx.x; i < n; i += FINAL_THREADS) {
-                p1 += __hip_atomic_load(&a.partials[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                p2 += __hip_atomic_load(&a.partials[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                p1 += take_partial(&a.partials[2 * i], &late);
+                p2 += take_partial(&a.partials[2 * i + 1], &late);
             }
         p1 = block_sum<NTHR>(p1, red);
         p2 = block_sum<NTHR>(p2, red);
+        __shared__ int s_late;
+        if (threadIdx.x == 0) s_late = 0;
+        __syncthreads();
+        if (late) s_late = 1;
+        __syncthreads();
         if (threadIdx.x == 0) {
+            if (s_late) a.state->flags |= FLAG_SYNC;
             step_finalize(a.state, p1, p2);
             a.state->arrive = 0u;
         }

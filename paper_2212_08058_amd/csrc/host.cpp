@@ -225,7 +225,7 @@ static unsigned long long g_graph_clock = 0;
 constexpr size_t GRAPH_CACHE_MAX = 16;
 
 // STPI_NO_FUSE=1 keeps the step finalisation in its own kernel (for comparison).
-static bool fusion_disabled() {
+bool fusion_disabled() {
     const char *e = std::getenv("STPI_NO_FUSE");
     return e && e[0] == '1';
 }
@@ -599,6 +599,10 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
     out->first_residuals[0] = hs.first_res[0];
     out->first_residuals[1] = hs.first_res[1];
     out->status = STPI_OK;
+    if (hs.flags & FLAG_SYNC) {
+        out->status = STPI_EHIP;
+        return fail(STPI_EHIP, "a step's partial sums did not arrive (step %d)", hs.iters + 1);
+    }
     if (hs.flags & FLAG_NONFINITE) out->status = STPI_ENONFINITE;
     else if (hs.flags & FLAG_ZERO) out->status = STPI_EZERO_NORM;
     (void)N;
@@ -773,6 +777,9 @@ int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevS
         return hip_fail(e, "operand bound");
     if (pform && init != 1 && (e = ops->to_product(f, x, buf1, N, state, s)) != hipSuccess)
         return hip_fail(e, "product-form start");
+    // steps that finalise themselves poll their partial-sum slots
+    if (v && (e = launch_partials_empty(partials, grid_blocks(*v, p), s)) != hipSuccess)
+        return hip_fail(e, "partials");
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init");
     return STPI_OK;
 }

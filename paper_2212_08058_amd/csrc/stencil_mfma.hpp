@@ -12,15 +12,21 @@
 // Range. The staged input is u' = f x_stored scale 2^S, where scale makes the
 // iterate unit and 2^S is chosen on the device from a bound B >= |f x scale|
 // so that |u'| < 2^10; the y-pass output is then below (2 PAD + 1) 2^10 <= 33 *
-// 2^10 (the taps are <= 1), inside half precision. The output picks up 2^-S in the epilogue's
-// scale, so z is the same as in the plain form. Values far below the largest
-// one lose relative precision (half precision subnormals), but never more
-// than 2^-24 * 2^10 / 2^S in absolute terms.
+// 2^10 (the taps are <= 1), inside half precision. The output picks up 2^-S in
+// the epilogue's scale, so z is the same as in the plain form. B is the
+// actual maximum (single step: max |f x| |scale|; iteration chains: max |w|
+// of the stored iterate, collected by the step that wrote it), so the
+// largest staged value lies in [2^9, 2^10) and the split keeps about 22
+// significant bits for every value within 2^14 of it; smaller values keep an
+// absolute error below 2^-24, i.e. 2^-33 of the largest.
 //
 // Tile. A workgroup owns TH x TW outputs (multiples of 16) and streams its
 // frames as the plain tile loop does (three-stage pipeline, one barrier per
-// phase, the same t-ring and epilogue; the epilogue's loads are issued at the
-// start of the phase). Per frame:
+// phase, the same t-ring and epilogue). Each phase issues the epilogue's
+// loads, then the matrix-core products of both passes (they read buffers
+// written before the phase's barrier), then does the vector work (staging,
+// t-ring, epilogue) while those run, and stores the y-pass result last.
+// Per frame:
 //   stage:  u' on the (TH + 2 PAD) x (TW + 2 PAD) slab around the tile (PAD =
 //           8 or 16, at least the space radius), split into
 //           hi and lo planes stored column-major (U^T[c][k], k = slab row),
@@ -115,62 +121,70 @@ __device__ __forceinline__ void split_half(float v, _Float16 &hi, _Float16 &lo) 
     lo = (_Float16)(v - (float)hi);
 }
 
-// y-pass of one 16 x 16 block of Y: reads the U^T planes, writes the Y planes.
+// Launders a constant so the compiler keeps it as an operand (fma(x, 1, y)
+// would otherwise fold to an add, which has no mixed-precision form).
+__device__ __forceinline__ float opaque(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Splits 4 floats into half-precision hi and lo parts: hi = fp16(v),
+// lo = fp16(v - hi) (one mixed-precision fma per element).
+__device__ __forceinline__ void split4(const float4_t &v, half4_t &h, half4_t &l, float one) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h[j] = (_Float16)v[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) l[j] = (_Float16)__builtin_fmaf(-(float)h[j], one, v[j]);
+}
+
+// y-pass products of one 16 x 16 block of Y (one dependency chain).
 template <class G>
-__device__ __forceinline__ void mfma_yblock(const _Float16 *U, _Float16 *Y, int b, int lane,
-                                            const half8_t (&thi)[G::KB], const half8_t (&tlo)[G::KB]) {
+__device__ __forceinline__ float4_t mfma_yblock_mma(const _Float16 *U, int b, int lane, const half8_t (&thi)[G::KB],
+                                                    const half8_t (&tlo)[G::KB]) {
     const int rb = b / G::NYC, cb = b % G::NYC;
     const int li = lane & 15, lg = lane >> 4;
     const _Float16 *p = U + (16 * cb + li) * G::UP + 16 * rb + 8 * lg;
-    // one accumulator per K block: independent dependency chains of three products
-    float4_t ac[G::KB];
+    float4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < G::KB; ++kb) {
         const half8_t ah = *reinterpret_cast<const half8_t *>(p + 32 * kb);
         const half8_t al = *reinterpret_cast<const half8_t *>(p + G::UPL + 32 * kb);
-        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, thi[kb], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, tlo[kb], ac[kb], 0, 0, 0);
-        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], ac[kb], 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, thi[kb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, tlo[kb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], acc, 0, 0, 0);
     }
-    float4_t acc = ac[0];
-#pragma unroll
-    for (int kb = 1; kb < G::KB; ++kb) acc += ac[kb];
+    return acc;
+}
+
+// Stores a y-pass block: split into the Y hi and lo planes.
+template <class G>
+__device__ __forceinline__ void mfma_yblock_store(_Float16 *Y, int b, int lane, const float4_t &acc, float one) {
+    const int rb = b / G::NYC, cb = b % G::NYC;
+    const int li = lane & 15, lg = lane >> 4;
     half4_t h, l;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        _Float16 a, c;
-        split_half(acc[j], a, c);
-        h[j] = a;
-        l[j] = c;
-    }
+    split4(acc, h, l, one);
     _Float16 *q = Y + (16 * rb + li) * G::YP + 16 * cb + 4 * lg;
     *reinterpret_cast<half4_t *>(q) = h;
     *reinterpret_cast<half4_t *>(q + G::YPL) = l;
 }
 
-// x-pass of one 16 x 16 output block: 4 consecutive outputs of one row per lane.
+// x-pass products of one 16 x 16 output block (one dependency chain).
 template <class G>
-__device__ __forceinline__ void mfma_xblock(const _Float16 *Y, int b, int lane, const half8_t (&thi)[G::KB],
-                                            const half8_t (&tlo)[G::KB], float (&v)[4]) {
+__device__ __forceinline__ float4_t mfma_xblock_mma(const _Float16 *Y, int b, int lane, const half8_t (&thi)[G::KB],
+                                                    const half8_t (&tlo)[G::KB]) {
     const int rb = b / G::NB, ob = b % G::NB;
     const int li = lane & 15, lg = lane >> 4;
     const _Float16 *p = Y + (16 * rb + li) * G::YP + 16 * ob + 8 * lg;
-    float4_t ac[G::KB];
+    float4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < G::KB; ++kb) {
         const half8_t bh = *reinterpret_cast<const half8_t *>(p + 32 * kb);
         const half8_t bl = *reinterpret_cast<const half8_t *>(p + G::YPL + 32 * kb);
-        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bh, float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tlo[kb], bh, ac[kb], 0, 0, 0);
-        ac[kb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bl, ac[kb], 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(tlo[kb], bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(thi[kb], bl, acc, 0, 0, 0);
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        float t = ac[0][j];
-#pragma unroll
-        for (int kb = 1; kb < G::KB; ++kb) t += ac[kb][j];
-        v[j] = t;
-    }
+    return acc;
 }
 
 // Streams one tile through frames [t0, t1) (reading [t0 - RT, t1 + RT) clipped
@@ -265,13 +279,34 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
     typename Op::template OutRaw<XPW, 4> oraw;
 
     const int nphase = t1 + RT - ts + 2;
+    const float one = opaque(1.f);
     ring_loop<NTS, -2>(nphase, [&](auto ring_pos, int p) __attribute__((always_inline)) {
         constexpr int J = decltype(ring_pos)::value;
         const int tx = p - 2;
         const int tout = ts + tx - RT;
         const bool emit = tx >= 0 && tout >= t0;
+        const bool xlive = tx >= 0 && tx < nin;
+        const bool ylive = p >= 1 && p - 1 < nin;
         // the epilogue's loads go first: they have the whole phase to arrive
         if (emit) op.template fetch_out<XPW, 4>(tout, ooff, oraw);
+        // matrix-core products of both passes (frames p - 2 and p - 1; the
+        // buffers they read were written before the last barrier), issued
+        // before the vector work of the phase so that they run beside it
+        float4_t xa[XPW];
+        if (xlive) {
+            const _Float16 *Y = Y0 + (tx & 1) * G::YBUF;
+#pragma unroll
+            for (int i = 0; i < XPW; ++i) xa[i] = mfma_xblock_mma<G>(Y, wid * XPW + i, lane, thi, tlo);
+        }
+        float4_t ya[G::YPW];
+        if (ylive) {
+            const _Float16 *U = U0 + ((p - 1) & 1) * G::UBUF;
+#pragma unroll
+            for (int m = 0; m < G::YPW; ++m) {
+                const int b = wid + m * G::NWAVE;
+                if (G::NYB % G::NWAVE == 0 || b < G::NYB) ya[m] = mfma_yblock_mma<G>(U, b, lane, thi, tlo);
+            }
+        }
         if (p < nin) {
             _Float16 *U = U0 + (p & 1) * G::UBUF;
 #pragma unroll
@@ -294,29 +329,21 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
             }
         }
         if (p + 1 < nin) op.template fetch<NPF>(ts + p + 1, poff, pf);
-        if (p >= 1 && p - 1 < nin) {
-            const _Float16 *U = U0 + ((p - 1) & 1) * G::UBUF;
+        if (tx >= 0) {
+            CT v[XPW][4];
+#pragma unroll
+            for (int i = 0; i < XPW; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[i][q] = xlive ? xa[i][q] : CT(0);
+            ring_step<J, CT, RT, XPW, 4>(acc, v, tp, xlive, emit, tout, op, ooff, oraw, d1, d2);
+        }
+        if (ylive) {
             _Float16 *Y = Y0 + ((p - 1) & 1) * G::YBUF;
 #pragma unroll
             for (int m = 0; m < G::YPW; ++m) {
                 const int b = wid + m * G::NWAVE;
-                if (G::NYB % G::NWAVE == 0 || b < G::NYB) mfma_yblock<G>(U, Y, b, lane, thi, tlo);
+                if (G::NYB % G::NWAVE == 0 || b < G::NYB) mfma_yblock_store<G>(Y, b, lane, ya[m], one);
             }
-        }
-        if (tx >= 0) {
-            CT v[XPW][4];
-            const bool live = tx < nin;
-            if (live) {
-                const _Float16 *Y = Y0 + (tx & 1) * G::YBUF;
-#pragma unroll
-                for (int i = 0; i < XPW; ++i) mfma_xblock<G>(Y, wid * XPW + i, lane, thi, tlo, v[i]);
-            } else {
-#pragma unroll
-                for (int i = 0; i < XPW; ++i)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) v[i][q] = CT(0);
-            }
-            ring_step<J, CT, RT, XPW, 4>(acc, v, tp, live, emit, tout, op, ooff, oraw, d1, d2);
         }
         __syncthreads();
     });
