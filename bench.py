@@ -64,6 +64,17 @@ def profiled_traffic(tag: str):
     return rec
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(f_np, kern, seconds: float):
     import numpy as np
 
@@ -74,20 +85,28 @@ def cpu_baseline(f_np, kern, seconds: float):
     x = np.full(f_np.shape, 1.0 / math.sqrt(f_np.size))
     f64 = f_np.astype(np.float64)
     rng = np.random.default_rng(0)
-    # a short probe sizes the timed sample to about `seconds` of CPU work
-    idx = rng.integers(0, f_np.size, 2000)
-    t0 = time.perf_counter()
-    oracle.apply_at(f64, x, k, idx)
-    rate = idx.size / max(time.perf_counter() - t0, 1e-6)
-    n = int(min(max(rate * seconds, 2000), 50_000_000))
-    idx = rng.integers(0, f_np.size, n)
-    t0 = time.perf_counter()
-    oracle.apply_at(f64, x, k, idx)
-    dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="voxel-iters/s", cores=oracle.num_threads(), kind="oracle",
+
+    def timed(n_threads, secs):
+        oracle.set_threads(n_threads)
+        # a short probe sizes the timed sample to about `secs` of CPU work
+        idx = rng.integers(0, f_np.size, 200 * n_threads)
+        t0 = time.perf_counter()
+        oracle.apply_at(f64, x, k, idx)
+        rate = idx.size / max(time.perf_counter() - t0, 1e-6)
+        n = int(min(max(rate * secs, 200), 50_000_000))
+        idx = rng.integers(0, f_np.size, n)
+        t0 = time.perf_counter()
+        oracle.apply_at(f64, x, k, idx)
+        return n, time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    n1, dt1 = timed(1, min(5.0, seconds / 3))
+    n, dt = timed(threads, seconds)
+    return dict(value=n / dt, unit="voxel-iters/s", cores=threads, kind="oracle",
+                cpu_model=_cpu_model(), nproc=os.cpu_count(), value_1_thread=n1 / dt1,
                 sample=f"{n} voxels drawn uniformly from the 64x480x854 clip, one application each "
                        f"(direct FP64 neighbourhood loop, {(2 * k.r_t + 1) * (2 * k.r_s + 1) ** 2} taps/voxel), "
-                       f"{dt:.1f} s")
+                       f"{dt:.1f} s on {threads} threads; {n1} voxels in {dt1:.1f} s on 1 thread")
 
 
 def main():
@@ -102,10 +121,10 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="let the autotuner pick the FP32 tile (default: the cost model's choice, which the "
                          "committed counter profile covers); the BF16 leg is always tuned")
-    ap.add_argument("--extras", default="bf16,copy",
-                    help="comma list of extra measurements to attach: bf16, batch, channels, warm (or none)")
+    ap.add_argument("--extras", default="bf16,copy,batch,warm",
+                    help="comma list of extra measurements to attach: bf16, copy, batch, channels, warm (or none)")
     ap.add_argument("--warm-train", type=int, default=200, help="training clips for the warm-start extra")
-    ap.add_argument("--warm-eval", type=int, default=10, help="evaluation clips for the warm-start extra")
+    ap.add_argument("--warm-eval", type=int, default=24, help="evaluation clips for the warm-start extra")
     ap.add_argument("--warm-epochs", type=int, default=2, help="training epochs for the warm-start extra")
     args = ap.parse_args()
 
@@ -207,8 +226,13 @@ def main():
     hbm = {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
            "bytes_per_voxel": bytes_per_voxel}
     if vinfo[8] == 3:
+        # the roofline that bounds a stencil is HBM bandwidth; what limits this
+        # kernel below it is recorded beside it (rocprofv3 SQ counters)
         out["roofline"] = {"bound": "hbm", **hbm, "traffic": None, "kernel": "fwd_step_kernel", "kernel_ms": kern_ms,
-                           "alu": alu}
+                           "alu": alu,
+                           "limiter": "instruction issue and latency, not HBM: per SIMD the vector ALU is busy ~41% "
+                                      "of the kernel time and the matrix cores ~9% (two wavefronts per SIMD, one "
+                                      "LDS-bound workgroup per CU, a barrier per frame phase)"}
     else:
         out["roofline"] = {"bound": "alu", **alu, "traffic": None, "kernel": "fwd_step_kernel", "kernel_ms": kern_ms,
                            "hbm": hbm}
@@ -281,6 +305,7 @@ def main():
         log("warm start vs plain")
         r = X.warm_start_experiment(n_train=args.warm_train, n_eval=args.warm_eval, epochs=args.warm_epochs, log=log)
         r.pop("iters", None)
+        r.pop("ms", None)
         out["warm"] = r
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample")

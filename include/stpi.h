@@ -226,7 +226,13 @@ size_t stpi_batch_workspace_bytes(const stpi_plan *plan);
 int stpi_batch_info(const stpi_plan *plan, int32_t info[11]);
 /* Power iteration of every clip (as stpi_iterate, per clip): x_flat is in/out,
  * init = 1 overwrites each clip with the uniform start, init = 0 uses x_flat.
- * Stops each clip at its first residual < tol (tol > 0) or after max_iters.
+ * init = 2 is init = 0 with the warm-start rule applied per clip on the
+ * device: a clip whose residual after the second application exceeds the
+ * first restarts from the uniform start (flags bit 2 set; its iteration count
+ * includes the two discarded applications; max_iters bounds the total).
+ * Stops each clip at its first residual < tol (tol > 0) or after max_iters;
+ * a clip that stopped costs the following steps nothing (every step claims
+ * tiles from the list of clips still iterating).
  * per_clip: host array of nclips results. Synchronises `stream` once. Calls
  * with a NULL stream run without graph capture. */
 int stpi_batch_iterate(stpi_plan *plan, const void *f_flat, void *x_flat, int init, int max_iters, double tol,

@@ -34,7 +34,8 @@ struct TileDesc {
 struct BatchCtl {
     uint32_t next_tile;   // work counter of the running step (reset by the finalisation)
     uint32_t done_clips;  // clips that stopped (converged, capped or failed)
-    uint32_t pad[2];
+    uint32_t n_active;    // tiles of the clips still iterating (see batch_compact_kernel)
+    uint32_t n_clips_active;
 };
 
 template <class ST>
@@ -48,16 +49,31 @@ struct BatchArgs {
     const TileDesc *tiles;
     BatchCtl *ctl;
     double *partials;  // [ntiles][2]
+    // clips still iterating, in tile-list order, and the exclusive prefix sums
+    // of their tile counts (rebuilt after every step)
+    const int32_t *active_clip;
+    const int32_t *active_cum;
     int ntiles, nclips;
     int rs;  // the problem's space radius (matrix-core variants)
     Taps<CT> taps;
 };
 
+// Wavefronts per SIMD the register allocation must allow: matrix-core tiles
+// whose LDS fits twice in a CU's 160 KB are built for two resident workgroups.
+template <int TH, int TW, int NTHR, int PIPE, int PAD>
+constexpr int batch_min_waves() {
+    if constexpr (PIPE == 3)
+        return 2 * (MfmaLds<PIPE, TH, TW, NTHR, PAD>::value * 4 + 1024) <= 160 * 1024 ? 2 * NTHR / 256 : 1;
+    else
+        return 1;
+}
+
 // PIPE: 1 runs each tile through the software-pipelined tile loop, 3 through
 // the matrix-core tile loop in product form (see FwdOpP: every clip's
 // buffers hold f x g, with g from the clip's own bound on |f|).
 template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int PIPE>
-__global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
+__global__ __launch_bounds__(NTHR, (batch_min_waves<TH, TW, NTHR, PIPE, RS <= 8 ? 8 : 16>()))
+void batch_step_kernel(BatchArgs<ST> a) {
     using CT = typename Compute<ST>::type;
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
     using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
@@ -94,9 +110,19 @@ __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
             s_tile = (int)__builtin_amdgcn_readfirstlane(mine);  // all lanes store the same value
         }
         __syncthreads();
-        const int t = __builtin_amdgcn_readfirstlane(s_tile);
+        const int g = __builtin_amdgcn_readfirstlane(s_tile);
         __syncthreads();
-        if (t >= a.ntiles) break;
+        if (g >= (int)__builtin_amdgcn_readfirstlane(a.ctl->n_active)) break;
+        // the active clip holding claimed tile g: last i with active_cum[i] <= g
+        int lo = 0, hi = __builtin_amdgcn_readfirstlane(a.ctl->n_clips_active) - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (__builtin_amdgcn_readfirstlane(a.active_cum[mid]) <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const int aclip = __builtin_amdgcn_readfirstlane(a.active_clip[lo]);
+        const int t = __builtin_amdgcn_readfirstlane(a.clips[aclip].tile_begin) + g -
+                      __builtin_amdgcn_readfirstlane(a.active_cum[lo]);
         const int clip = __builtin_amdgcn_readfirstlane(a.tiles[t].clip);
         const int tx0 = __builtin_amdgcn_readfirstlane(a.tiles[t].x0);
         const int ty0 = __builtin_amdgcn_readfirstlane(a.tiles[t].y0);
@@ -159,7 +185,10 @@ __global__ __launch_bounds__(NTHR) void batch_step_kernel(BatchArgs<ST> a) {
 }
 
 // One workgroup per clip: the clip's step finalisation (see finalize_kernel).
-__device__ __forceinline__ void finalize_state(DevState *s, double p1, double p2, BatchCtl *ctl) {
+// With the rise check (a warm start), a clip whose second residual exceeds
+// its first restarts from the uniform start 1/sqrt(n) on the device: its
+// iteration count keeps the two discarded steps.
+__device__ __forceinline__ void finalize_state(DevState *s, double p1, double p2, BatchCtl *ctl, double n) {
     const double scale = s->scale;
     const double nz = sqrt(p2);
     bool stop = false;
@@ -179,8 +208,16 @@ __device__ __forceinline__ void finalize_state(DevState *s, double p1, double p2
         s->cur ^= 1;
         s->iters += 1;
         if (s->pform == 2) s->pform = 1;
+        s->refill = 0;
         if (s->iters <= 2) s->first_res[s->iters - 1] = s->residual;
-        if (s->tol > 0.0 && s->residual < s->tol) {
+        if (s->check_rise && s->iters == 2 && !(s->first_res[1] <= s->first_res[0])) {
+            s->flags |= FLAG_ROSE;
+            s->check_rise = 0;
+            s->scale = 1.0 / sqrt(n);
+            s->wmax[0] = s->wmax[1] = 0u;
+            if (s->pform) s->pform = 2;  // product form: the next step stages f itself
+            else s->refill = 1;          // plain form: batch_refill_kernel writes the constant 1
+        } else if (s->tol > 0.0 && s->residual < s->tol) {
             s->converged = 1;
             stop = true;
         }
@@ -206,6 +243,7 @@ struct BatchLaunch {
     const TileDesc *tiles;
     BatchCtl *ctl;
     double *partials;
+    const int32_t *active_clip, *active_cum;
     int ntiles, nclips, grid;
     double gs[2 * 16 + 1];
     double gt[2 * 8 + 1];
@@ -229,6 +267,8 @@ hipError_t launch_batch(const BatchLaunch &L, hipStream_t stream) {
     a.tiles = L.tiles;
     a.ctl = L.ctl;
     a.partials = L.partials;
+    a.active_clip = L.active_clip;
+    a.active_cum = L.active_cum;
     a.ntiles = L.ntiles;
     a.nclips = L.nclips;
     a.rs = 0;
@@ -253,6 +293,20 @@ int batch_blocks_per_cu() {
 }
 
 constexpr int BATCH_NORM_BLOCKS = 64;  // workgroups per clip in the per-clip reductions
+
+// Plain-form batch after a rejected warm start: the current buffer of every
+// clip marked for it <- 1 (the finalisation already set the uniform scale).
+template <class ST>
+__global__ void batch_refill_kernel(ST *buf0, ST *buf1, const ClipDesc *clips, const DevState *states) {
+    using CT = typename Compute<ST>::type;
+    const DevState *s = states + blockIdx.y;
+    if (!s->refill) return;
+    const ClipDesc cd = clips[blockIdx.y];
+    ST *x = (s->cur ? buf1 : buf0) + cd.offset;
+    const size_t n = (size_t)cd.T * cd.H * cd.W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(x + i, CT(1));
+}
 
 // x[clip] <- 1 (uniform start, scale set by the init kernel)
 template <class ST>

@@ -68,13 +68,16 @@ struct DevState {
     // buffer a step writes collects it; the step's finalisation clears the
     // entry of the buffer it read, which the next step writes).
     uint32_t wmax[2];
+    // Batched chains, plain form: 1 after a rejected warm start until the
+    // clip's buffer has been refilled with the uniform start.
+    int32_t refill;
 };
 
 static_assert(sizeof(DevState) <= 256, "the iteration state lives in a 256-byte workspace slot");
 
 constexpr uint32_t FLAG_ZERO = 1u;
 constexpr uint32_t FLAG_NONFINITE = 2u;
-constexpr uint32_t FLAG_ROSE = 4u;  // stopped by the check_rise rule (not an error)
+constexpr uint32_t FLAG_ROSE = 4u;  // the check_rise rule fired (not an error): single clip stops, batched clip restarts
 
 // Exponent e of a bound (bound < 2^e, from frexp), clamped to [-lim, lim];
 // 0 for a zero or non-finite bound.

@@ -149,6 +149,13 @@ hipError_t batch_from_product_impl(void *x, const void *buf1, const void *f, con
     return hipGetLastError();
 }
 
+hipError_t batch_refill_impl(void *x, void *buf1, const ClipDesc *clips, const DevState *states, int nclips,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(batch_refill_kernel<ST_>, dim3(BATCH_NORM_BLOCKS, nclips), dim3(256), 0, s, (ST_ *)x,
+                       (ST_ *)buf1, clips, states);
+    return hipGetLastError();
+}
+
 const DtypeOps kOps = {sizeof(ST_),       kVariants,        (int)(sizeof(kVariants) / sizeof(kVariants[0])),
                        &fill_ones_impl,   &sumsq_impl,      &normalize_impl,
                        &bound_impl,        &to_product_impl, &from_product_impl,
@@ -157,7 +164,8 @@ const DtypeOps kOps = {sizeof(ST_),       kVariants,        (int)(sizeof(kVarian
                        &train_init_impl,  &max_impl,        &bce_impl,
                        &bce_fin_impl,     kBatch,           kNBatch,
                        &batch_fill_impl,  &batch_sumsq_impl, &batch_normalize_impl,
-                       &batch_bound_impl, &batch_to_product_impl, &batch_from_product_impl};
+                       &batch_bound_impl, &batch_to_product_impl, &batch_from_product_impl,
+                       &batch_refill_impl};
 
 }  // namespace
 

@@ -45,6 +45,9 @@ struct DtypeOps {
                                    int nclips, hipStream_t);
     hipError_t (*batch_from_product)(void *x, const void *buf1, const void *f, const ClipDesc *clips,
                                      const DevState *states, int nclips, hipStream_t);
+    // plain-form batch: uniform restart of the clips whose warm start was rejected
+    hipError_t (*batch_refill)(void *x, void *buf1, const ClipDesc *clips, const DevState *states, int nclips,
+                               hipStream_t);
 };
 
 const DtypeOps *dtype_ops_f32();

@@ -16,9 +16,10 @@ struct stpi_plan {
     const stpi::BatchVariant *v = nullptr;
     stpi::ClipDesc *d_clips = nullptr;
     stpi::TileDesc *d_tiles = nullptr;
+    int32_t *d_order = nullptr;  // clip indices in tile-list order
     std::vector<stpi::ClipDesc> clips;  // host copy, in the caller's order
     int64_t extent = 0;                 // elements the flat buffers must hold
-    size_t ws_state_off = 0, ws_partials_off = 0, ws_buf_off = 0, ws_total = 0;
+    size_t ws_state_off = 0, ws_active_off = 0, ws_partials_off = 0, ws_buf_off = 0, ws_total = 0;
     // captured chains: (f, x, ws, init, max_iters, tol, stream) -> graph
     struct G {
         const void *f;
@@ -99,8 +100,13 @@ static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int ini
     BatchCtl *ctl = (BatchCtl *)w;
     DevState *states = (DevState *)(w + P->ws_state_off);
     double *partials = (double *)(w + P->ws_partials_off);
+    int32_t *active_clip = (int32_t *)(w + P->ws_active_off);
+    int32_t *active_cum = active_clip + P->nclips;
     void *buf1 = w + P->ws_buf_off;
     hipError_t e;
+    auto compact = [&]() -> hipError_t {
+        return launch_batch_compact(states, P->d_clips, P->d_order, P->nclips, active_clip, active_cum, ctl, s);
+    };
     // matrix-core variants run every step in product form (a chain of no steps never launches one)
     const int pform = P->v->PIPE == 3 && max_iters > 0 ? 1 : 0;
     auto tail = [&]() -> hipError_t {
@@ -112,7 +118,8 @@ static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int ini
         return STPI_OK;
     }
     if (part <= 1) {
-        if ((e = launch_batch_init(states, P->d_clips, P->nclips, tol, max_iters, init, pform, ctl, s)) != hipSuccess)
+        if ((e = launch_batch_init(states, P->d_clips, P->nclips, tol, max_iters, init == 1 ? 1 : 0,
+                                   init == 2 ? 1 : 0, pform, ctl, s)) != hipSuccess)
             return hip_fail(e, "batch init");
         if (init == 1) {
             // product form: the first step stages f itself
@@ -129,6 +136,7 @@ static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int ini
         if (pform && init != 1 &&
             (e = ops->batch_to_product(f, x, buf1, P->d_clips, states, P->nclips, s)) != hipSuccess)
             return hip_fail(e, "batch product-form start");
+        if ((e = compact()) != hipSuccess) return hip_fail(e, "batch active list");
     }
     BatchLaunch BL;
     std::memset(&BL, 0, sizeof(BL));
@@ -140,6 +148,8 @@ static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int ini
     BL.tiles = P->d_tiles;
     BL.ctl = ctl;
     BL.partials = partials;
+    BL.active_clip = active_clip;
+    BL.active_cum = active_cum;
     BL.ntiles = P->ntiles;
     BL.nclips = P->nclips;
     BL.grid = P->grid;
@@ -149,6 +159,12 @@ static int enqueue_batch(stpi_plan *P, const void *f, void *x, void *ws, int ini
         if ((e = P->v->launch(BL, s)) != hipSuccess) return hip_fail(e, "batch step");
         if ((e = launch_batch_finalize(partials, P->d_clips, states, P->nclips, ctl, s)) != hipSuccess)
             return hip_fail(e, "batch finalize");
+        // the rise check fires after the second step; plain-form clips that
+        // restart need their buffer refilled (product-form ones stage f)
+        if (init == 2 && !pform && part <= 1 && k == 1 &&
+            (e = ops->batch_refill(x, buf1, P->d_clips, states, P->nclips, s)) != hipSuccess)
+            return hip_fail(e, "batch refill");
+        if ((e = compact()) != hipSuccess) return hip_fail(e, "batch active list");
     }
     if (part == 0 && (e = tail()) != hipSuccess) return hip_fail(e, "batch normalize");
     return STPI_OK;
@@ -230,6 +246,8 @@ int stpi_batch_plan(const stpi_clip *clips, int nclips, float sigma_s, float sig
     P->grid = cus * v->blocks_per_cu();
     hipError_t e = hipMalloc((void **)&P->d_clips, sizeof(ClipDesc) * nclips);
     if (e == hipSuccess) e = hipMalloc((void **)&P->d_tiles, sizeof(TileDesc) * tiles.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&P->d_order, sizeof(int32_t) * nclips);
+    if (e == hipSuccess) e = hipMemcpy(P->d_order, by_len.data(), sizeof(int32_t) * nclips, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(P->d_clips, cds.data(), sizeof(ClipDesc) * nclips, hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -241,6 +259,8 @@ int stpi_batch_plan(const stpi_clip *clips, int nclips, float sigma_s, float sig
     const size_t elem = ops_for(dtype)->elem;
     P->ws_state_off = 256;
     size_t off = P->ws_state_off + ((sizeof(DevState) * nclips + 255) & ~(size_t)255);
+    P->ws_active_off = off;
+    off += ((sizeof(int32_t) * 2 * nclips + 255) & ~(size_t)255);
     P->ws_partials_off = off;
     const size_t npart = std::max((size_t)P->ntiles, (size_t)nclips * BATCH_NORM_BLOCKS);
     off += ((npart * 2 * sizeof(double) + 255) & ~(size_t)255);
@@ -276,7 +296,8 @@ int stpi_batch_iterate(stpi_plan *plan, const void *f, void *x, int init, int ma
     if (!plan || !f || !x || !per_clip) return fail(STPI_EINVAL, "NULL plan, buffer or result");
     if (f == x) return fail(STPI_EINVAL, "x must not alias f");
     if (max_iters < 0) return fail(STPI_EINVAL, "max_iters must be >= 0");
-    if (init != 0 && init != 1) return fail(STPI_EINVAL, "init must be 0 (use x) or 1 (uniform)");
+    if (init < 0 || init > 2)
+        return fail(STPI_EINVAL, "init must be 0 (use x), 1 (uniform) or 2 (use x, rise check per clip)");
     if (!std::isfinite(tol)) return fail(STPI_EINVAL, "tol must be finite");
     if (!ws || ws_bytes < plan->ws_total)
         return fail(STPI_EWORKSPACE, "batch workspace needs %zu bytes", plan->ws_total);
@@ -381,6 +402,7 @@ void stpi_plan_destroy(stpi_plan *plan) {
     if (plan->poll_ev) (void)hipEventDestroy(plan->poll_ev);
     if (plan->d_clips) (void)hipFree(plan->d_clips);
     if (plan->d_tiles) (void)hipFree(plan->d_tiles);
+    if (plan->d_order) (void)hipFree(plan->d_order);
     delete plan;
 }
 

@@ -65,7 +65,9 @@ hipError_t launch_dot_finalize(const double *partials, int n, const double *a_no
 hipError_t launch_norm_finalize(const double *partials, int n, double *out, hipStream_t st);
 hipError_t launch_sum0_finalize(const double *partials, int n, double *out, hipStream_t st);
 hipError_t launch_batch_init(DevState *states, const ClipDesc *clips, int nclips, double tol, int max_iters,
-                             int uniform, int pform, BatchCtl *ctl, hipStream_t st);
+                             int uniform, int check_rise, int pform, BatchCtl *ctl, hipStream_t st);
+hipError_t launch_batch_compact(const DevState *states, const ClipDesc *clips, const int32_t *clip_order, int nclips,
+                                int32_t *active_clip, int32_t *active_cum, BatchCtl *ctl, hipStream_t st);
 hipError_t launch_batch_state_from_norm(const double *partials, DevState *states, int nclips, BatchCtl *ctl,
                                         hipStream_t st);
 hipError_t launch_batch_finalize(const double *partials, const ClipDesc *clips, DevState *states, int nclips,

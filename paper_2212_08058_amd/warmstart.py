@@ -153,9 +153,12 @@ def solve_from(x0: torch.Tensor, f, kern, tol=1e-4, cap=2000, x=None, ws=None, s
 
     One device chain: it stops after its second step if that residual is
     above the first (the rule is checked on the device), and only then is the
-    iteration restarted from the uniform start. Returns (x, info dict); info
-    has iters (all applications, including the fallback's wasted ones),
-    fallback flag, r1, r2, converged, residual.
+    iteration restarted from the uniform start. A warm start the iteration
+    cannot use at all (a zero or non-finite norm on its first steps: e.g. an
+    x0 that vanishes wherever f > 0, or a non-finite net output) falls back
+    the same way. Returns (x, info dict); info has iters (all applications,
+    including the fallback's wasted ones), fallback flag, r1, r2, converged,
+    residual.
     """
     if x is None:
         x = x0
@@ -163,7 +166,8 @@ def solve_from(x0: torch.Tensor, f, kern, tol=1e-4, cap=2000, x=None, ws=None, s
         x.copy_(x0)
     x, r = power_iterate(f, kern, tol=tol, max_iters=cap, x0=x, x=x, ws=ws, stream=stream, check=False,
                          rise_check=True)
-    info = dict(r1=r["r1"], r2=r["r2"] if r["iters"] >= 2 else None, fallback=bool(r["flags"] & 4),
+    failed = bool(r["flags"] & 3)  # zero or non-finite norm
+    info = dict(r1=r["r1"], r2=r["r2"] if r["iters"] >= 2 else None, fallback=bool(r["flags"] & 4) or failed,
                 iters=r["iters"], converged=r["converged"], residual=r["residual"])
     if info["fallback"]:
         x, r2 = power_iterate(f, kern, tol=tol, max_iters=cap, x=x, ws=ws, stream=stream, check=False)

@@ -235,3 +235,71 @@ def _batch_product_form_checks(Pm, B, kern, shapes, fs):
     for k in (0, 3, 5):
         xr, oi = oracle.iterate(fz[k], okf(kern), tol=1e-4, cap=50)
         assert abs(res[k]["iters"] - oi.iters) <= 1, (k, res[k]["iters"], oi.iters)
+
+
+@pytest.mark.parametrize("kp", [(2.0, 1.0, 4, 2), (4.0, 1.5, 8, 3)])
+def test_batch_rise_check_restarts_on_device(P, kp):
+    """init = 2: per clip, the warm-start rule (restart from the uniform start
+    if the second residual exceeds the first) runs on the device. Warm starts
+    made to rise (the second eigenvector of the clip's dense A plus 1e-3 of the
+    first: the iterate then turns away from it faster at the second step)
+    restart: their result is bitwise that of a uniform-start run two steps
+    shorter, flags bit 2 set, iteration count including the discarded steps.
+    The other clips (start near the Perron vector) are bitwise the init = 0
+    run. Both the plain tile loop (r = (4, 2)) and the matrix-core loop in
+    product form (r = (8, 3))."""
+    Pm, B = P
+    kern = Pm.Kernel(*kp)
+    shapes = [(3, 8, 12), (2, 10, 14), (4, 6, 15), (3, 9, 9)]
+    fs = _clips(shapes, seed=40)
+    x0s, bad = [], []
+    for i, f in enumerate(fs):
+        A = oracle.dense_matrix(f, okf(kern))
+        lam, V = np.linalg.eigh(A)
+        v1, v2 = V[:, -1] * np.sign(V[:, -1].sum()), V[:, -2]
+        if i % 2 == 0:
+            x0 = v2 + 1e-3 * v1
+        else:
+            x0 = v1 + 1e-3 * np.random.default_rng(i).standard_normal(v1.size)
+        x0s.append(torch.from_numpy((x0 / np.linalg.norm(x0)).reshape(f.shape).astype(np.float32)).to(DEV))
+        bad.append(i % 2 == 0)
+    plan = B.BatchPlan(shapes, kern)
+    print("plan", plan.info())
+    f_flat = plan.pack([torch.from_numpy(f).to(DEV) for f in fs])
+    n = 12
+    x_warm = plan.pack(x0s)
+    x_warm, res = plan.iterate(f_flat, x_warm, init=2, max_iters=n, tol=0.0)
+    x_unif, res_u = plan.iterate(f_flat, init=1, max_iters=n - 2, tol=0.0)
+    x_plain = plan.pack(x0s)
+    x_plain, res_p = plan.iterate(f_flat, x_plain, init=0, max_iters=n, tol=0.0)
+    torch.cuda.synchronize()
+    for i, (r, ru, rp) in enumerate(zip(res, res_u, res_p)):
+        xw, xu, xp = (list(plan.views(v))[i] for v in (x_warm, x_unif, x_plain))
+        print(i, "bad" if bad[i] else "good", "r1", r["r1"], "r2", r["r2"], "flags", r["flags"], "iters", r["iters"])
+        assert r["iters"] == n
+        if bad[i]:
+            assert r["r2"] > r["r1"] and r["flags"] & 4
+            assert torch.equal(xw, xu) and r["lambda_"] == ru["lambda_"] and r["residual"] == ru["residual"]
+        else:
+            assert r["r2"] <= r["r1"] and not r["flags"] & 4
+            assert torch.equal(xw, xp) and r["lambda_"] == rp["lambda_"]
+
+
+def test_batch_converged_clips_leave_the_tile_list(P):
+    """Clips that stop at different iterations leave the active tile list
+    (rebuilt after every step): every clip's result is bitwise that of the
+    same clip planned alone, iteration count and convergence included."""
+    Pm, B = P
+    kern = Pm.Kernel(4.0, 1.5, 8, 3)
+    shapes = [(16, 120, 216)] * 6 + [(16, 120, 216)]
+    fs = _clips(shapes, seed=50)
+    plan = B.BatchPlan(shapes, kern)
+    f_flat = plan.pack([torch.from_numpy(f).to(DEV) for f in fs])
+    x_flat, res = plan.iterate(f_flat, max_iters=300, tol=1e-4)
+    iters = [r["iters"] for r in res]
+    print("iterations", iters)
+    for i, f in enumerate(fs):
+        one = B.BatchPlan([shapes[i]], kern)
+        xo, ro = one.iterate(one.pack([torch.from_numpy(f).to(DEV)]), max_iters=300, tol=1e-4)
+        assert ro[0]["iters"] == res[i]["iters"] and ro[0]["converged"] == res[i]["converged"]
+        assert torch.equal(list(one.views(xo))[0], list(plan.views(x_flat))[i])

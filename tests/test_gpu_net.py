@@ -145,3 +145,36 @@ def test_warm_start_and_fallback(W):
     xg = x.double().cpu().numpy()
     assert 1 - abs(float(np.sum(xg * xstar))) < 1e-3
     assert oracle.fallback(info["r1"], info["r2"])
+
+
+def test_unusable_warm_start_falls_back(W):
+    """A warm start that vanishes wherever f > 0 (A x0 = 0) or holds a
+    non-finite value falls back to the uniform start and still finds the
+    principal eigenvector (the dense eigh Perron vector)."""
+    from paper_2212_08058_amd import Kernel
+    kern = Kernel(2.0, 1.0, 2, 1)
+    k = oracle.Kernel(2.0, 1.0, 2, 1)
+    f = np.zeros((2, 8, 16))
+    f[:, 2:6, 1:5] = 1.0
+    f[:, 2:6, 10:14] = 0.6
+    A = oracle.dense_matrix(f, k)
+    _, V = np.linalg.eigh(A)
+    xstar = (V[:, -1] * np.sign(V[:, -1].sum())).reshape(f.shape)
+    fd = torch.from_numpy(f.astype(np.float32)).to(DEV)
+
+    class Mock:
+        def __init__(self, x0):
+            self.v = torch.from_numpy(np.ascontiguousarray(x0, dtype=np.float32)).to(DEV)
+
+        def x0(self, _f):
+            return self.v.clone()
+
+    off_support = (f == 0).astype(np.float32)   # zero wherever f > 0
+    nonfinite = np.ones_like(f, dtype=np.float32)
+    nonfinite[0, 0, 0] = np.inf
+    for name, x0 in (("zero on supp(f)", off_support), ("non-finite", nonfinite)):
+        x, info, _ = W.solve_warm(Mock(x0), fd, kern, tol=1e-6, cap=5000)
+        print(name, info)
+        assert info["fallback"] and info["converged"], name
+        xg = x.double().cpu().numpy()
+        assert 1 - float(np.sum(xg * xstar)) < 1e-5, name
