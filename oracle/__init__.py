@@ -12,6 +12,12 @@ What it computes, each function citing the passage it restates:
   -- Eq. 2 with alpha = 0, Eq. 4, first convolution term of Eq. 7.
 * ``iterate``: power iteration with global L2 normalisation after every
   application (Eq. 4 + Eq. 8, Alg. 1 outer loop).
+* ``sfseg_apply``/``sfseg_apply_at``/``sfseg_iterate``/``sfseg_dense``: the
+  full SFSeg operator with the first-order Taylor affinity of Eq. 2
+  (alpha > 0, unary map s = S^p distinct from the pairwise feature f), in the
+  scaling of the update of Eq. 7 (M / alpha), as a direct neighbourhood sum
+  (C) and as an explicit matrix; ``sfseg_apply_conv`` restates Eq. 7 itself
+  (three Gaussian filterings of s x, f^2 s x and f s x, recombined per voxel).
 * ``dense_matrix``/``perron``: the explicit N x N adjacency on tiny volumes and
   its principal eigenvector (Eq. 3, Perron-Frobenius).
 * ``combine``/``combine_bwd``: softmax-weighted channel sum f = sum_c
@@ -70,6 +76,8 @@ def _load():
         ci, cd = ctypes.c_int, ctypes.c_double
         lib.oracle_apply.argtypes = [ci, ci, ci, dp, dp, cd, cd, ci, ci, dp]
         lib.oracle_apply_at.argtypes = [ci, ci, ci, dp, dp, cd, cd, ci, ci, i64p, ctypes.c_int64, dp]
+        lib.oracle_sfseg_apply.argtypes = [ci, ci, ci, dp, dp, dp, cd, cd, cd, ci, ci, dp]
+        lib.oracle_sfseg_apply_at.argtypes = [ci, ci, ci, dp, dp, dp, cd, cd, cd, ci, ci, i64p, ctypes.c_int64, dp]
         lib.oracle_conv3d_fwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp]
         lib.oracle_conv3d_bwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp, dp, dp]
         lib.oracle_num_threads.restype = ci
@@ -156,8 +164,13 @@ def iterate(f, k: Kernel, x0=None, iters: int | None = None, tol: float | None =
     Returns (x, IterInfo) or, with keep=True, (x, IterInfo, [x_0 .. x_K]).
     """
     f = _f64(f)
-    N = f.size
-    x = np.full(f.shape, 1.0 / math.sqrt(N)) if x0 is None else _f64(x0).copy()
+    return _power(lambda v: apply(f, v, k), f.shape, x0, iters, tol, cap, keep)
+
+
+def _power(apply_fn, shape, x0, iters, tol, cap, keep):
+    """The loop of ``iterate`` for any operator ``apply_fn``."""
+    N = int(np.prod(shape))
+    x = np.full(shape, 1.0 / math.sqrt(N)) if x0 is None else _f64(x0).copy()
     nx = math.sqrt(float(np.sum(x * x)))
     if not nx > 0:
         raise ValueError("x0 has zero norm")
@@ -166,7 +179,7 @@ def iterate(f, k: Kernel, x0=None, iters: int | None = None, tol: float | None =
     info = IterInfo(residuals=[], lambdas=[], rayleigh=[])
     traj = [x.copy()] if keep else None
     for _ in range(limit):
-        z = apply(f, x, k)
+        z = apply_fn(x)
         n = math.sqrt(float(np.sum(z * z)))
         if not math.isfinite(n):
             info.status = "nonfinite"
@@ -189,6 +202,72 @@ def iterate(f, k: Kernel, x0=None, iters: int | None = None, tol: float | None =
     if keep:
         return x, info, traj
     return x, info
+
+
+def sfseg_apply(s, f, x, alpha: float, k: Kernel) -> np.ndarray:
+    """z = (M x) / alpha with M_ij = s_i s_j [1 - alpha (f_i - f_j)^2] G_ij
+    (Eq. 2, Taylor affinity; the update of Eq. 5-7), direct loop in FP64."""
+    s, f, x = _f64(s), _f64(f), _f64(x)
+    assert s.ndim == 3 and s.shape == f.shape == x.shape
+    T, H, W = s.shape
+    z = np.empty_like(s)
+    rc = _load().oracle_sfseg_apply(T, H, W, _dptr(s), _dptr(f), _dptr(x), float(alpha), k.sigma_s, k.sigma_t,
+                                    k.r_s, k.r_t, _dptr(z))
+    if rc != 0:
+        raise ValueError("oracle_sfseg_apply: invalid arguments")
+    return z
+
+
+def sfseg_apply_at(s, f, x, alpha: float, k: Kernel, idx) -> np.ndarray:
+    """(M x)_i / alpha for the flat indices ``idx`` only."""
+    s, f, x = _f64(s), _f64(f), _f64(x)
+    T, H, W = s.shape
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    out = np.empty(idx.shape, dtype=np.float64)
+    rc = _load().oracle_sfseg_apply_at(T, H, W, _dptr(s), _dptr(f), _dptr(x), float(alpha), k.sigma_s, k.sigma_t,
+                                       k.r_s, k.r_t, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.size,
+                                       _dptr(out))
+    if rc != 0:
+        raise ValueError("oracle_sfseg_apply_at: invalid arguments or index out of range")
+    return out
+
+
+def sfseg_apply_conv(s, f, x, alpha: float, k: Kernel) -> np.ndarray:
+    """Eq. 7 as written: S (1/alpha - F^2) G*(S X) - S G*(F^2 S X) + 2 S F G*(F S X),
+    each G* a plain Gaussian filtering (``apply`` with a unit feature)."""
+    s, f, x = _f64(s), _f64(f), _f64(x)
+    one = np.ones_like(s)
+    u = s * x
+    g1 = apply(one, u, k)
+    g2 = apply(one, f * f * u, k)
+    g3 = apply(one, f * u, k)
+    return s * (1.0 / alpha - f * f) * g1 - s * g2 + 2.0 * s * f * g3
+
+
+def sfseg_iterate(s, f, alpha: float, k: Kernel, x0=None, iters: int | None = None, tol: float | None = None,
+                  cap: int | None = None):
+    """Power iteration with the full operator (Eq. 7 then the normalisation of
+    Eq. 8), the same loop, start and stopping rule as ``iterate``."""
+    return _power(lambda v: sfseg_apply(s, f, v, alpha, k), _f64(s).shape, x0, iters, tol, cap, False)
+
+
+def sfseg_dense(s, f, alpha: float, k: Kernel) -> np.ndarray:
+    """Explicit M / alpha (tiny volumes only), built pair by pair from Eq. 2."""
+    s, f = _f64(s), _f64(f)
+    T, H, W = s.shape
+    N = s.size
+    if N > 4096:
+        raise ValueError("sfseg_dense is for tiny volumes")
+    coords = [(t, y, x) for t in range(T) for y in range(H) for x in range(W)]
+    sf, ff = s.reshape(-1), f.reshape(-1)
+    M = np.zeros((N, N))
+    for i, (ti, yi, xi) in enumerate(coords):
+        for j, (tj, yj, xj) in enumerate(coords):
+            dt, dy, dx = tj - ti, yj - yi, xj - xi
+            if abs(dt) <= k.r_t and abs(dy) <= k.r_s and abs(dx) <= k.r_s:
+                g = math.exp(-(dt * dt) / (2 * k.sigma_t ** 2) - (dy * dy + dx * dx) / (2 * k.sigma_s ** 2))
+                M[i, j] = sf[i] * sf[j] * (1.0 - alpha * (ff[i] - ff[j]) ** 2) * g
+    return M / alpha
 
 
 def dense_matrix(f, k: Kernel) -> np.ndarray:

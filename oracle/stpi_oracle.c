@@ -133,6 +133,86 @@ int oracle_apply_at(int T, int H, int W, const double *f, const double *x,
 }
 
 /* ---------------------------------------------------------------------------
+ * Full SFSeg operator (Sec. 3: Eq. 2, its first-order Taylor affinity, and the
+ * power-iteration update of Eq. 5-7). With the unary map s (already raised to
+ * the power p) and the pairwise feature f,
+ *
+ *   M_ij = s_i s_j [1 - alpha (f_i - f_j)^2] G_ij                  (Eq. 2)
+ *
+ * and the update as Eq. 7 writes it (Eq. 5 without its leading alpha) is
+ *
+ *   z_i = (M x)_i / alpha = s_i sum_{j in N(i)} s_j [1/alpha - (f_i - f_j)^2] G_ij x_j.
+ *
+ * Direct 3D box loop in double, in (dt, dy, dx) order, like oracle_apply.
+ * ------------------------------------------------------------------------- */
+static double sfseg_sum(int T, int H, int W, const double *s, const double *f, const double *xv, double ainv,
+                        const double *w, int r_s, int r_t, int t, int y, int x) {
+    int ns = 2 * r_s + 1;
+    double fi = f[((size_t)t * H + y) * W + x];
+    double acc = 0.0;
+    for (int dt = -r_t; dt <= r_t; ++dt) {
+        int tt = t + dt;
+        if (tt < 0 || tt >= T) continue;
+        for (int dy = -r_s; dy <= r_s; ++dy) {
+            int yy = y + dy;
+            if (yy < 0 || yy >= H) continue;
+            const double *wrow = w + ((size_t)(dt + r_t) * ns + (dy + r_s)) * ns + r_s;
+            size_t base = ((size_t)tt * H + yy) * W;
+            for (int dx = -r_s; dx <= r_s; ++dx) {
+                int xx = x + dx;
+                if (xx < 0 || xx >= W) continue;
+                double d = fi - f[base + xx];
+                acc += s[base + xx] * (ainv - d * d) * wrow[dx] * xv[base + xx];
+            }
+        }
+    }
+    return acc;
+}
+
+int oracle_sfseg_apply(int T, int H, int W, const double *s, const double *f, const double *x, double alpha,
+                       double sigma_s, double sigma_t, int r_s, int r_t, double *z) {
+    if (T < 1 || H < 1 || W < 1 || r_s < 0 || r_t < 0 || !(sigma_s > 0) || !(sigma_t > 0) || !(alpha > 0))
+        return 1;
+    double *w = weight_box(sigma_s, sigma_t, r_s, r_t);
+    if (!w) return 1;
+    double ainv = 1.0 / alpha;
+    long rows = (long)T * H;
+#pragma omp parallel for schedule(static)
+    for (long row = 0; row < rows; ++row) {
+        int t = (int)(row / H), y = (int)(row % H);
+        for (int xi = 0; xi < W; ++xi) {
+            size_t i = (size_t)row * W + xi;
+            z[i] = s[i] * sfseg_sum(T, H, W, s, f, x, ainv, w, r_s, r_t, t, y, xi);
+        }
+    }
+    free(w);
+    return 0;
+}
+
+int oracle_sfseg_apply_at(int T, int H, int W, const double *s, const double *f, const double *x, double alpha,
+                          double sigma_s, double sigma_t, int r_s, int r_t, const int64_t *idx, int64_t n_idx,
+                          double *out) {
+    if (T < 1 || H < 1 || W < 1 || r_s < 0 || r_t < 0 || !(sigma_s > 0) || !(sigma_t > 0) || !(alpha > 0))
+        return 1;
+    double *w = weight_box(sigma_s, sigma_t, r_s, r_t);
+    if (!w) return 1;
+    double ainv = 1.0 / alpha;
+    int64_t N = (int64_t)T * H * W;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t k = 0; k < n_idx; ++k) {
+        int64_t i = idx[k];
+        if (i < 0 || i >= N) { bad |= 1; out[k] = NAN; continue; }
+        int t = (int)(i / ((int64_t)H * W));
+        int y = (int)((i / W) % H);
+        int xi = (int)(i % W);
+        out[k] = s[i] * sfseg_sum(T, H, W, s, f, x, ainv, w, r_s, r_t, t, y, xi);
+    }
+    free(w);
+    return bad;
+}
+
+/* ---------------------------------------------------------------------------
  * Warm-start network: 'same' 3x3x3 convolution, zero padding, bias.
  * in  [Cin][T][H][W], wgt [Cout][Cin][3][3][3], bias [Cout], out [Cout][T][H][W]
  *   out[o,t,y,x] = bias[o] + sum_{i,a,b,c} wgt[o,i,a,b,c] * in[i, t+a-1, y+b-1, x+c-1]

@@ -546,3 +546,95 @@ def test_net_loss_and_warm_start_against_torch():
     x0 = oracle.warm_start_x0(y, eps=1e-3)
     ref = torch.nn.functional.normalize((torch.relu(torch.tensor(y)) + 1e-3).reshape(-1), dim=0).reshape(y.shape)
     np.testing.assert_allclose(x0, ref.numpy(), rtol=1e-14, atol=1e-16)
+
+
+# --- the full SFSeg operator (Eq. 2 Taylor affinity, Eq. 5-7) -----------------
+
+def _sfseg_case(seed, shape=(3, 6, 7)):
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(0.05, 1.0, shape)
+    f = rng.uniform(0.0, 1.0, shape)
+    x = rng.standard_normal(shape)
+    return s, f, x
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.3, 2.5])
+def test_sfseg_apply_matches_pairwise_matrix(alpha):
+    """The direct loop equals the explicit matrix built pair by pair from
+    Eq. 2's affinity s_i s_j [1 - alpha (f_i - f_j)^2] G_ij, divided by alpha."""
+    k = Kernel(1.7, 0.9, 2, 1)
+    s, f, x = _sfseg_case(3)
+    M = oracle.sfseg_dense(s, f, alpha, k)
+    z = oracle.sfseg_apply(s, f, x, alpha, k)
+    ref = (M @ x.reshape(-1)).reshape(x.shape)
+    assert np.max(np.abs(z - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("k", [Kernel(1.7, 0.9, 2, 1), Kernel(3.0, 1.5, 5, 2)])
+def test_sfseg_apply_matches_three_library_correlations(k):
+    """Eq. 7: S (1/alpha - F^2) G*(S X) - S G*(F^2 S X) + 2 S F G*(F S X), each
+    G* computed with scipy's zero-padded correlation."""
+    s, f, x = _sfseg_case(4, (4, 9, 11))
+    alpha = 0.7
+    G3 = np.einsum("a,b,c->abc", _g1(k.r_t, k.sigma_t), _g1(k.r_s, k.sigma_s), _g1(k.r_s, k.sigma_s))
+
+    def conv(v):
+        return ndimage.correlate(v, G3, mode="constant", cval=0.0)
+
+    u = s * x
+    ref = s * (1 / alpha - f * f) * conv(u) - s * conv(f * f * u) + 2 * s * f * conv(f * u)
+    z = oracle.sfseg_apply(s, f, x, alpha, k)
+    assert np.max(np.abs(z - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(oracle.sfseg_apply_conv(s, f, x, alpha, k) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_sfseg_special_cases():
+    """Constant f: every pairwise difference vanishes and the operator is the
+    single-field one on s, divided by alpha. alpha -> 0: alpha times the
+    operator tends to the single-field one (the Taylor term is O(alpha))."""
+    k = Kernel(2.0, 1.0, 3, 2)
+    s, f, x = _sfseg_case(5, (3, 8, 9))
+    fc = np.full_like(f, 0.37)
+    for alpha in (1.0, 0.25):
+        z = oracle.sfseg_apply(s, fc, x, alpha, k)
+        ref = oracle.apply(s, x, k) / alpha
+        assert np.max(np.abs(z - ref)) <= 1e-13 * np.max(np.abs(ref))
+    a = 1e-9
+    z = a * oracle.sfseg_apply(s, f, x, a, k)
+    ref = oracle.apply(s, x, k)
+    assert np.max(np.abs(z - ref)) <= 1e-7 * np.max(np.abs(ref))
+
+
+def test_sfseg_symmetry_and_scaling():
+    """M is symmetric (<y, M x> = <M y, x>); z is quadratic in s and linear in x."""
+    k = Kernel(2.0, 1.0, 3, 1)
+    s, f, x = _sfseg_case(6, (3, 7, 10))
+    y = np.random.default_rng(60).standard_normal(x.shape)
+    a = float(np.sum(y * oracle.sfseg_apply(s, f, x, 0.8, k)))
+    b = float(np.sum(oracle.sfseg_apply(s, f, y, 0.8, k) * x))
+    assert abs(a - b) <= 1e-12 * abs(a)
+    z1 = oracle.sfseg_apply(s, f, x, 0.8, k)
+    z2 = oracle.sfseg_apply(2.0 * s, f, 3.0 * x, 0.8, k)
+    assert np.max(np.abs(z2 - 12.0 * z1)) <= 1e-12 * np.max(np.abs(z2))
+
+
+def test_sfseg_perron_vector_and_negative_affinity():
+    """With f in [0, 1] and alpha <= 1 every affinity is >= 0 and the power
+    iteration reaches the nonnegative principal eigenvector of the dense
+    matrix (eigh). With alpha (max f - min f)^2 > 1 some affinities are negative."""
+    k = Kernel(2.0, 1.0, 2, 1)
+    rng = np.random.default_rng(7)
+    s = rng.uniform(0.1, 1.0, (3, 6, 8))
+    f = rng.uniform(0.0, 1.0, s.shape)
+    M = oracle.sfseg_dense(s, f, 1.0, k)
+    assert M.min() >= 0.0
+    lam, v, w = oracle.perron(M)
+    assert w[-1] - w[-2] > 1e-3 * w[-1]
+    x, info = oracle.sfseg_iterate(s, f, 1.0, k, tol=1e-13, cap=20000)
+    assert info.converged
+    xf = x.reshape(-1)
+    assert 1.0 - float(xf @ v) < 1e-12
+    assert xf.min() >= -1e-15
+    assert abs(info.lambdas[-1] - lam) <= 1e-10 * lam
+    Mneg = oracle.sfseg_dense(s, f, 4.0, k)
+    assert Mneg.min() < 0.0
