@@ -109,6 +109,54 @@ def cpu_baseline(f_np, kern, seconds: float):
                        f"{dt:.1f} s on {threads} threads; {n1} voxels in {dt1:.1f} s on 1 thread")
 
 
+def sfseg_leg(f_np, kern, iters, steps, warmup, reps, stream, dev):
+    """The full operator of Eq. 7 (three filtered fields) on the same clip: s =
+    the soft mask to the power p = 0.2, f = a second soft mask in [0, 1]
+    (standing in for the optical-flow magnitude), alpha = 1. Whole 20-iteration
+    jobs from the uniform start, and the step kernel timed with HIP events on
+    its stream (each timed call also launches the two-sum reduction kernel)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2212_08058_amd import sfseg as SF
+
+    T, H, W = f_np.shape
+    g, _ = synth.blob_clip(T, H, W, 3, 1001)
+    with torch.cuda.stream(stream):
+        s = SF.sfseg_unary(torch.from_numpy(f_np).to(dev), 0.2, stream=stream)
+        fd = torch.from_numpy(g).to(dev)
+        x = torch.empty_like(s)
+        ws = torch.empty(SF.sfseg_workspace_bytes(s.shape, kern), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        SF.sfseg_iterate(s, fd, kern, 1.0, iters=iters, x=x, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, r = SF.sfseg_iterate(s, fd, kern, 1.0, iters=iters, x=x, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    N = s.numel()
+    z = torch.empty_like(s)
+    SF.sfseg_step(s, fd, x, kern, 1.0, z=z, ws=ws, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        SF.sfseg_step(s, fd, x, kern, 1.0, z=z, ws=ws, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    kms = e0.elapsed_time(e1) / reps
+    # per voxel: 3 fields x (y, x and t taps) multiply-adds + staging and recombination
+    flop = 2 * 3 * (2 * (2 * kern.r_s + 1) + (2 * kern.r_t + 1)) + 12
+    return {"value": N * iters / dt, "unit": "voxel-iters/s", "ms_per_step": dt * 1e3, "iters": iters,
+            "alpha": 1.0, "p": 0.2, "lambda": r["lambda_"], "residual": r["residual"],
+            "roofline": {"bound": "alu", "achieved": flop * N / (kms * 1e-3) / 1e12, "peak": VALU_FP32_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": flop * N / (kms * 1e-3) / 1e12 / VALU_FP32_PEAK_TFLOPS,
+                         "flop_per_voxel": flop, "kernel": "sfseg_step_kernel", "kernel_ms": kms,
+                         "hbm_gbs": 16 * N / (kms * 1e-3) / 1e9, "bytes_per_voxel": 16}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,8 +169,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="let the autotuner pick the FP32 tile (default: the cost model's choice, which the "
                          "committed counter profile covers); the BF16 leg is always tuned")
-    ap.add_argument("--extras", default="bf16,copy,batch,warm",
-                    help="comma list of extra measurements to attach: bf16, copy, batch, channels, warm (or none)")
+    ap.add_argument("--extras", default="bf16,copy,sfseg,batch,warm",
+                    help="comma list of extra measurements to attach: bf16, copy, sfseg, batch, channels, warm "
+                         "(or none)")
     ap.add_argument("--warm-train", type=int, default=200, help="training clips for the warm-start extra")
     ap.add_argument("--warm-eval", type=int, default=24, help="evaluation clips for the warm-start extra")
     ap.add_argument("--warm-epochs", type=int, default=2, help="training epochs for the warm-start extra")
@@ -294,6 +343,9 @@ def main():
         out["copy"] = {"kernel": "scale_by_norm_kernel (reads one array, writes one array)",
                        "bytes_read": Nvox * elem, "bytes_written": Nvox * elem, "kernel_ms": cms,
                        "gbs": 2 * Nvox * elem / (cms * 1e-3) / 1e9}
+    if "sfseg" in extras and args.dtype == "f32":
+        log("full SFSeg operator (alpha = 1, p = 0.2)")
+        out["sfseg"] = sfseg_leg(f_np, kern, iters, args.steps, args.warmup, args.kernel_reps, stream, dev)
     from paper_2212_08058_amd import experiments as X
     if "batch" in extras:
         log("batched uneven clips")

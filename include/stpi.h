@@ -148,6 +148,39 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
  * masked by f != 0. STPI_NO_PRODUCT=1 in the environment selects the plain
  * form. */
 
+/* ---- full SFSeg operator (alpha > 0) ----------------------------------------
+ * The paper's update with the first-order Taylor affinity (Sec. 3: Eq. 2,
+ * Eq. 5-7; multi-channel form Eq. 10 with s = S_m^p, f = F_m):
+ *
+ *   z = s (1/alpha - f^2) G*(s x) - s G*(f^2 s x) + 2 s f G*(f s x),
+ *   z_i = s_i sum_j s_j [1/alpha - (f_i - f_j)^2] G_ij x_j  = (M x)_i / alpha,
+ *
+ * with M_ij = s_i s_j [1 - alpha (f_i - f_j)^2] G_ij (Eq. 2), s the unary map
+ * raised to the power p (stpi_sfseg_unary) and f the pairwise feature, G as
+ * for stpi_iterate. The three filtered fields go through one fused stencil
+ * pass. float (STPI_F32) and double (STPI_F64) storage; r_s <= 16, r_t <= 5
+ * (STPI_EUNSUPPORTED otherwise). M is symmetric; it is nonnegative (Perron
+ * semantics) when s >= 0 and alpha (max f - min f)^2 <= 1, e.g. f in [0, 1]
+ * and alpha <= 1; stpi_sfseg_iterate checks this on the device and fails with
+ * STPI_EINVAL (flags bit 4) when it does not hold. */
+
+/* s = S^p elementwise (S >= 0, p >= 0; device volumes of n elements). */
+int stpi_sfseg_unary(int64_t n, int dtype, const void *S, double p, void *s, void *stream);
+/* Device workspace of stpi_sfseg_step / stpi_sfseg_iterate (0 if p is invalid
+ * or unsupported). */
+size_t stpi_sfseg_workspace_bytes(const stpi_problem *p);
+/* One application, unnormalised: z as above with x scaled by x_scale;
+ * d_sums[0] = sum z^2, d_sums[1] = sum z .* x * x_scale (device doubles).
+ * z must not alias s, f or x. */
+int stpi_sfseg_step(const stpi_problem *p, const void *s, const void *f, double alpha, const void *x,
+                    double x_scale, void *z, double *d_sums, void *ws, size_t ws_bytes, void *stream);
+/* Power iteration with the full operator (Eq. 7 then Eq. 8; Alg. 1 without
+ * its soft-binarisation): x in/out, init = 1 uniform start, init = 0 the
+ * caller's x (Alg. 1 starts from the unary map: pass it as x). Stopping, the
+ * result and the residual as stpi_iterate. Synchronises `stream`. */
+int stpi_sfseg_iterate(const stpi_problem *p, const void *s, const void *f, double alpha, void *x, int init,
+                       int max_iters, double tol, void *ws, size_t ws_bytes, stpi_result *out, void *stream);
+
 /* ---- kernel variants ------------------------------------------------------
  * Each storage type has a list of compiled step kernels (radii RS >= r_s,
  * RT >= r_t, tile TH x TW, NTHR threads, RY rows per y-pass item, QX outputs

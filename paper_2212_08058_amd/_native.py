@@ -62,6 +62,12 @@ PROTOTYPES = [
     ("stpi_step_noalloc_scratch_bytes", _sz, [_PP]),
     ("stpi_step_noalloc", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     ("stpi_iterate", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _sz, _RP, _vp]),
+    ("stpi_sfseg_unary", ctypes.c_int, [ctypes.c_int64, ctypes.c_int, _vp, ctypes.c_double, _vp, _vp]),
+    ("stpi_sfseg_workspace_bytes", _sz, [_PP]),
+    ("stpi_sfseg_step", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _vp, _vp, _vp, _sz,
+                                       _vp]),
+    ("stpi_sfseg_iterate", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_double, _vp, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, _vp, _sz, _RP, _vp]),
     ("stpi_variant_count", ctypes.c_int, [ctypes.c_int]),
     ("stpi_variant_info", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
     ("stpi_launch_shape", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),

@@ -100,6 +100,7 @@ constexpr uint64_t PARTIAL_EMPTY = 0x7ff4dead5a17ab1eull;
 // the arrival counter is only bumped after the slot's store has completed).
 constexpr int PARTIAL_SPIN_LIMIT = 1 << 20;
 constexpr uint32_t FLAG_SYNC = 8u;  // a partial sum never arrived (see PARTIAL_SPIN_LIMIT)
+constexpr uint32_t FLAG_AFFINITY = 16u;  // full operator: a Taylor affinity could be negative (see sfseg.hip)
 
 // Workgroup size and summation order of the per-step reduction of partial
 // sums: thread i < FINAL_THREADS adds entries i, i + FINAL_THREADS, ... in

@@ -123,7 +123,7 @@ static int tiles_for(const Variant &v, const stpi_problem *p) {
     return ((p->W + v.TW - 1) / v.TW) * ((p->H + v.TH - 1) / v.TH);
 }
 
-static int device_cus() {
+int device_cus() {
     static int cus[64] = {0};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;

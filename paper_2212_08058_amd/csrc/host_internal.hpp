@@ -56,6 +56,7 @@ hipError_t launch_state_from_norm(const double *partials, int n, DevState *s, hi
 hipError_t launch_clear_word(uint32_t *w, hipStream_t st);
 hipError_t launch_partials_empty(double *partials, int n, hipStream_t st);
 bool fusion_disabled();
+int device_cus();  // compute units of the current device
 hipError_t launch_finalize(const double *partials, int n, DevState *s, hipStream_t st);
 hipError_t launch_step_sums(const double *partials, int n, double x_scale, double *d_sums, hipStream_t st);
 hipError_t launch_combine_bwd_finalize(int C, int nblocks, const double *partials, const double *w, double *gw,
