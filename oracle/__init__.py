@@ -18,6 +18,9 @@ What it computes, each function citing the passage it restates:
   scaling of the update of Eq. 7 (M / alpha), as a direct neighbourhood sum
   (C) and as an explicit matrix; ``sfseg_apply_conv`` restates Eq. 7 itself
   (three Gaussian filterings of s x, f^2 s x and f s x, recombined per voxel).
+* ``online_iterate``: partial iterations over moving sub-windows, each
+  started from the previous window's solution on the shared frames (Sec. 4,
+  "Online vs Offline processing").
 * ``dense_matrix``/``perron``: the explicit N x N adjacency on tiny volumes and
   its principal eigenvector (Eq. 3, Perron-Frobenius).
 * ``combine``/``combine_bwd``: softmax-weighted channel sum f = sum_c
@@ -268,6 +271,36 @@ def sfseg_dense(s, f, alpha: float, k: Kernel) -> np.ndarray:
                 g = math.exp(-(dt * dt) / (2 * k.sigma_t ** 2) - (dy * dy + dx * dx) / (2 * k.sigma_s ** 2))
                 M[i, j] = sf[i] * sf[j] * (1.0 - alpha * (ff[i] - ff[j]) ** 2) * g
     return M / alpha
+
+
+def online_iterate(f, k: Kernel, q: int, shift: int, iters: int | None = None, tol: float | None = None,
+                   cap: int | None = None):
+    """Partial iterations over q-frame sub-windows (Sec. 4, "Online vs Offline
+    processing"): windows start at frames 0, shift, 2 shift, ... (the last one
+    ends at the last frame); a window's start vector takes the previous
+    window's final solution on the frames the two share and the uniform value
+    1/sqrt(q H W) on its new frames; each frame keeps the value of the last
+    window that contains it. Returns (x, [IterInfo per window])."""
+    f = _f64(f)
+    T = f.shape[0]
+    starts = list(range(0, T - q + 1, shift))
+    if starts[-1] != T - q:
+        starts.append(T - q)
+    out = np.zeros_like(f)
+    infos = []
+    prev, prev_a = None, None
+    c = 1.0 / math.sqrt(q * f.shape[1] * f.shape[2])
+    for a in starts:
+        x0 = np.full((q,) + f.shape[1:], c)
+        if prev is not None:
+            m = a - prev_a
+            for t in range(q - m):
+                x0[t] = prev[t + m]
+        x, info = iterate(f[a:a + q], k, x0=x0, iters=iters, tol=tol, cap=cap)
+        out[a:a + q] = x
+        infos.append(info)
+        prev, prev_a = x, a
+    return out, infos
 
 
 def dense_matrix(f, k: Kernel) -> np.ndarray:

@@ -638,3 +638,30 @@ def test_sfseg_perron_vector_and_negative_affinity():
     assert abs(info.lambdas[-1] - lam) <= 1e-10 * lam
     Mneg = oracle.sfseg_dense(s, f, 4.0, k)
     assert Mneg.min() < 0.0
+
+
+# --- online / partial iteration over sub-windows ----------------------------
+
+def test_online_iterate_limits():
+    """One window covering the video is the full iteration; windows that do
+    not overlap are independent iterations from the uniform start; the start
+    of an overlapping window carries the previous solution's shared frames
+    (checked on a case whose windows shift by one frame: frame t of window
+    w + 1 starts at frame t + 1 of window w's solution)."""
+    rng = np.random.default_rng(71)
+    f = rng.uniform(0.05, 1.0, (6, 5, 7))
+    k = Kernel(1.5, 1.0, 2, 1)
+    x_full, info = oracle.iterate(f, k, iters=7)
+    x_one, infos = oracle.online_iterate(f, k, q=6, shift=3, iters=7)
+    assert len(infos) == 1 and np.array_equal(x_one, x_full)
+    x_sep, infos = oracle.online_iterate(f, k, q=3, shift=3, iters=5)
+    for a in (0, 3):
+        xa, _ = oracle.iterate(f[a:a + 3], k, iters=5)
+        assert np.max(np.abs(x_sep[a:a + 3] - xa)) <= 1e-15
+    # shift 1, one iteration per window: the second window's start is the
+    # first window's solution moved by one frame plus a uniform last frame
+    w0, _ = oracle.iterate(f[0:3], k, iters=1)
+    start = np.concatenate([w0[1:3], np.full((1, 5, 7), 1.0 / math.sqrt(3 * 5 * 7))])
+    w1, _ = oracle.iterate(f[1:4], k, x0=start, iters=1)
+    x4, infos = oracle.online_iterate(f[:4], k, q=3, shift=1, iters=1)
+    assert len(infos) == 2 and np.max(np.abs(x4[1:4] - w1)) <= 1e-15 and np.array_equal(x4[0], w0[0])
