@@ -148,6 +148,19 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
  * masked by f != 0. STPI_NO_PRODUCT=1 in the environment selects the plain
  * form. */
 
+/* ---- online / partial iteration over sub-windows ---------------------------
+ * Sec. 4, "Online vs Offline processing": a long or streaming video is
+ * processed in q-frame sub-windows; each window runs a few iterations,
+ * starting from the previous window's final solution on the frames the two
+ * share. stpi_window_start writes that start vector for a window of
+ * pw->T = q frames that lies `shift` frames after the previous one (x_prev,
+ * its final unit solution, q frames): frames [0, q - shift) take x_prev's
+ * frames [shift, q), the `shift` new frames the uniform start value
+ * 1/sqrt(q H W). shift = q (no overlap; x_prev may be NULL) gives the uniform
+ * start. Pass x0 to stpi_iterate with init = 0 (it normalises first). The
+ * Python driver online.online_iterate runs a whole video this way. */
+int stpi_window_start(const stpi_problem *pw, const void *x_prev, int shift, void *x0, void *stream);
+
 /* ---- full SFSeg operator (alpha > 0) ----------------------------------------
  * The paper's update with the first-order Taylor affinity (Sec. 3: Eq. 2,
  * Eq. 5-7; multi-channel form Eq. 10 with s = S_m^p, f = F_m):

@@ -247,3 +247,54 @@ def warm_start_experiment(n_train=2000, n_eval=200, epochs=2, train_shape=(16, 2
                                         iters_median=float(np.median([r["iters"] for r in res_w])),
                                         unconverged=sum(not r["converged"] for r in res_w))
     return out
+
+
+def online_vs_full(f_np, kern, settings=((16, 8, 5), (16, 8, 10), (32, 16, 10)), full_iters=20, tol=1e-4, cap=2000,
+                   reps=3, device="cuda", log=print):
+    """Partial iterations over sub-windows (Sec. 4, "Online vs Offline
+    processing") against iterating the whole video: wall time, and per-frame
+    agreement with the full video's solution converged to `tol` (cosine of the
+    frame's vectors, IoU of the masks x >= max(x) / 2 per frame), for the
+    windowed run and for a fixed full_iters-iteration full run."""
+    from . import online
+
+    f = torch.from_numpy(f_np).to(device)
+    x_conv, r_conv = power_iterate(f, kern, tol=tol, max_iters=cap)
+    x_full = torch.empty_like(f)
+    ws = torch.empty(workspace_bytes(f.shape, kern), dtype=torch.uint8, device=device)
+    out = torch.empty_like(f)
+
+    def timed(fn):
+        fn()
+        _sync()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            _sync()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    t_full = timed(lambda: power_iterate(f, kern, iters=full_iters, x=x_full, ws=ws))
+
+    def agree(x):
+        a = x.double()
+        b = x_conv.double()
+        cos = (a * b).sum(dim=(1, 2)) / (a.norm(dim=(1, 2)) * b.norm(dim=(1, 2)))
+        ma = a >= 0.5 * a.amax(dim=(1, 2), keepdim=True)
+        mb = b >= 0.5 * b.amax(dim=(1, 2), keepdim=True)
+        iou = (ma & mb).sum(dim=(1, 2)).double() / (ma | mb).sum(dim=(1, 2)).clamp(min=1).double()
+        return dict(cos_median=float(cos.median()), cos_min=float(cos.min()), iou_median=float(iou.median()),
+                    iou_min=float(iou.min()))
+
+    T = f.shape[0]
+    res = dict(full_iters=full_iters, converged_iters=r_conv["iters"], seconds_full=t_full,
+               frame_iterations_full=T * full_iters, full_vs_converged=agree(x_full), windows=[])
+    for q, shift, it in settings:
+        t_online = timed(lambda: online.online_iterate(f, kern, q, shift, iters=it, out=out, wait=False))
+        nwin = len(online.window_starts(T, q, shift))
+        res["windows"].append(dict(q=q, shift=shift, window_iters=it, windows=nwin, seconds=t_online,
+                                   speedup_vs_full=t_full / t_online, frame_iterations=nwin * q * it,
+                                   vs_converged=agree(out)))
+        log(f"  online q={q} shift={shift} iters={it}: {t_online * 1e3:.2f} ms, {res['windows'][-1]['vs_converged']}")
+    return res
