@@ -18,6 +18,10 @@ What it computes, each function citing the passage it restates:
   scaling of the update of Eq. 7 (M / alpha), as a direct neighbourhood sum
   (C) and as an explicit matrix; ``sfseg_apply_conv`` restates Eq. 7 itself
   (three Gaussian filterings of s x, f^2 s x and f s x, recombined per voxel).
+* ``exp_apply``/``exp_dense``/``exp_iterate``: the exact exponential pairwise
+  affinity of Eq. 1 (before the Taylor approximation), direct loop and
+  explicit matrix, for the exact-vs-approximate comparison of Sec. 4
+  ("Quantitative analysis").
 * ``online_iterate``: partial iterations over moving sub-windows, each
   started from the previous window's solution on the shared frames (Sec. 4,
   "Online vs Offline processing").
@@ -81,6 +85,7 @@ def _load():
         lib.oracle_apply_at.argtypes = [ci, ci, ci, dp, dp, cd, cd, ci, ci, i64p, ctypes.c_int64, dp]
         lib.oracle_sfseg_apply.argtypes = [ci, ci, ci, dp, dp, dp, cd, cd, cd, ci, ci, dp]
         lib.oracle_sfseg_apply_at.argtypes = [ci, ci, ci, dp, dp, dp, cd, cd, cd, ci, ci, i64p, ctypes.c_int64, dp]
+        lib.oracle_exp_apply.argtypes = [ci, ci, ci, dp, dp, dp, cd, cd, cd, ci, ci, dp]
         lib.oracle_conv3d_fwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp]
         lib.oracle_conv3d_bwd.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp, dp, dp]
         lib.oracle_num_threads.restype = ci
@@ -271,6 +276,44 @@ def sfseg_dense(s, f, alpha: float, k: Kernel) -> np.ndarray:
                 g = math.exp(-(dt * dt) / (2 * k.sigma_t ** 2) - (dy * dy + dx * dx) / (2 * k.sigma_s ** 2))
                 M[i, j] = sf[i] * sf[j] * (1.0 - alpha * (ff[i] - ff[j]) ** 2) * g
     return M / alpha
+
+
+def exp_apply(s, f, x, alpha: float, k: Kernel) -> np.ndarray:
+    """z = E x with the exact pairwise affinity of Eq. 1,
+    E_ij = s_i s_j exp(-alpha (f_i - f_j)^2) G_ij (direct loop, FP64)."""
+    s, f, x = _f64(s), _f64(f), _f64(x)
+    T, H, W = s.shape
+    z = np.empty_like(s)
+    rc = _load().oracle_exp_apply(T, H, W, _dptr(s), _dptr(f), _dptr(x), float(alpha), k.sigma_s, k.sigma_t,
+                                  k.r_s, k.r_t, _dptr(z))
+    if rc != 0:
+        raise ValueError("oracle_exp_apply: invalid arguments")
+    return z
+
+
+def exp_dense(s, f, alpha: float, k: Kernel) -> np.ndarray:
+    """Explicit E (tiny volumes only), built pair by pair from Eq. 1."""
+    s, f = _f64(s), _f64(f)
+    T, H, W = s.shape
+    N = s.size
+    if N > 4096:
+        raise ValueError("exp_dense is for tiny volumes")
+    coords = [(t, y, x) for t in range(T) for y in range(H) for x in range(W)]
+    sf, ff = s.reshape(-1), f.reshape(-1)
+    E = np.zeros((N, N))
+    for i, (ti, yi, xi) in enumerate(coords):
+        for j, (tj, yj, xj) in enumerate(coords):
+            dt, dy, dx = tj - ti, yj - yi, xj - xi
+            if abs(dt) <= k.r_t and abs(dy) <= k.r_s and abs(dx) <= k.r_s:
+                E[i, j] = sf[i] * sf[j] * math.exp(-alpha * (ff[i] - ff[j]) ** 2 - (dt * dt) / (2 * k.sigma_t ** 2)
+                                                   - (dy * dy + dx * dx) / (2 * k.sigma_s ** 2))
+    return E
+
+
+def exp_iterate(s, f, alpha: float, k: Kernel, x0=None, iters: int | None = None, tol: float | None = None,
+                cap: int | None = None):
+    """Power iteration with the exact affinity (the loop of ``iterate``)."""
+    return _power(lambda v: exp_apply(s, f, v, alpha, k), _f64(s).shape, x0, iters, tol, cap, False)
 
 
 def online_iterate(f, k: Kernel, q: int, shift: int, iters: int | None = None, tol: float | None = None,

@@ -213,6 +213,50 @@ int oracle_sfseg_apply_at(int T, int H, int W, const double *s, const double *f,
 }
 
 /* ---------------------------------------------------------------------------
+ * Exact pairwise affinity (Sec. 3, Eq. 1, before the Taylor approximation):
+ *
+ *   E_ij = s_i s_j exp(-alpha (f_i - f_j)^2) G_ij,   z = E x,
+ *
+ * direct 3D box loop in double, (dt, dy, dx) order.
+ * ------------------------------------------------------------------------- */
+int oracle_exp_apply(int T, int H, int W, const double *s, const double *f, const double *x, double alpha,
+                     double sigma_s, double sigma_t, int r_s, int r_t, double *z) {
+    if (T < 1 || H < 1 || W < 1 || r_s < 0 || r_t < 0 || !(sigma_s > 0) || !(sigma_t > 0) || !(alpha >= 0))
+        return 1;
+    double *w = weight_box(sigma_s, sigma_t, r_s, r_t);
+    if (!w) return 1;
+    int ns = 2 * r_s + 1;
+    long rows = (long)T * H;
+#pragma omp parallel for schedule(static)
+    for (long row = 0; row < rows; ++row) {
+        int t = (int)(row / H), y = (int)(row % H);
+        for (int xi = 0; xi < W; ++xi) {
+            size_t i = (size_t)row * W + xi;
+            double acc = 0.0;
+            for (int dt = -r_t; dt <= r_t; ++dt) {
+                int tt = t + dt;
+                if (tt < 0 || tt >= T) continue;
+                for (int dy = -r_s; dy <= r_s; ++dy) {
+                    int yy = y + dy;
+                    if (yy < 0 || yy >= H) continue;
+                    const double *wrow = w + ((size_t)(dt + r_t) * ns + (dy + r_s)) * ns + r_s;
+                    size_t base = ((size_t)tt * H + yy) * W;
+                    for (int dx = -r_s; dx <= r_s; ++dx) {
+                        int xx = xi + dx;
+                        if (xx < 0 || xx >= W) continue;
+                        double d = f[i] - f[base + xx];
+                        acc += s[base + xx] * exp(-alpha * d * d) * wrow[dx] * x[base + xx];
+                    }
+                }
+            }
+            z[i] = s[i] * acc;
+        }
+    }
+    free(w);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
  * Warm-start network: 'same' 3x3x3 convolution, zero padding, bias.
  * in  [Cin][T][H][W], wgt [Cout][Cin][3][3][3], bias [Cout], out [Cout][T][H][W]
  *   out[o,t,y,x] = bias[o] + sum_{i,a,b,c} wgt[o,i,a,b,c] * in[i, t+a-1, y+b-1, x+c-1]

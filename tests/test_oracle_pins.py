@@ -665,3 +665,42 @@ def test_online_iterate_limits():
     w1, _ = oracle.iterate(f[1:4], k, x0=start, iters=1)
     x4, infos = oracle.online_iterate(f[:4], k, q=3, shift=1, iters=1)
     assert len(infos) == 2 and np.max(np.abs(x4[1:4] - w1)) <= 1e-15 and np.array_equal(x4[0], w0[0])
+
+
+# --- exact exponential affinity (Eq. 1) ---------------------------------------
+
+def test_exp_apply_matches_pairwise_matrix_and_limits():
+    """The direct loop equals the explicit matrix of Eq. 1 built pair by pair;
+    alpha = 0 is the single-field operator on s; for small alpha the exact
+    affinity and alpha times the Taylor operator of Eq. 7 differ by O(alpha^2)
+    (exp(-a d^2) = 1 - a d^2 + O(a^2)), checked by the ratio of the errors at
+    alpha and alpha / 2."""
+    k = Kernel(1.7, 0.9, 2, 1)
+    rng = np.random.default_rng(81)
+    s = rng.uniform(0.05, 1.0, (3, 6, 7))
+    f = rng.uniform(0.0, 1.0, s.shape)
+    x = rng.standard_normal(s.shape)
+    for alpha in (0.0, 0.8, 3.0):
+        E = oracle.exp_dense(s, f, alpha, k)
+        z = oracle.exp_apply(s, f, x, alpha, k)
+        ref = (E @ x.reshape(-1)).reshape(x.shape)
+        assert np.max(np.abs(z - ref)) <= 1e-13 * np.max(np.abs(ref))
+    z0 = oracle.exp_apply(s, f, x, 0.0, k)
+    assert np.max(np.abs(z0 - oracle.apply(s, x, k))) <= 1e-13 * np.max(np.abs(z0))
+    errs = []
+    for a in (1e-2, 5e-3):
+        d = oracle.exp_apply(s, f, x, a, k) - a * oracle.sfseg_apply(s, f, x, a, k)
+        errs.append(np.max(np.abs(d)))
+    assert 3.5 <= errs[0] / errs[1] <= 4.5
+
+
+def test_exp_iterate_perron():
+    """The exact-affinity iteration reaches the principal eigenvector of E (eigh)."""
+    k = Kernel(2.0, 1.0, 2, 1)
+    rng = np.random.default_rng(82)
+    s = rng.uniform(0.1, 1.0, (3, 6, 8))
+    f = rng.uniform(0.0, 1.0, s.shape)
+    lam, v, w = oracle.perron(oracle.exp_dense(s, f, 2.0, k))
+    x, info = oracle.exp_iterate(s, f, 2.0, k, tol=1e-13, cap=20000)
+    assert info.converged and 1.0 - float(x.reshape(-1) @ v) < 1e-12
+    assert abs(info.lambdas[-1] - lam) <= 1e-10 * lam
