@@ -169,9 +169,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="let the autotuner pick the FP32 tile (default: the cost model's choice, which the "
                          "committed counter profile covers); the BF16 leg is always tuned")
-    ap.add_argument("--extras", default="bf16,copy,sfseg,online,batch,warm",
-                    help="comma list of extra measurements to attach: bf16, copy, sfseg, online, batch, channels, "
-                         "warm (or none)")
+    ap.add_argument("--extras", default="bf16,copy,sfseg,taylor,online,batch,warm",
+                    help="comma list of extra measurements to attach: bf16, copy, sfseg, taylor, online, batch, "
+                         "channels, warm (or none)")
     ap.add_argument("--warm-train", type=int, default=200, help="training clips for the warm-start extra")
     ap.add_argument("--warm-eval", type=int, default=24, help="evaluation clips for the warm-start extra")
     ap.add_argument("--warm-epochs", type=int, default=2, help="training epochs for the warm-start extra")
@@ -347,6 +347,9 @@ def main():
         log("full SFSeg operator (alpha = 1, p = 0.2)")
         out["sfseg"] = sfseg_leg(f_np, kern, iters, args.steps, args.warmup, args.kernel_reps, stream, dev)
     from paper_2212_08058_amd import experiments as X
+    if "taylor" in extras and args.dtype == "f32":
+        log("exact (Eq. 1) vs Taylor (Eq. 2) affinity study")
+        out["taylor"] = [X.taylor_study(shape=(10, 20, 20), log=log), X.taylor_study(shape=(16, 64, 112), log=log)]
     if "online" in extras and args.dtype == "f32":
         log("online sub-windows vs the full video")
         out["online"] = X.online_vs_full(f_np, kern, log=log)

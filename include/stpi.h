@@ -148,6 +148,20 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
  * masked by f != 0. STPI_NO_PRODUCT=1 in the environment selects the plain
  * form. */
 
+/* ---- exact exponential affinity (comparison operator) ----------------------
+ * Sec. 3, Eq. 1 before the Taylor approximation, for the exact-vs-approximate
+ * comparison of Sec. 4 ("Quantitative analysis"):
+ *   z_i = s_i sum_{j in N(i)} s_j exp(-alpha (f_i - f_j)^2) G_ij x_j,
+ * alpha >= 0. Not separable: a direct LDS-tiled gather of the whole box per
+ * output (meant for small volumes). float or double; r_s <= 8, r_t <= 4
+ * (STPI_EUNSUPPORTED otherwise). Arguments and results as the stpi_sfseg_*
+ * calls. */
+size_t stpi_exp_workspace_bytes(const stpi_problem *p);
+int stpi_exp_step(const stpi_problem *p, const void *s, const void *f, double alpha, const void *x, double x_scale,
+                  void *z, double *d_sums, void *ws, size_t ws_bytes, void *stream);
+int stpi_exp_iterate(const stpi_problem *p, const void *s, const void *f, double alpha, void *x, int init,
+                     int max_iters, double tol, void *ws, size_t ws_bytes, stpi_result *out, void *stream);
+
 /* ---- online / partial iteration over sub-windows ---------------------------
  * Sec. 4, "Online vs Offline processing": a long or streaming video is
  * processed in q-frame sub-windows; each window runs a few iterations,

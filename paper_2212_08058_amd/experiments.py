@@ -298,3 +298,79 @@ def online_vs_full(f_np, kern, settings=((16, 8, 5), (16, 8, 10), (32, 16, 10)),
                                    vs_converged=agree(out)))
         log(f"  online q={q} shift={shift} iters={it}: {t_online * 1e3:.2f} ms, {res['windows'][-1]['vs_converged']}")
     return res
+
+
+def noisy_study_fields(shape, seed, noise=0.5, p=0.2):
+    """The exact-vs-Taylor study's synthetic input: a soft blob mask with
+    heavy additive U[0, noise] noise, clipped to [0, 1], raised to p as the
+    unary map s, and the same mask with an independent noise draw as the
+    pairwise feature f."""
+    T, H, W = shape
+    mask, rng = synth.blob_mask(T, H, W, 3, seed)
+    S = np.clip(mask + rng.uniform(0.0, noise, mask.shape), 0.0, 1.0)
+    F = np.clip(mask + rng.uniform(0.0, noise, mask.shape), 0.0, 1.0)
+    return (S ** p).astype(np.float32), F.astype(np.float32), mask
+
+
+def taylor_study(shape=(10, 20, 20), seed=90, alpha=1.0, iters=30, start_deg=70.0, sigma_s=2.0, sigma_t=1.0,
+                 r_s=4, r_t=2, device="cuda", log=print):
+    """Sec. 4, "Quantitative analysis": the SFSeg iterates (Taylor affinity,
+    Eq. 2 / Eq. 7) against the exact eigenvector of the exponential affinity
+    (Eq. 1), from a start start_deg degrees away from it: angle (degrees) and
+    IoU of the masks x >= max(x) / 2 after every iteration, the angle between
+    the two converged eigenvectors, and the time per iteration of each
+    operator on the GPU."""
+    from . import sfseg as SF
+
+    kern = Kernel(sigma_s, sigma_t, r_s, r_t)
+    s_np, f_np, _ = noisy_study_fields(shape, seed)
+    s = torch.from_numpy(s_np).to(device)
+    f = torch.from_numpy(f_np).to(device)
+    v, rv = SF.exp_iterate(s, f, kern, alpha, tol=1e-8, max_iters=5000)
+    xt, rt = SF.sfseg_iterate(s, f, kern, alpha, tol=1e-8, max_iters=5000)
+    vd = v.double().reshape(-1)
+    vd = vd / vd.norm()
+    rng = np.random.default_rng(seed + 1)
+    w = torch.from_numpy(rng.uniform(0.0, 1.0, vd.numel())).to(device)
+    w = w - (w @ vd) * vd
+    w = w / w.norm()
+    th = math.radians(start_deg)
+    x = (math.cos(th) * vd + math.sin(th) * w).to(torch.float32).reshape(s.shape).contiguous()
+
+    def metrics(xv):
+        a = xv.double().reshape(-1)
+        a = a / a.norm()
+        ang = math.degrees(math.acos(min(1.0, abs(float(a @ vd)))))
+        ma, mb = a >= 0.5 * a.max(), vd >= 0.5 * vd.max()
+        iou = float((ma & mb).sum()) / max(1, int((ma | mb).sum()))
+        return ang, iou
+
+    curve = [metrics(x)]
+    for _ in range(iters):
+        x, _ = SF.sfseg_iterate(s, f, kern, alpha, iters=1, x0=x, x=x)
+        curve.append(metrics(x))
+    ang_conv, iou_conv = metrics(xt)
+    # time per iteration of the three operators (HIP events on the current stream)
+    import paper_2212_08058_amd as P
+    z = torch.empty_like(s)
+
+    def per_iter(fn, reps=20):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+    ms_exp = per_iter(lambda: SF.exp_step(s, f, x, kern, alpha, z=z))
+    ms_tay = per_iter(lambda: SF.sfseg_step(s, f, x, kern, alpha, z=z))
+    ms_plain = per_iter(lambda: P.step(s, x, kern, z=z))
+    log(f"  taylor study {shape}: start {curve[0][0]:.1f} deg -> {curve[-1][0]:.2f} deg after {iters} "
+        f"iterations (IoU {curve[-1][1]:.3f}); converged Taylor vs exact {ang_conv:.3f} deg, IoU {iou_conv:.3f}")
+    return dict(shape=list(shape), alpha=alpha, seed=seed, kernel=dict(sigma_s=sigma_s, sigma_t=sigma_t, r_s=r_s,
+                                                                        r_t=r_t),
+                exact_iters=rv["iters"], taylor_iters=rt["iters"],
+                angle_deg=[round(a, 4) for a, _ in curve], iou=[round(b, 4) for _, b in curve],
+                converged_angle_deg=ang_conv, converged_iou=iou_conv,
+                ms_per_iter=dict(exact_gather=ms_exp, taylor_three_fields=ms_tay, single_field=ms_plain))
