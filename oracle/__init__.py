@@ -33,6 +33,11 @@ What it computes, each function citing the passage it restates:
 * ``forward_train``/``adjoint``: reverse-mode derivative of the normalised
   iteration (gradient through the full spectral algorithm, Sec. 3.4).
 * ``bce``: binary cross-entropy on x / max(x).
+* ``combine_sigmoid``/``softbin``/``focal_dice``/``forward_train_pp``/
+  ``adjoint_pp``/``loss_and_grad_pp``: the paper's learning objective on the
+  single-field operator: the sigmoid-affine combination with bias (Eq. 9),
+  soft-binarised iterations after the first N_cont (Alg. 1, step 3) and the
+  Focal-Dice loss (Eq. 12), with the reverse mode through all of them.
 * ``net_forward``/``net_backward``: 4-layer 3x3x3 'same' conv net (C).
 * ``adamw_step``: AdamW with AMSGrad (Eq. 13).
 * ``fallback``: warm-start fallback rule.
@@ -488,6 +493,121 @@ def loss_and_grad(fc, w, gt, k: Kernel, iters: int):
     loss, g_x = bce(tape["xs"][-1], gt)
     g_f = adjoint(f, k, tape, g_x)
     return loss, combine_bwd(fc, w, g_f), tape
+
+
+# ---------------------------------------------------------------------------
+# The paper's learning objective (SFSeg++): sigmoid-affine channel
+# combination (Eq. 9), soft-binarised iterations after N_cont continuous ones
+# (Alg. 1, step 3), Focal-Dice loss (Eq. 12)
+# ---------------------------------------------------------------------------
+
+def sigmoid(a):
+    """The standard logistic 1 / (1 + exp(-a)) (Eq. 9 prints exp(+x): a sign slip)."""
+    a = _f64(a)
+    return 0.5 * (1.0 + np.tanh(0.5 * a))
+
+
+def combine_sigmoid(fc, w, b: float) -> np.ndarray:
+    """Eq. 9: f = sigmoid(sum_c w_c fc_c + b)."""
+    fc = _f64(fc)
+    w = np.asarray(w, dtype=np.float64)
+    a = np.tensordot(w, fc, axes=(0, 0)) + b
+    return sigmoid(a)
+
+
+def combine_sigmoid_bwd(fc, w, b: float, g_f):
+    """(dL/dw, dL/db) of Eq. 9 given dL/df: f' = f (1 - f)."""
+    f = combine_sigmoid(fc, w, b)
+    ga = _f64(g_f) * f * (1.0 - f)
+    return np.tensordot(_f64(fc), ga, axes=([1, 2, 3], [0, 1, 2])), float(np.sum(ga))
+
+
+def softbin(y, kappa: float, theta: float) -> np.ndarray:
+    """Soft-binarisation of a unit iterate (Alg. 1, step 3, with the sigmoid's
+    parameter made explicit): sigmoid(kappa (sqrt(N) y - theta))."""
+    y = _f64(y)
+    return sigmoid(kappa * (math.sqrt(y.size) * y - theta))
+
+
+def focal_dice(x, gt, gamma: float = 0.75, eps: float = 1.0):
+    """Eq. 12 per frame with the soft Dice 2 sum(x gt) / (sum x + sum gt),
+    smoothed by eps: J = sum_t (1 - D_t)^gamma, D_t = (2 P_t + eps) / (X_t + Y_t + eps).
+    Returns (J, dJ/dx)."""
+    x = _f64(x)
+    y = _f64(gt)
+    P = np.sum(x * y, axis=(1, 2))
+    X = np.sum(x, axis=(1, 2))
+    Y = np.sum(y, axis=(1, 2))
+    den = X + Y + eps
+    D = (2.0 * P + eps) / den
+    J = float(np.sum((1.0 - D) ** gamma))
+    dJ_dD = -gamma * (1.0 - D) ** (gamma - 1.0)
+    dD_dx = (2.0 * y * den[:, None, None] - (2.0 * P + eps)[:, None, None]) / (den ** 2)[:, None, None]
+    return J, dJ_dD[:, None, None] * dD_dx
+
+
+def forward_train_pp(f, k: Kernel, n_iter: int, n_cont: int, kappa: float, theta: float):
+    """Alg. 1's loop on the single-field operator: every iteration applies A and
+    normalises (y = A x / ||A x||); iterations after the first n_cont are then
+    soft-binarised (x = softbin(y)). Returns dict(xs=[inputs x_0..x_K], ys=[y_1..y_K],
+    ns=[||A x_k||], vs=[G (f x_k / ||x_k||)], soft=[bool per iteration]); xs[K] is the output."""
+    f = _f64(f)
+    N = f.size
+    x = np.full(f.shape, 1.0 / math.sqrt(N))
+    ones = np.ones_like(f)
+    xs, ys, ns, vs, soft = [x], [], [], [], []
+    for it in range(n_iter):
+        xu = x / np.linalg.norm(x)
+        v = apply(ones, f * xu, k)
+        z = f * v
+        n = math.sqrt(float(np.sum(z * z)))
+        y = z / n
+        sb = it >= n_cont
+        x = softbin(y, kappa, theta) if sb else y
+        xs.append(x)
+        ys.append(y)
+        ns.append(n)
+        vs.append(v)
+        soft.append(sb)
+    return dict(xs=xs, ys=ys, ns=ns, vs=vs, soft=soft)
+
+
+def adjoint_pp(f, k: Kernel, tape, kappa: float, g_out):
+    """dL/df through forward_train_pp in reverse: the soft-binarisation
+    (g_y = g_x sigmoid' kappa sqrt(N)), the normalisation of the step's output
+    and of its input, and the step itself (as ``adjoint``)."""
+    f = _f64(f)
+    N = f.size
+    ones = np.ones_like(f)
+    g = _f64(g_out).copy()  # gradient w.r.t. xs[K]
+    g_f = np.zeros_like(f)
+    for j in range(len(tape["ns"]) - 1, -1, -1):
+        x_out = tape["xs"][j + 1]
+        if tape["soft"][j]:
+            g = g * x_out * (1.0 - x_out) * kappa * math.sqrt(N)
+        y = tape["ys"][j]
+        g_z = (g - y * float(np.sum(y * g))) / tape["ns"][j]
+        x_in = tape["xs"][j]
+        nx = float(np.linalg.norm(x_in))
+        xu = x_in / nx
+        g_f += tape["vs"][j] * g_z
+        g_u = apply(ones, f * g_z, k)
+        g_f += xu * g_u
+        g_xu = f * g_u
+        g = (g_xu - xu * float(np.sum(xu * g_xu))) / nx
+    return g_f
+
+
+def loss_and_grad_pp(fc, w, b: float, gt, k: Kernel, n_iter: int, n_cont: int, kappa: float, theta: float,
+                     gamma: float = 0.75):
+    """End to end (SFSeg++ objective): f = combine_sigmoid(fc, w, b); Alg. 1's
+    loop with soft-binarisation; Focal-Dice on the output. Returns (J, dJ/dw, dJ/db, tape)."""
+    f = combine_sigmoid(fc, w, b)
+    tape = forward_train_pp(f, k, n_iter, n_cont, kappa, theta)
+    J, g_x = focal_dice(tape["xs"][-1], gt, gamma)
+    g_f = adjoint_pp(f, k, tape, kappa, g_x)
+    g_w, g_b = combine_sigmoid_bwd(fc, w, b, g_f)
+    return J, g_w, g_b, tape
 
 
 # ---------------------------------------------------------------------------

@@ -704,3 +704,64 @@ def test_exp_iterate_perron():
     x, info = oracle.exp_iterate(s, f, 2.0, k, tol=1e-13, cap=20000)
     assert info.converged and 1.0 - float(x.reshape(-1) @ v) < 1e-12
     assert abs(info.lambdas[-1] - lam) <= 1e-10 * lam
+
+
+# --- the SFSeg++ learning objective ---------------------------------------------
+
+def test_pp_pieces_match_torch_autograd():
+    """Eq. 9's combination, the soft-binarisation and the per-frame Focal-Dice
+    loss and their derivatives against torch (float64, CPU autograd)."""
+    import torch
+    rng = np.random.default_rng(91)
+    fc = rng.uniform(0.0, 1.0, (4, 3, 5, 6))
+    w = rng.standard_normal(4)
+    b = 0.3
+    g_f = rng.standard_normal((3, 5, 6))
+    tw = torch.tensor(w, requires_grad=True)
+    tb = torch.tensor(b, dtype=torch.float64, requires_grad=True)
+    tf = torch.sigmoid((tw[:, None, None, None] * torch.tensor(fc)).sum(0) + tb)
+    assert np.max(np.abs(tf.detach().numpy() - oracle.combine_sigmoid(fc, w, b))) <= 1e-15
+    (tf * torch.tensor(g_f)).sum().backward()
+    gw, gb = oracle.combine_sigmoid_bwd(fc, w, b, g_f)
+    assert np.max(np.abs(gw - tw.grad.numpy())) <= 1e-13 and abs(gb - float(tb.grad)) <= 1e-13
+    y = rng.standard_normal((3, 5, 6))
+    y /= np.linalg.norm(y)
+    ty = torch.tensor(y)
+    ref = torch.sigmoid(2.5 * (ty * math.sqrt(y.size) - 0.7))
+    assert np.max(np.abs(oracle.softbin(y, 2.5, 0.7) - ref.numpy())) <= 1e-15
+    x = rng.uniform(0.0, 1.0, (3, 5, 6))
+    gt = (rng.uniform(size=x.shape) > 0.5).astype(np.float64)
+    tx = torch.tensor(x, requires_grad=True)
+    tg = torch.tensor(gt)
+    inter = (tx * tg).sum(dim=(1, 2))
+    dice = (2 * inter + 1.0) / (tx.sum(dim=(1, 2)) + tg.sum(dim=(1, 2)) + 1.0)
+    J = ((1 - dice) ** 0.75).sum()
+    J.backward()
+    Jo, gxo = oracle.focal_dice(x, gt, 0.75, 1.0)
+    assert abs(Jo - float(J)) <= 1e-13 and np.max(np.abs(gxo - tx.grad.numpy())) <= 1e-13
+
+
+def test_pp_gradient_matches_finite_differences():
+    """The whole objective (combination, continuous and soft-binarised
+    iterations, Focal-Dice): dJ/dw and dJ/db against central differences."""
+    rng = np.random.default_rng(92)
+    k = Kernel(2.0, 1.0, 2, 1)
+    fc = rng.uniform(0.0, 1.0, (3, 3, 6, 7))
+    gt = (rng.uniform(size=fc.shape[1:]) > 0.6).astype(np.float64)
+    w = np.array([0.8, -0.4, 1.1])
+    b = -0.2
+    args = dict(k=k, n_iter=6, n_cont=3, kappa=2.0, theta=1.0)
+    J, gw, gb, _ = oracle.loss_and_grad_pp(fc, w, b, gt, **args)
+    h = 1e-6
+    for c in range(3):
+        wp, wm = w.copy(), w.copy()
+        wp[c] += h
+        wm[c] -= h
+        fd = (oracle.loss_and_grad_pp(fc, wp, b, gt, **args)[0] - oracle.loss_and_grad_pp(fc, wm, b, gt, **args)[0]) / (2 * h)
+        assert abs(fd - gw[c]) <= 1e-6 * max(1.0, abs(fd)), (c, fd, gw[c])
+    fd = (oracle.loss_and_grad_pp(fc, w, b + h, gt, **args)[0] - oracle.loss_and_grad_pp(fc, w, b - h, gt, **args)[0]) / (2 * h)
+    assert abs(fd - gb) <= 1e-6 * max(1.0, abs(fd))
+    # with no soft-binarised iteration the tape is the plain normalised iteration
+    tape = oracle.forward_train_pp(oracle.combine_sigmoid(fc, w, b), k, 5, 5, 2.0, 1.0)
+    x_plain, _ = oracle.iterate(oracle.combine_sigmoid(fc, w, b), k, iters=5)
+    assert np.max(np.abs(tape["xs"][-1] - x_plain)) <= 1e-14
