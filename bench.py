@@ -169,9 +169,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="let the autotuner pick the FP32 tile (default: the cost model's choice, which the "
                          "committed counter profile covers); the BF16 leg is always tuned")
-    ap.add_argument("--extras", default="bf16,copy,sfseg,taylor,online,batch,warm",
-                    help="comma list of extra measurements to attach: bf16, copy, sfseg, taylor, online, batch, "
-                         "channels, warm (or none)")
+    ap.add_argument("--extras", default="bf16,copy,sfseg,taylor,online,objective,batch,warm",
+                    help="comma list of extra measurements to attach: bf16, copy, sfseg, taylor, online, objective, "
+                         "batch, channels, warm (or none)")
     ap.add_argument("--warm-train", type=int, default=200, help="training clips for the warm-start extra")
     ap.add_argument("--warm-eval", type=int, default=24, help="evaluation clips for the warm-start extra")
     ap.add_argument("--warm-epochs", type=int, default=2, help="training epochs for the warm-start extra")
@@ -359,6 +359,9 @@ def main():
     if "channels" in extras:
         log("channel-combination training step")
         out["channels"] = X.channel_training_step(log=log)
+    if "objective" in extras:
+        log("the paper's objective: sigmoid-affine combination, soft-binarisation, Focal-Dice")
+        out["objective"] = X.pp_training_step(log=log)
     if "warm" in extras:
         log("warm start vs plain")
         r = X.warm_start_experiment(n_train=args.warm_train, n_eval=args.warm_eval, epochs=args.warm_epochs, log=log)

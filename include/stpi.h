@@ -148,6 +148,38 @@ int stpi_iterate(const stpi_problem *p, const void *f, void *x, int init, int ma
  * masked by f != 0. STPI_NO_PRODUCT=1 in the environment selects the plain
  * form. */
 
+/* ---- the paper's learning objective (SFSeg++), single-field operator --------
+ * Float or double device volumes; device scalars are doubles; ws is device
+ * scratch of the stated size (STPI_AUX_WS_BYTES always suffices for
+ * C <= STPI_MAX_CHANNELS and T <= 1300 frames).
+ * stpi_combine_sigmoid_fwd: Eq. 9, f = sigmoid(sum_c w_c fc_c + b), fc
+ *   [C][n], w [C], b one value (the standard logistic; the paper prints
+ *   exp(+x), a sign slip).
+ * stpi_combine_sigmoid_bwd: g_wb[0..C-1] = dL/dw, g_wb[C] = dL/db from dL/df
+ *   and the forward's f.
+ * stpi_softbin_fwd: Alg. 1, step 3 with the sigmoid's parameter explicit:
+ *   b = sigmoid(kappa (sqrt(n) z / ||z|| - theta)), *bnorm = ||b||.
+ * stpi_softbin_bwd: given g w.r.t. b / ||b|| (unit = 1, *d = <b / ||b||, g>)
+ *   or w.r.t. b (unit = 0), g_y = dL/dy for y = z_prev / ||z_prev|| (the
+ *   iterate b was made from) and *d_prev = <y, g_y>, the two inputs of the
+ *   adjoint step of the iteration before it.
+ * stpi_focal_dice: Eq. 12 per frame with the soft Dice (reading of its
+ *   intersection over union): J = sum_t (1 - D_t)^gamma, D_t = (2 sum x gt +
+ *   eps) / (sum x + sum gt + eps) over frame t; *loss = J, g_x = dJ/dx.
+ *   x [T][plane], gt [T][plane] bytes (0 / nonzero). */
+int stpi_combine_sigmoid_fwd(int C, int64_t n, int dtype, const void *fc, const double *w, const double *b, void *f,
+                             void *stream);
+int stpi_combine_sigmoid_bwd(int C, int64_t n, int dtype, const void *fc, const void *f, const void *g_f,
+                             double *g_wb, void *ws, size_t ws_bytes, void *stream);
+int stpi_softbin_fwd(int64_t n, int dtype, const void *z, const double *znorm, double kappa, double theta, void *b,
+                     double *bnorm, void *ws, size_t ws_bytes, void *stream);
+int stpi_softbin_bwd(int64_t n, int dtype, int unit, const void *g, const double *d, const void *b,
+                     const double *bnorm, const void *z_prev, const double *znorm_prev, double kappa, void *g_y,
+                     double *d_prev, void *ws, size_t ws_bytes, void *stream);
+size_t stpi_focal_dice_workspace_bytes(int T);
+int stpi_focal_dice(int T, int64_t plane, int dtype, const void *x, const uint8_t *gt, double gamma, double eps,
+                    double *loss, void *g_x, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- exact exponential affinity (comparison operator) ----------------------
  * Sec. 3, Eq. 1 before the Taylor approximation, for the exact-vs-approximate
  * comparison of Sec. 4 ("Quantitative analysis"):

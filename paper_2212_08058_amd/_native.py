@@ -73,6 +73,17 @@ PROTOTYPES = [
     ("stpi_exp_step", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     ("stpi_exp_iterate", ctypes.c_int, [_PP, _vp, _vp, ctypes.c_double, _vp, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_double, _vp, _sz, _RP, _vp]),
+    ("stpi_combine_sigmoid_fwd", ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                                 _vp]),
+    ("stpi_combine_sigmoid_bwd", ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int, _vp, _vp, _vp, _vp, _vp,
+                                                 _sz, _vp]),
+    ("stpi_softbin_fwd", ctypes.c_int, [ctypes.c_int64, ctypes.c_int, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                                        _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_softbin_bwd", ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
+    ("stpi_focal_dice_workspace_bytes", _sz, [ctypes.c_int]),
+    ("stpi_focal_dice", ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int, _vp, _vp, ctypes.c_double,
+                                       ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     ("stpi_variant_count", ctypes.c_int, [ctypes.c_int]),
     ("stpi_variant_info", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
     ("stpi_launch_shape", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),

@@ -374,3 +374,41 @@ def taylor_study(shape=(10, 20, 20), seed=90, alpha=1.0, iters=30, start_deg=70.
                 angle_deg=[round(a, 4) for a, _ in curve], iou=[round(b, 4) for _, b in curve],
                 converged_angle_deg=ang_conv, converged_iou=iou_conv,
                 ms_per_iter=dict(exact_gather=ms_exp, taylor_three_fields=ms_tay, single_field=ms_plain))
+
+
+def pp_training_step(n_iter=15, n_cont=10, kappa=2.0, theta=1.0, reps=5, device="cuda", log=print):
+    """The paper's objective on the channel workload (C = 8, 32x240x432, K as
+    the channel workload): sigmoid-affine combination (Eq. 9), n_iter
+    iterations of which the last n_iter - n_cont are soft-binarised (Alg. 1),
+    Focal-Dice (Eq. 12, gamma 0.75), backward and one AdamW step."""
+    c = synth.CONFIGS["channels"]
+    kern = Kernel(c["sigma_s"], c["sigma_t"], c["r_s"], c["r_t"])
+    fc, gt = synth.channel_stack(c["C"], c["T"], c["H"], c["W"], seed=c["seed"])
+    fcd = torch.from_numpy(fc).to(device)
+    gtd = torch.from_numpy(gt).to(device)
+    w = torch.zeros(c["C"], dtype=torch.float64, device=device, requires_grad=True)
+    b = torch.zeros((), dtype=torch.float64, device=device, requires_grad=True)
+    opt = learn.AdamW([w, b.reshape(1)], lr=0.05, weight_decay=0.0)
+
+    def step():
+        w.grad = None
+        b.grad = None
+        J = learn.focal_dice(learn.sfseg_pp(fcd, w, b, kern, n_iter, n_cont, kappa, theta), gtd)
+        J.backward()
+        opt.step([w.grad, b.grad.reshape(1)])
+        return J
+
+    step()
+    _sync()
+    ts, losses = [], []
+    for _ in range(reps):
+        _sync()
+        t0 = time.perf_counter()
+        J = step()
+        _sync()
+        ts.append(time.perf_counter() - t0)
+        losses.append(float(J))
+    N = c["T"] * c["H"] * c["W"]
+    t = float(np.median(ts))
+    return dict(seconds_per_step=t, losses=losses, n_iter=n_iter, n_cont=n_cont, kappa=kappa, theta=theta,
+                weights=w.detach().cpu().tolist(), bias=float(b), voxels=N, step_voxel_iters_per_s=2 * N * n_iter / t)

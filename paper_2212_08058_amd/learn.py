@@ -199,3 +199,146 @@ class AdamW:
             N.check(N.lib.stpi_adamw(p.numel(), _dt(p), p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(),
                                      vm.data_ptr(), self.t, self.lr, self.betas[0], self.betas[1], self.eps,
                                      self.wd, 1 if self.amsgrad else 0, _stream_ptr(None)))
+
+
+# ---------------------------------------------------------------------------
+# The paper's objective (SFSeg++) on the single-field operator: Eq. 9's
+# sigmoid-affine combination with bias, Alg. 1's loop with soft-binarised
+# iterations after the first n_cont, and the Focal-Dice loss of Eq. 12.
+# ---------------------------------------------------------------------------
+
+class SFSegPP(torch.autograd.Function):
+    """Output of Alg. 1's loop on f = sigmoid(sum_c w_c fc_c + b).
+
+    Every iteration applies A and normalises; iterations after the first
+    n_cont are then soft-binarised, b = sigmoid(kappa (sqrt(N) y - theta)),
+    and the next iteration takes b (normalised inside the step). The output is
+    the last soft mask (or the unit iterate if n_cont = n_iter). The whole
+    tape is kept (n_iter volumes); the backward runs the library's adjoint
+    step, soft-binarisation backward and combination backward."""
+
+    @staticmethod
+    def forward(ctx, fc, w, b, kern: Kernel, n_iter: int, n_cont: int, kappa: float, theta: float):
+        if fc.dim() != 4 or not fc.is_cuda or not fc.is_contiguous() or fc.dtype not in (torch.float32,
+                                                                                         torch.float64):
+            raise ValueError("fc must be a contiguous float32/float64 device tensor [C][T][H][W]")
+        if n_iter < 1 or not 0 <= n_cont <= n_iter:
+            raise ValueError("need n_iter >= 1 and 0 <= n_cont <= n_iter")
+        C, T, H, W = fc.shape
+        n = T * H * W
+        dev, dt = fc.device, fc.dtype
+        p = problem_for((T, H, W), kern, dt)
+        ws = torch.empty(workspace_bytes((T, H, W), kern, dt), dtype=torch.uint8, device=dev)
+        aux = _aux_ws(dev)
+        wd = w.detach().to(torch.float64).contiguous()
+        bd = b.detach().to(torch.float64).reshape(1).contiguous()
+        f = torch.empty((T, H, W), dtype=dt, device=dev)
+        N.check(N.lib.stpi_combine_sigmoid_fwd(C, n, _dt(fc), fc.data_ptr(), wd.data_ptr(), bd.data_ptr(),
+                                               f.data_ptr(), _stream_ptr(None)))
+        # tape: the input of every step (and its norm), its output, v, and the output's norm
+        norms_in = torch.empty(n_iter + 1, dtype=torch.float64, device=dev)
+        norms_out = torch.empty(n_iter, dtype=torch.float64, device=dev)
+        z = torch.empty((T, H, W), dtype=dt, device=dev)
+        N.check(N.lib.stpi_train_init(ctypes.byref(p), z.data_ptr(), norms_in.data_ptr(), _stream_ptr(None)))
+        ins, outs, vs = [z], [], []
+        for it in range(n_iter):
+            zo = torch.empty_like(z)
+            v = torch.empty_like(z)
+            N.check(N.lib.stpi_train_step(ctypes.byref(p), f.data_ptr(), ins[-1].data_ptr(),
+                                          norms_in[it:].data_ptr(), zo.data_ptr(), v.data_ptr(),
+                                          norms_out[it:].data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(None)))
+            outs.append(zo)
+            vs.append(v)
+            if it >= n_cont:
+                bb = torch.empty_like(z)
+                N.check(N.lib.stpi_softbin_fwd(n, _dt(fc), zo.data_ptr(), norms_out[it:].data_ptr(), float(kappa),
+                                               float(theta), bb.data_ptr(), norms_in[it + 1:].data_ptr(),
+                                               aux.data_ptr(), aux.numel(), _stream_ptr(None)))
+                ins.append(bb)
+            else:
+                ins.append(zo)
+                norms_in[it + 1:it + 2].copy_(norms_out[it:it + 1])
+        if n_cont < n_iter:
+            x = ins[-1]
+        else:
+            x = torch.empty_like(z)
+            N.check(N.lib.stpi_normalize(n, _dt(fc), outs[-1].data_ptr(), norms_out[n_iter - 1:].data_ptr(),
+                                         x.data_ptr(), _stream_ptr(None)))
+        ctx.save = dict(fc=fc, f=f, p=p, ws=ws, aux=aux, ins=ins, outs=outs, vs=vs, norms_in=norms_in,
+                        norms_out=norms_out, n_iter=n_iter, n_cont=n_cont, kappa=kappa, n=n, C=C,
+                        w_dtype=w.dtype, b_dtype=b.dtype)
+        return x.clone() if n_cont < n_iter else x
+
+    @staticmethod
+    def backward(ctx, g_x):
+        S = ctx.save
+        fc, f, p, ws, aux, n = S["fc"], S["f"], S["p"], S["ws"], S["aux"], S["n"]
+        ins, outs, vs, nin, nout = S["ins"], S["outs"], S["vs"], S["norms_in"], S["norms_out"]
+        K, n_cont, kappa = S["n_iter"], S["n_cont"], S["kappa"]
+        dt = _dt(f)
+        s = _stream_ptr(None)
+        g = g_x.to(f.dtype).contiguous().clone()
+        d = torch.empty(K + 1, dtype=torch.float64, device=f.device)
+        g_new = torch.empty_like(g)
+        # gradient w.r.t. the unit output y_K of the last step, and <y_K, g>
+        if K > n_cont:
+            N.check(N.lib.stpi_softbin_bwd(n, dt, 0, g.data_ptr(), None, ins[K].data_ptr(), None,
+                                           outs[K - 1].data_ptr(), nout[K - 1:].data_ptr(), float(kappa),
+                                           g_new.data_ptr(), d[K:].data_ptr(), aux.data_ptr(), aux.numel(), s))
+            g, g_new = g_new, g
+        else:
+            N.check(N.lib.stpi_dot(n, dt, outs[K - 1].data_ptr(), nout[K - 1:].data_ptr(), g.data_ptr(),
+                                   d[K:].data_ptr(), aux.data_ptr(), aux.numel(), s))
+        g_f = torch.zeros_like(f)
+        for k in range(K - 1, -1, -1):
+            # step k: input ins[k] (norm nin[k]), output outs[k] (norm nout[k]); g is w.r.t. outs[k] / nout[k]
+            N.check(N.lib.stpi_adjoint_step(ctypes.byref(p), f.data_ptr(), ins[k].data_ptr(), nin[k:].data_ptr(),
+                                            outs[k].data_ptr(), nout[k:].data_ptr(), vs[k].data_ptr(), g.data_ptr(),
+                                            d[k + 1:].data_ptr(), g_new.data_ptr(), g_f.data_ptr(),
+                                            d[k:].data_ptr(), ws.data_ptr(), ws.numel(), s))
+            g, g_new = g_new, g  # now w.r.t. ins[k] / nin[k]
+            if k >= 1 and k - 1 >= n_cont:
+                # ins[k] is the soft mask made from outs[k - 1]
+                N.check(N.lib.stpi_softbin_bwd(n, dt, 1, g.data_ptr(), d[k:].data_ptr(), ins[k].data_ptr(),
+                                               nin[k:].data_ptr(), outs[k - 1].data_ptr(), nout[k - 1:].data_ptr(),
+                                               float(kappa), g_new.data_ptr(), d[k:].data_ptr(), aux.data_ptr(),
+                                               aux.numel(), s))
+                g, g_new = g_new, g
+        g_wb = torch.empty(S["C"] + 1, dtype=torch.float64, device=f.device)
+        N.check(N.lib.stpi_combine_sigmoid_bwd(S["C"], n, dt, fc.data_ptr(), f.data_ptr(), g_f.data_ptr(),
+                                               g_wb.data_ptr(), aux.data_ptr(), aux.numel(), s))
+        return (None, g_wb[:S["C"]].to(S["w_dtype"]), g_wb[S["C"]].reshape(()).to(S["b_dtype"]), None, None, None,
+                None, None)
+
+
+def sfseg_pp(fc, w, b, kern: Kernel, n_iter: int = 10, n_cont: int = 5, kappa: float = 2.0,
+             theta: float = 1.0) -> torch.Tensor:
+    return SFSegPP.apply(fc, w, b, kern, n_iter, n_cont, kappa, theta)
+
+
+class FocalDiceLoss(torch.autograd.Function):
+    """Eq. 12 per frame, soft Dice, with the library's forward and gradient (stpi_focal_dice)."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, gt: torch.Tensor, gamma: float, eps: float):
+        xc = x.detach().contiguous()
+        gtb = gt.to(torch.uint8).contiguous()
+        T = xc.shape[0]
+        plane = xc.numel() // T
+        loss = torch.empty((), dtype=torch.float64, device=x.device)
+        g = torch.empty_like(xc)
+        wsz = int(N.lib.stpi_focal_dice_workspace_bytes(T))
+        ws = torch.empty(wsz, dtype=torch.uint8, device=x.device)
+        N.check(N.lib.stpi_focal_dice(T, plane, _dt(xc), xc.data_ptr(), gtb.data_ptr(), float(gamma), float(eps),
+                                      loss.data_ptr(), g.data_ptr(), ws.data_ptr(), wsz, _stream_ptr(None)))
+        ctx.save_for_backward(g)
+        return loss.to(x.dtype)
+
+    @staticmethod
+    def backward(ctx, g_out):
+        (g,) = ctx.saved_tensors
+        return g * g_out.to(g.dtype), None, None, None
+
+
+def focal_dice(x, gt, gamma: float = 0.75, eps: float = 1.0):
+    return FocalDiceLoss.apply(x, gt, gamma, eps)
