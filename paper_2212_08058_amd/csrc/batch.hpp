@@ -158,7 +158,7 @@ void batch_step_kernel(BatchArgs<ST> a) {
                 // staging power of two from the input's own maximum (as the single-clip step)
                 const float win = first ? fb : __uint_as_float(st_->wmax[cur]);
                 const int ein = bound_exponent((float)((double)win * st_->scale * pp.ginv_in), 100);
-                pp.scale = ldexpf(1.f, ein - 10);
+                pp.sg = ldexpf(1.f, ein - 10 - 2 * e);
                 const float umul = (float)(st_->scale * ldexp(1.0, 10 - ein) * pp.ginv_in);
                 stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(pp, a.taps, tapl, umul, a.rs, T, 0, T, H, W, tx0, ty0,
                                                        lds, d1, d2);

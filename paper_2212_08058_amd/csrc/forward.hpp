@@ -208,7 +208,7 @@ __device__ __forceinline__ float recip_or_zero(float fv) {
 // then stages one array, w (times a power of two: w scale 2^(10 + e) =
 // f x_unit 2^(10 - e)), instead of f and x, and its epilogue reads f and w at
 // the outputs as the plain form reads f and x. It stores
-// w_new = (f (2^-S acc)) f g; the iterate is w / (f g) (0 where f = 0). The
+// w_new = acc f^2 2^-S g; the iterate is w / (f g) (0 where f = 0). The
 // sums are taken on its float image x~ = fl(w rcp(f)) / g: p2 = sum x~_new^2
 // and p1 = sum x~_prev x~_new, products exact in double. The next step forms
 // x~_prev from the same stored w and f, so it is bitwise this step's x~_new:
@@ -233,8 +233,8 @@ struct FwdOpP {
     const ST *f;
     const ST *src;  // w of the current iterate (or f)
     ST *dst;        // w of the next
-    CT scale;       // 2^-S, undoes the staging prescale
     CT gout;        // g
+    CT sg;          // 2^-S g (2^-S undoes the staging prescale): w_new = acc f^2 sg
     double ginv_in, ginv_out;
     size_t plane;
     uint32_t pbytes;
@@ -288,8 +288,7 @@ struct FwdOpP {
 #pragma unroll
             for (int q = 0; q < QX; ++q) {
                 const CT fv = raw.f[i][q];
-                const CT z = scale * (fv * acc[i][q]);
-                w[q] = (z * fv) * gout;
+                w[q] = (acc[i][q] * (fv * fv)) * sg;
                 const CT r = recip_or_zero(fv);
                 const CT wr = IO::rounded(w[q]);
                 wmax = fmaxf(wmax, fabsf(wr));
@@ -382,7 +381,7 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
             // staging power of two from the input's own maximum
             const float win = first ? bound : __uint_as_float(a.state->wmax[cur]);
             const int ein = bound_exponent((float)((double)win * scale * pp.ginv_in), 100);
-            pp.scale = ldexpf(1.f, ein - 10);
+            pp.sg = ldexpf(1.f, ein - 10 - 2 * e);
             const float umul = (float)(scale * ldexp(1.0, 10 - ein) * pp.ginv_in);
             stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(pp, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0,
                                                    lds, d1, d2);
