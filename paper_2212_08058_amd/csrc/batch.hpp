@@ -11,6 +11,8 @@
 // chain does. No workgroup ever waits for another, so the grid always drains.
 #pragma once
 
+#include <type_traits>
+
 #include "chain.hpp"
 #include "forward.hpp"
 
@@ -60,10 +62,10 @@ struct BatchArgs {
 
 // Wavefronts per SIMD the register allocation must allow: matrix-core tiles
 // whose LDS fits twice in a CU's 160 KB are built for two resident workgroups.
-template <int TH, int TW, int NTHR, int PIPE, int PAD>
+template <int TH, int TW, int NTHR, int PIPE, int PAD, int UPLANES>
 constexpr int batch_min_waves() {
     if constexpr (PIPE == 3)
-        return 2 * (MfmaLds<PIPE, TH, TW, NTHR, PAD>::value * 4 + 1024) <= 160 * 1024 ? 2 * NTHR / 256 : 1;
+        return 2 * (MfmaLds<PIPE, TH, TW, NTHR, PAD, UPLANES>::value * 4 + 1024) <= 160 * 1024 ? 2 * NTHR / 256 : 1;
     else
         return 1;
 }
@@ -72,14 +74,18 @@ constexpr int batch_min_waves() {
 // the matrix-core tile loop in product form (see FwdOpP: every clip's
 // buffers hold f x g, with g from the clip's own bound on |f|).
 template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int PIPE>
-__global__ __launch_bounds__(NTHR, (batch_min_waves<TH, TW, NTHR, PIPE, RS <= 8 ? 8 : 16>()))
+__global__ __launch_bounds__(NTHR, (batch_min_waves<TH, TW, NTHR, PIPE, RS <= 8 ? 8 : 16,
+                                                     std::is_same<ST, bf16>::value ? 1 : 2>()))
 void batch_step_kernel(BatchArgs<ST> a) {
     using CT = typename Compute<ST>::type;
     using G = Geometry<RS, RT, TH, TW, NTHR, RY, QX>;
     using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
     constexpr int PAD = RS <= 8 ? 8 : 16;
     static_assert(PIPE != 3 || ((RS == 16 || RS == 8) && sizeof(CT) == 4), "matrix-core batch variants");
-    __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR, PAD>::value : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
+    // bfloat16 buffers stage values exact in half precision (one U plane)
+    constexpr bool EXACT = PIPE == 3 && std::is_same<ST, bf16>::value;
+    __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR, PAD, EXACT ? 1 : 2>::value
+                                : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
     __shared__ double red[NTHR / 64];
     __shared__ int s_tile;
     __shared__ float tapl[2 * 16 + 1];  // matrix-core variants: space taps centred at 16
@@ -157,11 +163,18 @@ void batch_step_kernel(BatchArgs<ST> a) {
                 pp.pbytes = op.pbytes;
                 // staging power of two from the input's own maximum (as the single-clip step)
                 const float win = first ? fb : __uint_as_float(st_->wmax[cur]);
-                const int ein = bound_exponent((float)((double)win * st_->scale * pp.ginv_in), 100);
-                pp.sg = ldexpf(1.f, ein - 10 - 2 * e);
-                const float umul = (float)(st_->scale * ldexp(1.0, 10 - ein) * pp.ginv_in);
-                stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(pp, a.taps, tapl, umul, a.rs, T, 0, T, H, W, tx0, ty0,
-                                                       lds, d1, d2);
+                float umul;
+                if constexpr (EXACT) {
+                    const int ein = bound_exponent((float)((double)win * pp.ginv_in), 100);
+                    pp.sg = (float)(st_->scale * ldexp(1.0, ein - 10 - 2 * e));
+                    umul = (float)ldexp(pp.ginv_in, 10 - ein);
+                } else {
+                    const int ein = bound_exponent((float)((double)win * st_->scale * pp.ginv_in), 100);
+                    pp.sg = ldexpf(1.f, ein - 10 - 2 * e);
+                    umul = (float)(st_->scale * ldexp(1.0, 10 - ein) * pp.ginv_in);
+                }
+                stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD, EXACT>(pp, a.taps, tapl, umul, a.rs, T, 0, T, H, W, tx0,
+                                                              ty0, lds, d1, d2);
                 d1 *= pp.ginv_in * pp.ginv_out;
                 d2 *= pp.ginv_out * pp.ginv_out;
                 const float m = block_max<NTHR>(pp.wmax, reinterpret_cast<float *>(red));

@@ -18,12 +18,14 @@ __device__ __forceinline__ float ld(const bf16 *p) {
     return __uint_as_float(((uint32_t)p->bits) << 16);
 }
 
-// Round-to-nearest-even float -> bfloat16 (NaN stays NaN).
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// Round-to-nearest-even float -> bfloat16 (NaN stays NaN): the hardware
+// conversion, one instruction per pair.
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2_bits(float a, float b) {
+    typedef float f2_t __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
+    const f2_t v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, b2_t));
 }
 
 __device__ __forceinline__ void st(float *p, float v) { *p = v; }

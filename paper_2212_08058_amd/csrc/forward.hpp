@@ -1,6 +1,8 @@
 // Forward power-iteration step and the small kernels of the iteration chain.
 #pragma once
 
+#include <type_traits>
+
 #include "stencil.hpp"
 #include "stencil_mfma.hpp"
 
@@ -284,27 +286,32 @@ struct FwdOpP {
         const auto rw = make_rsrc(dst + (size_t)t * plane, pbytes);
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            CT w[QX];
+            CT w[QX], wr[QX];  // w_new and what its store leaves in memory
 #pragma unroll
             for (int q = 0; q < QX; ++q) {
                 const CT fv = raw.f[i][q];
                 w[q] = (acc[i][q] * (fv * fv)) * sg;
-                const CT r = recip_or_zero(fv);
-                const CT wr = IO::rounded(w[q]);
-                wmax = fmaxf(wmax, fabsf(wr));
-                const double xn = (double)(wr * r);
+            }
+            bool whole = false;
+            if constexpr (QX == 4) {
+                if (off[i][3] != OOB) {
+                    IO::store4_rounded(rw, off[i][0], w, wr);
+                    whole = true;
+                }
+            }
+            if (!whole) {
+#pragma unroll
+                for (int q = 0; q < QX; ++q) wr[q] = IO::store_rounded(rw, off[i][q], w[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                const CT r = recip_or_zero(raw.f[i][q]);
+                wmax = fmaxf(wmax, fabsf(wr[q]));
+                const double xn = (double)(wr[q] * r);
                 const double xp = (double)(raw.u[i][q] * r);
                 d2 = fma(xn, xn, d2);
                 d1 = fma(xp, xn, d1);
             }
-            if constexpr (QX == 4) {
-                if (off[i][3] != OOB) {
-                    IO::store4(rw, off[i][0], w);
-                    continue;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < QX; ++q) IO::store(rw, off[i][q], w[q]);
         }
     }
 };
@@ -324,7 +331,10 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
                   "matrix-core variants: RS 8 or 16 (the slab margin), float arithmetic");
     static_assert(!PF || PIPE == 3, "the product form runs on the matrix-core tile loop");
     constexpr int PAD = RS <= 8 ? 8 : 16;
-    __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR, PAD>::value : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
+    // bfloat16 product-form chains stage values exact in half precision
+    constexpr bool EXACT = PF && std::is_same<ST, bf16>::value;
+    __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR, PAD, EXACT ? 1 : 2>::value
+                                : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
     __shared__ double red[NTHR / 64];
 
     const int nbx = (a.W + TW - 1) / TW, nby = (a.H + TH - 1) / TH;
@@ -380,11 +390,20 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
             pp.pbytes = op.pbytes;
             // staging power of two from the input's own maximum
             const float win = first ? bound : __uint_as_float(a.state->wmax[cur]);
-            const int ein = bound_exponent((float)((double)win * scale * pp.ginv_in), 100);
-            pp.sg = ldexpf(1.f, ein - 10 - 2 * e);
-            const float umul = (float)(scale * ldexp(1.0, 10 - ein) * pp.ginv_in);
-            stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(pp, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0,
-                                                   lds, d1, d2);
+            float umul;
+            if constexpr (EXACT) {
+                // stage w ginv_in 2^(10 - ein) (a power of two times a bfloat16
+                // value: exact in half precision); the scale moves to the epilogue
+                const int ein = bound_exponent((float)((double)win * pp.ginv_in), 100);
+                pp.sg = (float)(scale * ldexp(1.0, ein - 10 - 2 * e));
+                umul = (float)ldexp(pp.ginv_in, 10 - ein);
+            } else {
+                const int ein = bound_exponent((float)((double)win * scale * pp.ginv_in), 100);
+                pp.sg = ldexpf(1.f, ein - 10 - 2 * e);
+                umul = (float)(scale * ldexp(1.0, 10 - ein) * pp.ginv_in);
+            }
+            stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD, EXACT>(pp, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W,
+                                                          x0, y0, lds, d1, d2);
             d1 *= pp.ginv_in * pp.ginv_out;
             d2 *= pp.ginv_out * pp.ginv_out;
             const float m = block_max<NTHR>(pp.wmax, reinterpret_cast<float *>(red));

@@ -71,6 +71,17 @@ struct BufIO<float> {
         for (int e = 0; e < 4; ++e) t[e] = __float_as_uint(v[e]);
         __builtin_amdgcn_raw_buffer_store_b128(t, r, boff, 0, 0);
     }
+    // store, and return what the store leaves in memory
+    __device__ static __forceinline__ float store_rounded(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
+        store(r, boff, v);
+        return v;
+    }
+    __device__ static __forceinline__ void store4_rounded(__amdgpu_buffer_rsrc_t r, uint32_t boff,
+                                                          const float (&v)[4], float (&vr)[4]) {
+        store4(r, boff, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vr[e] = v[e];
+    }
 };
 
 template <>
@@ -95,9 +106,27 @@ struct BufIO<bf16> {
     __device__ static __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, uint32_t boff, const float (&v)[4]) {
         using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
         V2 t;
-        t[0] = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
-        t[1] = (uint32_t)f32_to_bf16_bits(v[2]) | ((uint32_t)f32_to_bf16_bits(v[3]) << 16);
+        t[0] = f32x2_to_bf16x2_bits(v[0], v[1]);
+        t[1] = f32x2_to_bf16x2_bits(v[2], v[3]);
         __builtin_amdgcn_raw_buffer_store_b64(t, r, boff, 0, 0);
+    }
+    // store, and return what the store leaves in memory (one rounding)
+    __device__ static __forceinline__ float store_rounded(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
+        const uint16_t b = f32_to_bf16_bits(v);
+        __builtin_amdgcn_raw_buffer_store_b16(b, r, boff, 0, 0);
+        return __uint_as_float((uint32_t)b << 16);
+    }
+    __device__ static __forceinline__ void store4_rounded(__amdgpu_buffer_rsrc_t r, uint32_t boff,
+                                                          const float (&v)[4], float (&vr)[4]) {
+        using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        V2 t;
+        t[0] = f32x2_to_bf16x2_bits(v[0], v[1]);
+        t[1] = f32x2_to_bf16x2_bits(v[2], v[3]);
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, boff, 0, 0);
+        vr[0] = __uint_as_float(t[0] << 16);
+        vr[1] = __uint_as_float(t[0] & 0xffff0000u);
+        vr[2] = __uint_as_float(t[1] << 16);
+        vr[3] = __uint_as_float(t[1] & 0xffff0000u);
     }
 };
 
@@ -119,6 +148,16 @@ struct BufIO<double> {
     __device__ static __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, uint32_t boff, const double (&v)[4]) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) store(r, boff + 8 * e, v[e]);
+    }
+    __device__ static __forceinline__ double store_rounded(__amdgpu_buffer_rsrc_t r, uint32_t boff, double v) {
+        store(r, boff, v);
+        return v;
+    }
+    __device__ static __forceinline__ void store4_rounded(__amdgpu_buffer_rsrc_t r, uint32_t boff,
+                                                          const double (&v)[4], double (&vr)[4]) {
+        store4(r, boff, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vr[e] = v[e];
     }
 };
 

@@ -65,7 +65,10 @@ constexpr int mfma_pitch(int n) {
 // PAD (8 or 16) is the slab margin, at least the space radius. An output
 // block of 16 rows (columns) reads 16 + 2 PAD slab rows (columns), that is KB
 // K blocks of 32 (the last 16 of them zero weight when PAD = 16).
-template <int TH, int TW, int NTHR, int PAD>
+// UPLANES: half-precision planes per staged U buffer: 2 (hi and lo) in
+// general, 1 when the staged values are exact in half precision (see
+// stencil_tile_mfma's EXACT).
+template <int TH, int TW, int NTHR, int PAD, int UPLANES = 2>
 struct MfmaGeometry {
     static constexpr int KB = (16 + 2 * PAD + 31) / 32;
     static constexpr int MB = TH / 16, NB = TW / 16;  // output blocks down / across
@@ -76,7 +79,7 @@ struct MfmaGeometry {
     static constexpr int YP = mfma_pitch(YW);
     static constexpr int UPL = SC * UP;               // halves per U plane
     static constexpr int YPL = TH * YP;               // halves per Y plane
-    static constexpr int UBUF = 2 * UPL;              // hi and lo planes
+    static constexpr int UBUF = UPLANES * UPL;        // hi (and lo) planes
     static constexpr int YBUF = 2 * YPL;
     static constexpr int LDS_HALVES = 2 * UBUF + 2 * YBUF;  // double-buffered
     static constexpr int LDS_FLOATS = LDS_HALVES / 2;
@@ -98,13 +101,13 @@ struct MfmaGeometry {
 };
 
 // LDS floats of a tile loop kind (instantiates the geometry only for PIPE 3).
-template <int PIPE, int TH, int TW, int NTHR, int PAD>
+template <int PIPE, int TH, int TW, int NTHR, int PAD, int UPLANES = 2>
 struct MfmaLds {
     static constexpr int value = 1;
 };
-template <int TH, int TW, int NTHR, int PAD>
-struct MfmaLds<3, TH, TW, NTHR, PAD> {
-    static constexpr int value = MfmaGeometry<TH, TW, NTHR, PAD>::LDS_FLOATS;
+template <int TH, int TW, int NTHR, int PAD, int UPLANES>
+struct MfmaLds<3, TH, TW, NTHR, PAD, UPLANES> {
+    static constexpr int value = MfmaGeometry<TH, TW, NTHR, PAD, UPLANES>::LDS_FLOATS;
 };
 
 // Staging item m of thread tid. When the items do not fill the last round,
@@ -137,8 +140,10 @@ __device__ __forceinline__ void split4(const float4_t &v, half4_t &h, half4_t &l
     for (int j = 0; j < 4; ++j) l[j] = (_Float16)__builtin_fmaf(-(float)h[j], one, v[j]);
 }
 
-// y-pass products of one 16 x 16 block of Y (one dependency chain).
-template <class G>
+// y-pass products of one 16 x 16 block of Y (one dependency chain). EXACT:
+// the staged values are exact in half precision (no lo plane, two products
+// per K block).
+template <class G, bool EXACT>
 __device__ __forceinline__ float4_t mfma_yblock_mma(const _Float16 *U, int b, int lane, const half8_t (&thi)[G::KB],
                                                     const half8_t (&tlo)[G::KB]) {
     const int rb = b / G::NYC, cb = b % G::NYC;
@@ -148,10 +153,12 @@ __device__ __forceinline__ float4_t mfma_yblock_mma(const _Float16 *U, int b, in
 #pragma unroll
     for (int kb = 0; kb < G::KB; ++kb) {
         const half8_t ah = *reinterpret_cast<const half8_t *>(p + 32 * kb);
-        const half8_t al = *reinterpret_cast<const half8_t *>(p + G::UPL + 32 * kb);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, thi[kb], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, tlo[kb], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], acc, 0, 0, 0);
+        if constexpr (!EXACT) {
+            const half8_t al = *reinterpret_cast<const half8_t *>(p + G::UPL + 32 * kb);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], acc, 0, 0, 0);
+        }
     }
     return acc;
 }
@@ -192,11 +199,15 @@ __device__ __forceinline__ float4_t mfma_xblock_mma(const _Float16 *Y, int b, in
 // f * x at staging and op.scale must be 2^-S. rs is the problem's space
 // radius (slab rows and columns beyond it are not read). lds holds
 // MfmaGeometry::LDS_FLOATS floats; tapl holds the 33 space taps centred at 16.
-template <class CT, int RT, int TH, int TW, int NTHR, int PAD, class Op>
+// EXACT: every staged value input * umul is exact in half precision (umul a
+// power of two, inputs with at most 11 significant bits in range, as
+// bfloat16 storage gives): one U plane, no split, two products per y-pass K
+// block.
+template <class CT, int RT, int TH, int TW, int NTHR, int PAD, bool EXACT = false, class Op>
 __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &tp, const float *tapl, float umul,
                                                   int rs, int T, int t0, int t1, int H, int W, int x0, int y0,
                                                   float *lds, double &d1, double &d2) {
-    using G = MfmaGeometry<TH, TW, NTHR, PAD>;
+    using G = MfmaGeometry<TH, TW, NTHR, PAD, EXACT ? 1 : 2>;
     constexpr int NPF = G::NPF, IPS = G::IPS, NTS = 2 * RT + 1, XPW = G::XPW;
     constexpr uint32_t ESZ = Op::ESZ;
     const int tid = threadIdx.x;
@@ -222,9 +233,9 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
 
     // zero the U^T rows [SR, UK) and the Y columns [SC, YW) of both buffers
     // (none when PAD = 8)
-    for (int i = tid; i < 2 * 2 * G::SC * (G::UK - G::SR); i += NTHR) {
+    for (int i = tid; i < 2 * (EXACT ? 1 : 2) * G::SC * (G::UK - G::SR); i += NTHR) {
         const int k = i % (G::UK - G::SR), rest = i / (G::UK - G::SR);
-        const int c = rest % G::SC, plane = rest / G::SC;  // plane: buffer * 2 + hi/lo
+        const int c = rest % G::SC, plane = rest / G::SC;  // plane: buffer * planes + hi/lo
         U0[plane * G::UPL + c * G::UP + G::SR + k] = (_Float16)0.f;
     }
     for (int i = tid; i < 2 * 2 * TH * (G::YW - G::SC); i += NTHR) {
@@ -304,7 +315,7 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
 #pragma unroll
             for (int m = 0; m < G::YPW; ++m) {
                 const int b = wid + m * G::NWAVE;
-                if (G::NYB % G::NWAVE == 0 || b < G::NYB) ya[m] = mfma_yblock_mma<G>(U, b, lane, thi, tlo);
+                if (G::NYB % G::NWAVE == 0 || b < G::NYB) ya[m] = mfma_yblock_mma<G, EXACT>(U, b, lane, thi, tlo);
             }
         }
         if (p < nin) {
@@ -314,17 +325,24 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
                 const int it = stage_item<G, NTHR>(tid, m);
                 if (G::NITEM % NTHR == 0 || m < IPS - 1 || it < G::NITEM) {
                     const int c = it % G::SC, g = it / G::SC;
-                    half8_t h, l;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        _Float16 a, b;
-                        split_half(op.template input<NPF>(pf, 8 * m + j) * umul, a, b);
-                        h[j] = a;
-                        l[j] = b;
-                    }
                     _Float16 *q = U + c * G::UP + 8 * g;
-                    *reinterpret_cast<half8_t *>(q) = h;
-                    *reinterpret_cast<half8_t *>(q + G::UPL) = l;
+                    if constexpr (EXACT) {
+                        half8_t h;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) h[j] = (_Float16)(op.template input<NPF>(pf, 8 * m + j) * umul);
+                        *reinterpret_cast<half8_t *>(q) = h;
+                    } else {
+                        half8_t h, l;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            _Float16 a, b;
+                            split_half(op.template input<NPF>(pf, 8 * m + j) * umul, a, b);
+                            h[j] = a;
+                            l[j] = b;
+                        }
+                        *reinterpret_cast<half8_t *>(q) = h;
+                        *reinterpret_cast<half8_t *>(q + G::UPL) = l;
+                    }
                 }
             }
         }
