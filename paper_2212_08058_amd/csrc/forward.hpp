@@ -513,11 +513,14 @@ constexpr bool fwd_can_fuse() {
     return NTHR >= FINAL_THREADS;
 }
 
+// Matrix-core variants report the occupancy of their product-form kernel,
+// the one an iteration chain runs (with bfloat16 storage it stages a single
+// half plane and may fit more workgroups per CU than the plain step).
 template <class ST, int RS, int RT, int TH, int TW, int NTHR, int RY, int QX, int OCC, int PIPE>
 int fwd_blocks_per_cu() {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, false>, NTHR, 0) != hipSuccess)
+            &n, fwd_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX, OCC, PIPE, PIPE == 3>, NTHR, 0) != hipSuccess)
         n = 1;
     return n > 0 ? n : 1;
 }
