@@ -161,6 +161,7 @@ void batch_step_kernel(BatchArgs<ST> a) {
                 pp.ginv_in = first ? 1.0 : pp.ginv_out;
                 pp.plane = op.plane;
                 pp.pbytes = op.pbytes;
+                pp.cut = tx0 + TW > W;
                 // staging power of two from the input's own maximum (as the single-clip step)
                 const float win = first ? fb : __uint_as_float(st_->wmax[cur]);
                 float umul;

@@ -74,15 +74,19 @@ struct FwdOp {
     CT scale;
     size_t plane;     // elements per frame
     uint32_t pbytes;  // bytes per frame
+    bool cut = false;  // epilogue operands came from 4-wide loads that groups cut by the right edge extend past it
 
     template <int NPF>
     struct Raw {
         CT f[NPF], x[NPF];
     };
+    // live = false issues the same loads on an empty range (they return 0 and
+    // touch no memory): the matrix-core tile loop fetches every phase, so the
+    // compiler's memory-counter waits count a fixed number of younger loads
     template <int NPF>
-    __device__ __forceinline__ void fetch(int t, const uint32_t (&off)[NPF], Raw<NPF> &raw) const {
-        const auto rf = make_rsrc(f + (size_t)t * plane, pbytes);
-        const auto rx = make_rsrc(src + (size_t)t * plane, pbytes);
+    __device__ __forceinline__ void fetch(int t, const uint32_t (&off)[NPF], Raw<NPF> &raw, bool live = true) const {
+        const auto rf = make_rsrc(f + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
+        const auto rx = make_rsrc(src + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
 #pragma unroll
         for (int k = 0; k < NPF; ++k) {
             raw.f[k] = IO::load(rf, off[k]);
@@ -100,10 +104,24 @@ struct FwdOp {
     // Epilogue operands. A group of QX = 4 outputs that lies wholly inside its
     // row moves with one 4-wide access; groups cut by the right edge of the
     // frame fall back to single elements with per-element out-of-range offsets.
-    template <int IPT, int QX>
-    __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw) const {
-        const auto rf = make_rsrc(f + (size_t)t * plane, pbytes);
-        const auto rx = make_rsrc(src + (size_t)t * plane, pbytes);
+    // WIDE (QX = 4): every group moves with one 4-wide access at its first
+    // offset, so the count of memory instructions is fixed; a group cut by the
+    // right edge then reads into the next row, and the epilogue must be told
+    // (cut) to take f there as zero.
+    template <int IPT, int QX, bool WIDE = false>
+    __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw,
+                                              bool live = true) const {
+        const auto rf = make_rsrc(f + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
+        const auto rx = make_rsrc(src + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
+        if constexpr (WIDE) {
+            static_assert(QX == 4, "4-wide groups");
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                IO::load4(rf, off[i][0], raw.f[i]);
+                IO::load4(rx, off[i][0], raw.x[i]);
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             if constexpr (QX == 4) {
@@ -181,7 +199,8 @@ struct FwdOp {
             CT z[QX];
 #pragma unroll
             for (int q = 0; q < QX; ++q) {
-                z[q] = scale * (raw.f[i][q] * acc[i][q]);
+                const CT fv = cut && off[i][q] == OOB ? CT(0) : raw.f[i][q];
+                z[q] = scale * (fv * acc[i][q]);
                 const double zs = (double)IO::rounded(z[q]);
                 d2 = fma(zs, zs, d2);
                 d1 = fma(zs, (double)raw.x[i][q], d1);
@@ -241,14 +260,15 @@ struct FwdOpP {
     size_t plane;
     uint32_t pbytes;
     mutable float wmax = 0.f;  // max |w_new| stored by this thread (the next step's staging bound)
+    bool cut = false;          // as FwdOp::cut
 
     template <int NPF>
     struct Raw {
         CT u[NPF];
     };
     template <int NPF>
-    __device__ __forceinline__ void fetch(int t, const uint32_t (&off)[NPF], Raw<NPF> &raw) const {
-        const auto ru = make_rsrc(src + (size_t)t * plane, pbytes);
+    __device__ __forceinline__ void fetch(int t, const uint32_t (&off)[NPF], Raw<NPF> &raw, bool live = true) const {
+        const auto ru = make_rsrc(src + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
 #pragma unroll
         for (int k = 0; k < NPF; ++k) raw.u[k] = IO::load(ru, off[k]);
     }
@@ -260,10 +280,20 @@ struct FwdOpP {
     struct OutRaw {
         CT f[IPT][QX], u[IPT][QX];
     };
-    template <int IPT, int QX>
-    __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw) const {
-        const auto rf = make_rsrc(f + (size_t)t * plane, pbytes);
-        const auto ru = make_rsrc(src + (size_t)t * plane, pbytes);
+    template <int IPT, int QX, bool WIDE = false>  // WIDE as FwdOp::fetch_out
+    __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw,
+                                              bool live = true) const {
+        const auto rf = make_rsrc(f + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
+        const auto ru = make_rsrc(src + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
+        if constexpr (WIDE) {
+            static_assert(QX == 4, "4-wide groups");
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                IO::load4(rf, off[i][0], raw.f[i]);
+                IO::load4(ru, off[i][0], raw.u[i]);
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             if constexpr (QX == 4) {
@@ -286,11 +316,11 @@ struct FwdOpP {
         const auto rw = make_rsrc(dst + (size_t)t * plane, pbytes);
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            CT w[QX], wr[QX];  // w_new and what its store leaves in memory
+            CT w[QX], wr[QX], fv[QX];  // w_new, what its store leaves in memory, f
 #pragma unroll
             for (int q = 0; q < QX; ++q) {
-                const CT fv = raw.f[i][q];
-                w[q] = (acc[i][q] * (fv * fv)) * sg;
+                fv[q] = cut && off[i][q] == OOB ? CT(0) : raw.f[i][q];
+                w[q] = (acc[i][q] * (fv[q] * fv[q])) * sg;
             }
             bool whole = false;
             if constexpr (QX == 4) {
@@ -305,7 +335,7 @@ struct FwdOpP {
             }
 #pragma unroll
             for (int q = 0; q < QX; ++q) {
-                const CT r = recip_or_zero(raw.f[i][q]);
+                const CT r = recip_or_zero(fv[q]);
                 wmax = fmaxf(wmax, fabsf(wr[q]));
                 const double xn = (double)(wr[q] * r);
                 const double xp = (double)(raw.u[i][q] * r);
@@ -338,10 +368,13 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     __shared__ double red[NTHR / 64];
 
     const int nbx = (a.W + TW - 1) / TW, nby = (a.H + TH - 1) / TH;
-    // consecutive units (the segments of one tile, then the next tile) share an XCD
-    const int unit = xcd_tile(blockIdx.x, nbx * nby * a.nseg);
+    // consecutive units share an XCD: neighbouring tiles of one frame segment
+    // (they stage overlapping slabs of the same frames at about the same time,
+    // so halo lines fetched by one are L2 hits for the other)
+    const int ntiles = nbx * nby;
+    const int unit = xcd_tile(blockIdx.x, ntiles * a.nseg);
     if (unit < 0) return;
-    const int tile = unit / a.nseg, seg = unit % a.nseg;
+    const int tile = unit % ntiles, seg = unit / ntiles;
     const int t0 = (int)((int64_t)seg * a.T / a.nseg), t1 = (int)((int64_t)(seg + 1) * a.T / a.nseg);
     FwdOp<ST> op;
     op.f = a.f;
@@ -388,6 +421,7 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
             pp.ginv_in = first ? 1.0 : pp.ginv_out;
             pp.plane = op.plane;
             pp.pbytes = op.pbytes;
+            pp.cut = x0 + TW > a.W;
             // staging power of two from the input's own maximum
             const float win = first ? bound : __uint_as_float(a.state->wmax[cur]);
             float umul;
@@ -413,6 +447,7 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
             const int e = bound_exponent(bound, 100);
             const float umul = (float)(scale * ldexp(1.0, 10 - e));
             op.scale = ldexpf(1.f, e - 10);
+            op.cut = x0 + TW > a.W;
             stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(op, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0,
                                                    lds, d1, d2);
         }

@@ -260,7 +260,9 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
             poff[8 * m + j] = ok ? (uint32_t)(gy * W + gx) * ESZ : OOB;
         }
     }
-    // output offsets: x-pass block i of this wavefront, row li, columns 4 lg .. 4 lg + 3
+    // output offsets: x-pass block i of this wavefront, row li, columns 4 lg .. 4 lg + 3.
+    // The epilogue's operands move in 4-wide loads at the first offset of each
+    // group: op.cut must be set where the tile reaches past the right edge.
     uint32_t ooff[XPW][4];
 #pragma unroll
     for (int i = 0; i < XPW; ++i) {
@@ -298,8 +300,11 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
         const bool emit = tx >= 0 && tout >= t0;
         const bool xlive = tx >= 0 && tx < nin;
         const bool ylive = p >= 1 && p - 1 < nin;
-        // the epilogue's loads go first: they have the whole phase to arrive
-        if (emit) op.template fetch_out<XPW, 4>(tout, ooff, oraw);
+        // the epilogue's loads go first: they have the whole phase to arrive.
+        // Both load groups are issued in every phase (on an empty range when
+        // not needed) so that the memory-counter waits before each use allow
+        // for the younger group instead of draining it.
+        op.template fetch_out<XPW, 4, true>(tout, ooff, oraw, emit);
         // matrix-core products of both passes (frames p - 2 and p - 1; the
         // buffers they read were written before the last barrier), issued
         // before the vector work of the phase so that they run beside it
@@ -346,7 +351,7 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
                 }
             }
         }
-        if (p + 1 < nin) op.template fetch<NPF>(ts + p + 1, poff, pf);
+        op.template fetch<NPF>(ts + p + 1, poff, pf, p + 1 < nin);
         if (tx >= 0) {
             CT v[XPW][4];
 #pragma unroll
