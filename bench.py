@@ -279,9 +279,11 @@ def main():
         # kernel below it is recorded beside it (rocprofv3 SQ counters)
         out["roofline"] = {"bound": "hbm", **hbm, "traffic": None, "kernel": "fwd_step_kernel", "kernel_ms": kern_ms,
                            "alu": alu,
-                           "limiter": "instruction issue and latency, not HBM: per SIMD the vector ALU is busy ~41% "
-                                      "of the kernel time and the matrix cores ~9% (two wavefronts per SIMD, one "
-                                      "LDS-bound workgroup per CU, a barrier per frame phase)"}
+                           "limiter": "instruction issue and latency, not HBM: per SIMD the vector ALU is busy ~48% "
+                                      "of the kernel time; a wavefront spends ~34% of its life in memory or barrier "
+                                      "waits and ~29% waiting to issue (two wavefronts per SIMD, one LDS-bound "
+                                      "workgroup per CU, a barrier per frame phase; vector-memory latency ~1200 "
+                                      "cycles, L2 hit rate ~55%)"}
     else:
         out["roofline"] = {"bound": "alu", **alu, "traffic": None, "kernel": "fwd_step_kernel", "kernel_ms": kern_ms,
                            "hbm": hbm}
