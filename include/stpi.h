@@ -434,6 +434,19 @@ int stpi_downsample(int T, int H, int W, int sy, int st, int dtype, const void *
  * out must not alias in or mul. Asynchronous; errors as stpi_downsample. */
 int stpi_upsample(int T, int H, int W, int sy, int st, int mode, int dtype, const void *in, const void *mul, void *out,
                   void *stream);
+/* The coarse problem of the two-level start (host only, no device work):
+ * coarse size as above, the kernel's sigmas divided by the factors
+ * (sigma_s / sy, sigma_t / st) and its radii rounded up (ceil(r_s / sy),
+ * ceil(r_t / st)), the dtype kept. STPI_EINVAL for NULL pointers, sizes or
+ * factors < 1, sigmas <= 0 or negative radii. */
+int stpi_coarse_problem(const stpi_problem *fine, int sy, int st, stpi_problem *coarse);
+/* y[i] = x[i] * s, times *s_dev as well when s_dev (a device double) is not
+ * NULL; formed in double and rounded to the storage type once. n elements of
+ * storage type dtype, device buffers; y may be x. Used for the start's O(1)
+ * scaling for the net and for a loss gradient times the incoming gradient.
+ * Asynchronous on `stream`; STPI_EINVAL for n < 0, an unknown dtype or NULL
+ * buffers (n > 0). */
+int stpi_scale(int64_t n, int dtype, const void *x, double s, const double *s_dev, void *y, void *stream);
 
 /* ---- learned warm start ------------------------------------------------------
  * A small 3D convolutional network predicts the start vector of the iteration

@@ -89,6 +89,9 @@ PROTOTYPES = [
     ("stpi_launch_shape", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]),
     ("stpi_downsample", ctypes.c_int, [ctypes.c_int] * 6 + [_vp, _vp, _vp]),
     ("stpi_upsample", ctypes.c_int, [ctypes.c_int] * 7 + [_vp, _vp, _vp, _vp]),
+    ("stpi_coarse_problem", ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(Problem)]),
+    ("stpi_scale", ctypes.c_int, [ctypes.c_int64, ctypes.c_int, _vp, ctypes.c_double, _vp, _vp, _vp]),
     ("stpi_set_variant", ctypes.c_int, [ctypes.c_int]),
     ("stpi_time_step", ctypes.c_int, [_PP, _vp, _vp, _vp, _vp, _sz, ctypes.c_int, ctypes.c_int, _vp,
                                       ctypes.POINTER(ctypes.c_double)]),

@@ -143,9 +143,30 @@ def power_iterate(f: torch.Tensor, k: Kernel, iters: int | None = None, tol: flo
     return x, out
 
 
+def coarse_problem(shape, k: Kernel, sy: int, st: int, dtype: torch.dtype = torch.float32):
+    """stpi_coarse_problem: the coarse grid's shape and kernel for factors (sy, st)."""
+    c = N.Problem()
+    N.check(N.lib.stpi_coarse_problem(ctypes.byref(problem_for(shape, k, dtype)), int(sy), int(st), ctypes.byref(c)))
+    return (c.T, c.H, c.W), Kernel(float(c.sigma_s), float(c.sigma_t), int(c.r_s), int(c.r_t))
+
+
 def coarse_shape(shape, sy: int, st: int):
-    T, H, W = (int(v) for v in shape)
-    return (-(-T // st), -(-H // sy), -(-W // sy))
+    return coarse_problem(shape, Kernel(1.0, 1.0, 0, 0), sy, st)[0]
+
+
+def scale(x: torch.Tensor, s: float, s_dev: torch.Tensor | None = None, out: torch.Tensor | None = None,
+          stream=None) -> torch.Tensor:
+    """stpi_scale: out = x * s (* s_dev, a float64 device scalar, when given)."""
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous device tensor")
+    if s_dev is not None and (s_dev.dtype != torch.float64 or not s_dev.is_cuda or s_dev.numel() != 1):
+        raise ValueError("s_dev must be one float64 device value")
+    out = torch.empty_like(x) if out is None else out
+    if out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must match x")
+    N.check(N.lib.stpi_scale(x.numel(), _dtype_code(x.dtype), x.data_ptr(), float(s),
+                             s_dev.data_ptr() if s_dev is not None else None, out.data_ptr(), _stream_ptr(stream)))
+    return out
 
 
 def downsample(x: torch.Tensor, sy: int, st: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

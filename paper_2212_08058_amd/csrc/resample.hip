@@ -4,6 +4,8 @@
 // voxel; arithmetic in float (double for double storage).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "../../include/stpi.h"
 #include "common.hpp"
 #include "host_internal.hpp"
@@ -98,6 +100,22 @@ static hipError_t launch_up(const CoarseDims &d, int mode, const void *in, const
     return hipGetLastError();
 }
 
+// y[i] = x[i] * s (times *s_dev when given), formed in double and rounded to
+// the storage type once.
+template <class ST>
+__global__ void scale_kernel(size_t n, const ST *x, double s, const double *s_dev, ST *y) {
+    const double m = s_dev ? s * *s_dev : s;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(y + i, (typename Compute<ST>::type)((double)ld(x + i) * m));
+}
+
+template <class ST>
+hipError_t launch_scale(size_t n, const void *x, double s, const double *s_dev, void *y, hipStream_t st_) {
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(scale_kernel<ST>, dim3(blocks), dim3(256), 0, st_, n, (const ST *)x, s, s_dev, (ST *)y);
+    return hipGetLastError();
+}
+
 static int coarse_dims(int T, int H, int W, int sy, int st, int dtype, CoarseDims &d) {
     if (T < 1 || H < 1 || W < 1) return fail(STPI_EINVAL, "volume must be at least 1x1x1 (got %dx%dx%d)", T, H, W);
     if (sy < 1 || st < 1) return fail(STPI_EINVAL, "factors must be >= 1 (got sy %d, st %d)", sy, st);
@@ -147,6 +165,39 @@ int stpi_upsample(int T, int H, int W, int sy, int st, int mode, int dtype, cons
                    : dtype == STPI_BF16 ? launch_up<bf16>(d, mode, in, mul, out, s)
                                         : launch_up<double>(d, mode, in, mul, out, s);
     return e == hipSuccess ? STPI_OK : hip_fail(e, "upsample");
+}
+
+int stpi_coarse_problem(const stpi_problem *fine, int sy, int st, stpi_problem *coarse) {
+    clear_error();
+    if (!fine || !coarse) return fail(STPI_EINVAL, "NULL problem");
+    CoarseDims d;
+    int rc = coarse_dims(fine->T, fine->H, fine->W, sy, st, fine->dtype, d);
+    if (rc) return rc;
+    if (fine->r_s < 0 || fine->r_t < 0 || !(fine->sigma_s > 0.f) || !(fine->sigma_t > 0.f))
+        return fail(STPI_EINVAL, "kernel needs sigmas > 0 and radii >= 0");
+    stpi_problem c = *fine;
+    c.T = d.Tc;
+    c.H = d.Hc;
+    c.W = d.Wc;
+    c.sigma_s = (float)((double)fine->sigma_s / sy);
+    c.sigma_t = (float)((double)fine->sigma_t / st);
+    c.r_s = (fine->r_s + sy - 1) / sy;
+    c.r_t = (fine->r_t + st - 1) / st;
+    *coarse = c;
+    return STPI_OK;
+}
+
+int stpi_scale(int64_t n, int dtype, const void *x, double s, const double *s_dev, void *y, void *stream) {
+    clear_error();
+    if (n < 0) return fail(STPI_EINVAL, "negative length");
+    if (dtype != STPI_F32 && dtype != STPI_BF16 && dtype != STPI_F64) return fail(STPI_EINVAL, "unknown dtype %d", dtype);
+    if (n == 0) return STPI_OK;
+    if (!x || !y) return fail(STPI_EINVAL, "NULL buffer");
+    hipStream_t sm = (hipStream_t)stream;
+    hipError_t e = dtype == STPI_F32    ? launch_scale<float>((size_t)n, x, s, s_dev, y, sm)
+                   : dtype == STPI_BF16 ? launch_scale<bf16>((size_t)n, x, s, s_dev, y, sm)
+                                        : launch_scale<double>((size_t)n, x, s, s_dev, y, sm);
+    return e == hipSuccess ? STPI_OK : hip_fail(e, "scale");
 }
 
 }  // extern "C"

@@ -21,7 +21,7 @@ import ctypes
 import torch
 
 from . import _native as N
-from .api import Kernel, _stream_ptr, problem_for, workspace_bytes
+from .api import Kernel, _stream_ptr, problem_for, scale, workspace_bytes
 
 
 def _dt(t: torch.Tensor) -> int:
@@ -169,7 +169,7 @@ class BCELoss(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_out):
         (g,) = ctx.saved_tensors
-        return g * g_out.to(g.dtype), None
+        return scale(g, 1.0, s_dev=g_out.detach().to(torch.float64).reshape(1).contiguous()), None
 
 
 def bce(x, gt):
@@ -337,7 +337,7 @@ class FocalDiceLoss(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_out):
         (g,) = ctx.saved_tensors
-        return g * g_out.to(g.dtype), None, None, None
+        return scale(g, 1.0, s_dev=g_out.detach().to(torch.float64).reshape(1).contiguous()), None, None, None
 
 
 def focal_dice(x, gt, gamma: float = 0.75, eps: float = 1.0):

@@ -28,7 +28,7 @@ import numpy as np
 import torch
 
 from . import _native as N
-from .api import (Kernel, _stream_ptr, coarse_shape, downsample, power_iterate, problem_for, upsample,
+from .api import (Kernel, _stream_ptr, coarse_problem, downsample, power_iterate, problem_for, scale, upsample,
                   workspace_bytes)
 from .learn import AdamW
 
@@ -127,8 +127,7 @@ class TwoLevel:
                  cap: int = 2000, device="cuda"):
         self.shape = tuple(int(v) for v in shape)
         self.sy, self.st, self.mode, self.tol, self.cap = int(sy), int(st), int(mode), float(tol), int(cap)
-        self.cshape = coarse_shape(self.shape, sy, st)
-        self.kc = Kernel(kern.sigma_s / sy, kern.sigma_t / st, -(-kern.r_s // sy), -(-kern.r_t // st))
+        self.cshape, self.kc = coarse_problem(self.shape, kern, sy, st)
         self.fc = torch.empty(self.cshape, dtype=torch.float32, device=device)
         self.xc = torch.empty_like(self.fc)
         self.wsc = torch.empty(workspace_bytes(self.cshape, self.kc), dtype=torch.uint8, device=device)
@@ -145,7 +144,7 @@ class TwoLevel:
 
     def net_input(self, u0: torch.Tensor) -> torch.Tensor:
         """The start scaled to O(1) for the net: u0 * sqrt(coarse voxels)."""
-        return u0 * math.sqrt(self.fc.numel())
+        return scale(u0, math.sqrt(self.fc.numel()))
 
 
 def solve_from(x0: torch.Tensor, f, kern, tol=1e-4, cap=2000, x=None, ws=None, stream=None):

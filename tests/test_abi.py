@@ -91,3 +91,25 @@ def test_grid_transfer_rejects_bad_arguments(native):
     assert L.stpi_upsample(4, 4, 4, 2, 1, 2, 0, 16, None, 32, None) == native.STPI_EINVAL  # mode
     assert L.stpi_upsample(4, 4, 4, 2, 1, 1, 0, 16, 32, 32, None) == native.STPI_EINVAL    # out aliases mul
     assert b"alias" in L.stpi_last_error()
+
+
+def test_coarse_problem_host_only(native):
+    """stpi_coarse_problem (host arithmetic, no device work): sizes rounded
+    up, sigmas divided by the factors, radii rounded up, dtype kept; bad
+    arguments rejected."""
+    P = native.Problem
+    fine = P(64, 480, 854, 5.0, 2.0, 15, 5, native.STPI_F32)
+    c = P()
+    assert native.lib.stpi_coarse_problem(ctypes.byref(fine), 4, 2, ctypes.byref(c)) == native.STPI_OK
+    assert (c.T, c.H, c.W) == (32, 120, 214)
+    assert (c.sigma_s, c.sigma_t, c.r_s, c.r_t, c.dtype) == (1.25, 1.0, 4, 3, native.STPI_F32)
+    fine = P(5, 7, 9, 3.0, 1.5, 8, 3, native.STPI_BF16)
+    assert native.lib.stpi_coarse_problem(ctypes.byref(fine), 3, 1, ctypes.byref(c)) == native.STPI_OK
+    assert (c.T, c.H, c.W, c.r_s, c.r_t, c.dtype) == (5, 3, 3, 3, 3, native.STPI_BF16)
+    assert c.sigma_s == 1.0 and c.sigma_t == 1.5
+    for bad in (dict(sy=0), dict(st=0)):
+        assert native.lib.stpi_coarse_problem(ctypes.byref(fine), bad.get("sy", 2), bad.get("st", 2),
+                                              ctypes.byref(c)) == native.STPI_EINVAL
+    assert native.lib.stpi_coarse_problem(None, 2, 2, ctypes.byref(c)) == native.STPI_EINVAL
+    zero = P(0, 7, 9, 3.0, 1.5, 8, 3, native.STPI_F32)
+    assert native.lib.stpi_coarse_problem(ctypes.byref(zero), 2, 2, ctypes.byref(c)) == native.STPI_EINVAL

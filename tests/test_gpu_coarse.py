@@ -86,3 +86,32 @@ def test_two_level_start_reaches_the_plain_eigenvector(P):
     assert info["converged"] and rp["converged"]
     assert 1.0 - float(torch.sum(xw.double() * xp.double())) < 1e-3
     assert info["iters"] <= rp["iters"]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16, torch.float64])
+def test_scale_kernel(P, dtype):
+    """stpi_scale: y = x s (times a device double when given), formed in
+    double and rounded once to the storage type (bfloat16: from the float
+    value, as every store of the library): bit-exact against the same
+    rounding on the host; y may be x; n = 0 is a no-op."""
+    _, api, _ = P
+    rng = np.random.default_rng(5)
+    x, xv = stored(rng.standard_normal(10007) * 3.0, dtype)
+    sd = torch.tensor([0.37], dtype=torch.float64, device=DEV)
+    for s, dev in ((1.7, None), (2.5, sd)):
+        m = s * (0.37 if dev is not None else 1.0)
+        y = api.scale(x, s, s_dev=dev)
+        want = xv * m
+        if dtype == torch.float64:
+            ref = want
+        else:
+            ref = torch.from_numpy(want.astype(np.float32)).to(dtype).double().numpy()
+        got = y.double().cpu().numpy()
+        assert np.array_equal(got, ref), (dtype, s, np.max(np.abs(got - ref)))
+    z = x.clone()
+    api.scale(z, 3.0, out=z)
+    torch.cuda.synchronize()
+    ref = xv * 3.0 if dtype == torch.float64 else torch.from_numpy((xv * 3.0).astype(np.float32)).to(dtype).double().numpy()
+    assert np.array_equal(z.double().cpu().numpy(), ref)
+    e = torch.empty(0, dtype=dtype, device=DEV)
+    api.scale(e, 2.0)
