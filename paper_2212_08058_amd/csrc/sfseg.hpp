@@ -121,10 +121,16 @@ __global__ __launch_bounds__(NTHR) void sfseg_step_kernel(SfsegArgs<ST> a) {
     const int ts = t0 - RT > 0 ? t0 - RT : 0;
     const int te = t1 + RT < a.T ? t1 + RT : a.T;
     CT ps[NPF], pfv[NPF], px[NPF];
-    auto fetch = [&](int t) __attribute__((always_inline)) {
-        const auto rs = make_rsrc(a.s + (size_t)t * plane, pbytes);
-        const auto rf = make_rsrc(a.f + (size_t)t * plane, pbytes);
-        const auto rx = make_rsrc(src + (size_t)t * plane, pbytes);
+    // ok = false issues the same loads on an empty range (they return 0 and
+    // touch no memory): both load groups below are issued in every frame, so
+    // the compiler's memory-counter waits before each use allow for the
+    // younger group instead of draining it
+    auto fetch = [&](int t, bool ok) __attribute__((always_inline)) {
+        const size_t tt = ok ? (size_t)t : 0;
+        const uint32_t pb = ok ? pbytes : 0u;
+        const auto rs = make_rsrc(a.s + tt * plane, pb);
+        const auto rf = make_rsrc(a.f + tt * plane, pb);
+        const auto rx = make_rsrc(src + tt * plane, pb);
 #pragma unroll
         for (int k = 0; k < NPF; ++k) {
             ps[k] = IO::load(rs, poff[k]);
@@ -132,7 +138,7 @@ __global__ __launch_bounds__(NTHR) void sfseg_step_kernel(SfsegArgs<ST> a) {
             px[k] = IO::load(rx, poff[k]);
         }
     };
-    fetch(ts);
+    fetch(ts, true);
     CT os[IPT][QX], of[IPT][QX], ox[IPT][QX];
     double d1 = 0.0, d2 = 0.0;
 
@@ -143,10 +149,13 @@ __global__ __launch_bounds__(NTHR) void sfseg_step_kernel(SfsegArgs<ST> a) {
         const bool live = tin < te;
         const int tout = tin - RT;
         const bool emit = tout >= t0;
-        if (emit) {
-            const auto rs = make_rsrc(a.s + (size_t)tout * plane, pbytes);
-            const auto rf = make_rsrc(a.f + (size_t)tout * plane, pbytes);
-            const auto rx = make_rsrc(src + (size_t)tout * plane, pbytes);
+        {
+            // the epilogue's operands (empty range when the frame is not emitted)
+            const size_t to = emit ? (size_t)tout : 0;
+            const uint32_t pb = emit ? pbytes : 0u;
+            const auto rs = make_rsrc(a.s + to * plane, pb);
+            const auto rf = make_rsrc(a.f + to * plane, pb);
+            const auto rx = make_rsrc(src + to * plane, pb);
 #pragma unroll
             for (int ii = 0; ii < IPT; ++ii)
 #pragma unroll
@@ -169,7 +178,9 @@ __global__ __launch_bounds__(NTHR) void sfseg_step_kernel(SfsegArgs<ST> a) {
                     lds[2 * SG::PLANE + e] = u3;
                 }
             }
-            if (tin + 1 < te) fetch(tin + 1);
+        }
+        fetch(tin + 1, tin + 1 < te);
+        if (live) {
             __syncthreads();
             // y-pass of each field: RY rows of one halo column per item
             for (int it = tid; it < NYI; it += NTHR) {
