@@ -28,8 +28,9 @@ struct AdjOp {
     size_t plane;
     uint32_t pbytes;
 
-    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs(const ST *p, int t) const {
-        return make_rsrc(p + (size_t)t * plane, pbytes);
+    // live = false: an empty range (the loads return 0 and touch no memory)
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs(const ST *p, int t, bool live = true) const {
+        return make_rsrc(p + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
     }
 
     template <int NPF>
@@ -37,8 +38,8 @@ struct AdjOp {
         CT f[NPF], g[NPF], z[NPF];
     };
     template <int NPF>
-    __device__ __forceinline__ void fetch(int t, const uint32_t (&off)[NPF], Raw<NPF> &raw) const {
-        const auto rf = rs(f, t), rg = rs(g1, t), rz = rs(zk1, t);
+    __device__ __forceinline__ void fetch(int t, const uint32_t (&off)[NPF], Raw<NPF> &raw, bool live = true) const {
+        const auto rf = rs(f, t, live), rg = rs(g1, t, live), rz = rs(zk1, t, live);
 #pragma unroll
         for (int k = 0; k < NPF; ++k) {
             raw.f[k] = IO::load(rf, off[k]);
@@ -55,10 +56,12 @@ struct AdjOp {
     struct OutRaw {
         CT f[IPT][QX], z[IPT][QX], v[IPT][QX], g[IPT][QX], z1[IPT][QX], gf[IPT][QX];
     };
-    template <int IPT, int QX>
-    __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw) const {
-        const auto rf = rs(f, t), rz = rs(zk, t), rv = rs(vk, t), rg = rs(g1, t), rz1 = rs(zk1, t),
-                   rgf = rs(gf, t);
+    // one element per load (a fixed count whatever the lanes); GRP unused
+    template <int IPT, int QX, int GRP = 0>
+    __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw,
+                                              bool live = true) const {
+        const auto rf = rs(f, t, live), rz = rs(zk, t, live), rv = rs(vk, t, live), rg = rs(g1, t, live),
+                   rz1 = rs(zk1, t, live), rgf = rs(gf, t, live);
 #pragma unroll
         for (int i = 0; i < IPT; ++i)
 #pragma unroll

@@ -147,6 +147,7 @@ void batch_step_kernel(BatchArgs<ST> a) {
             op.pbytes = (uint32_t)(op.plane * sizeof(ST));
             const int T = __builtin_amdgcn_readfirstlane(cd.T);
             const int H = __builtin_amdgcn_readfirstlane(cd.H), W = __builtin_amdgcn_readfirstlane(cd.W);
+            op.cut = tx0 + TW > W;  // 4-wide epilogue loads read past the right edge here
             if constexpr (PIPE == 3) {
                 // the single-clip product-form step's arithmetic, on this clip's state
                 const float fb = __uint_as_float(st_->ubound);

@@ -396,6 +396,7 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     op.pbytes = (uint32_t)(op.plane * sizeof(ST));
     double d1 = 0.0, d2 = 0.0;
     const int x0 = (tile % nbx) * TW, y0 = (tile / nbx) * TH;
+    op.cut = x0 + TW > a.W;  // 4-wide epilogue loads read past the right edge here
     if constexpr (PIPE == 3) {
         // space taps centred at 16 (the kernel's are centred at RS)
         __shared__ float tapl[2 * 16 + 1];
@@ -447,7 +448,6 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
             const int e = bound_exponent(bound, 100);
             const float umul = (float)(scale * ldexp(1.0, 10 - e));
             op.scale = ldexpf(1.f, e - 10);
-            op.cut = x0 + TW > a.W;
             stencil_tile_mfma<CT, RT, TH, TW, NTHR, PAD>(op, a.taps, tapl, umul, a.rs, a.T, t0, t1, a.H, a.W, x0, y0,
                                                    lds, d1, d2);
         }

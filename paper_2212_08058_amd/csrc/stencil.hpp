@@ -141,13 +141,21 @@ struct BufIO<double> {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, boff, 0, 0);
     }
     __device__ static __forceinline__ double rounded(double v) { return v; }
+    // four element loads; an offset that would wrap past 2^32 (boff near the
+    // out-of-range marker) stays out of range instead of wrapping into the buffer
     __device__ static __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, uint32_t boff, double (&v)[4]) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = load(r, boff + 8 * e);
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t o = boff + 8u * e;
+            v[e] = load(r, o < boff ? OOB : o);
+        }
     }
     __device__ static __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, uint32_t boff, const double (&v)[4]) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) store(r, boff + 8 * e, v[e]);
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t o = boff + 8u * e;
+            store(r, o < boff ? OOB : o, v[e]);
+        }
     }
     __device__ static __forceinline__ double store_rounded(__amdgpu_buffer_rsrc_t r, uint32_t boff, double v) {
         store(r, boff, v);
@@ -386,8 +394,13 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
                 const int e = tid + k * NTHR;
                 if (NU % NTHR == 0 || k < NPF - 1 || e < NU) U[e] = op.template input<NPF>(pf, k);
             }
-            if (emit) op.template fetch_out<IPT, QX>(tout, ooff, oraw);
-            if (tin + 1 < te) op.template fetch<NPF>(tin + 1, poff, pf);
+        }
+        // both load groups are issued for every frame (on an empty range when
+        // not needed), so that the memory-counter waits before each use allow
+        // for the younger group instead of draining it
+        op.template fetch_out<IPT, QX, 1>(tout, ooff, oraw, emit);
+        op.template fetch<NPF>(tin + 1, poff, pf, tin + 1 < te);
+        if (live) {
             __syncthreads();
             // y-pass
             for (int it = tid; it < NYI; it += NTHR) {
@@ -431,7 +444,6 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
                 }
             }
         } else {
-            if (emit) op.template fetch_out<IPT, QX>(tout, ooff, oraw);
 #pragma unroll
             for (int i = 0; i < IPT; ++i)
 #pragma unroll
@@ -528,8 +540,10 @@ __device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &
                 if (NU % NTHR == 0 || k < NPF - 1 || e < NU) U[e] = op.template input<NPF>(pf, k);
             }
         }
-        if (emit) op.template fetch_out<IPT, QX>(tout, ooff, oraw);
-        if (p + 1 < nin) op.template fetch<NPF>(ts + p + 1, poff, pf);
+        // both load groups in every phase (empty range when not needed): the
+        // memory-counter waits then allow for the younger group
+        op.template fetch_out<IPT, QX, 1>(tout, ooff, oraw, emit);
+        op.template fetch<NPF>(ts + p + 1, poff, pf, p + 1 < nin);
         // y-pass of local frame p - 1
         if (p >= 1 && p - 1 < nin) {
             const CT *U = U0 + ((p - 1) & 1) * PG::UB;
