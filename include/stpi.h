@@ -131,7 +131,11 @@ int stpi_step_noalloc(const stpi_problem *p, const void *f, const void *x, doubl
  * (flags bit 2 set, status OK; the caller restarts from uniform). On return
  * x holds the last unit iterate.
  * tol > 0: stop at the first k with ||x_k - x_{k-1}|| < tol, or after
- * max_iters applications; tol <= 0: exactly max_iters applications.
+ * max_iters applications; tol <= 0: exactly max_iters applications (Alg. 1's
+ * fixed count). A fixed-count run forms the inner product with the previous
+ * iterate (the residual and the Rayleigh quotient) on its first two
+ * applications and its last only, the ones it reports: the others do not
+ * read the previous iterate. The iterates are the same either way.
  * The iteration runs on the device without host round trips; the call
  * synchronises `stream` once at the end and fills *out (host). out may be
  * NULL: the call then returns as soon as the chain is enqueued (tolerance
@@ -278,7 +282,9 @@ int stpi_time_step(const stpi_problem *p, const void *f, const void *x, void *z,
  * stpi_iterate runs it (the step kernel with its fused finalisation; on a
  * matrix-core variant the product form, see stpi_iterate), measured with HIP
  * events on `stream` around `reps` back-to-back steps of a fixed-count chain
- * from the uniform start. f: device volume of p->dtype; x: a device volume of
+ * from the uniform start (steps 2 .. reps + 1 of a chain of reps + 2, so all
+ * but the first timed step skip the previous iterate as stpi_iterate's
+ * fixed-count runs do). f: device volume of p->dtype; x: a device volume of
  * p->dtype used as scratch (overwritten); ws as for stpi_iterate. variant: as
  * for stpi_time_step. *product_form (if not NULL) receives 1 when the product
  * form ran. Synchronises `stream`. Used by the benchmark. */

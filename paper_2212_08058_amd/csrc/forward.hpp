@@ -21,6 +21,7 @@ struct FwdLaunch {
     int T, H, W;
     int nseg;            // frame segments per tile (0 is read as 1)
     int fuse;            // iterate mode: finalise the step in its last workgroup (if the variant can)
+    int no_prev;         // iterate mode: the step's inner product with the previous iterate is not formed
     // matrix-core variants: float bits of a bound on |f x_stored scale| (iterate
     // mode: on |f|, the iterate being unit; single step: on |f x_stored|, scaled
     // by |x_scale| in the kernel)
@@ -48,6 +49,7 @@ struct FwdArgs {
     DevState *state;
     double *partials;
     int fuse;  // 1: the last workgroup to finish reduces the partials and finalises the step
+    int no_prev;  // 1: the previous iterate is not read at the outputs (p1 = 0; see FwdOp::prev)
     double x_scale;
     const double *norm_in;
     ST *vout;
@@ -75,6 +77,11 @@ struct FwdOp {
     size_t plane;     // elements per frame
     uint32_t pbytes;  // bytes per frame
     bool cut = false;  // epilogue operands came from 4-wide loads that groups cut by the right edge extend past it
+    // false: the epilogue reads the previous iterate on an empty range (as 0),
+    // so p1 is 0. A chain of a fixed count of steps uses p1 (the cosine with
+    // the previous iterate: the residual and the Rayleigh quotient) only on
+    // its first two steps and its last; the other steps save that read.
+    bool prev = true;
 
     template <int NPF>
     struct Raw {
@@ -112,7 +119,7 @@ struct FwdOp {
     __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw,
                                               bool live = true) const {
         const auto rf = make_rsrc(f + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
-        const auto rx = make_rsrc(src + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
+        const auto rx = make_rsrc(src + (size_t)(live ? t : 0) * plane, live && prev ? pbytes : 0u);
         if constexpr (WIDE) {
             static_assert(QX == 4, "4-wide groups");
 #pragma unroll
@@ -148,7 +155,7 @@ struct FwdOp {
     __device__ __forceinline__ void fetch_out_fixed(int t, const uint32_t (&off)[IPT][QX],
                                                     OutRaw<IPT, QX> &raw) const {
         const auto rf = make_rsrc(f + (size_t)t * plane, pbytes);
-        const auto rx = make_rsrc(src + (size_t)t * plane, pbytes);
+        const auto rx = make_rsrc(src + (size_t)t * plane, prev ? pbytes : 0u);
 #pragma unroll
         for (int i = 0; i < IPT; ++i)
 #pragma unroll
@@ -261,6 +268,7 @@ struct FwdOpP {
     uint32_t pbytes;
     mutable float wmax = 0.f;  // max |w_new| stored by this thread (the next step's staging bound)
     bool cut = false;          // as FwdOp::cut
+    bool prev = true;          // as FwdOp::prev
 
     template <int NPF>
     struct Raw {
@@ -284,7 +292,7 @@ struct FwdOpP {
     __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw,
                                               bool live = true) const {
         const auto rf = make_rsrc(f + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
-        const auto ru = make_rsrc(src + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
+        const auto ru = make_rsrc(src + (size_t)(live ? t : 0) * plane, live && prev ? pbytes : 0u);
         if constexpr (WIDE) {
             static_assert(QX == 4, "4-wide groups");
 #pragma unroll
@@ -397,6 +405,7 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
     double d1 = 0.0, d2 = 0.0;
     const int x0 = (tile % nbx) * TW, y0 = (tile / nbx) * TH;
     op.cut = x0 + TW > a.W;  // 4-wide epilogue loads read past the right edge here
+    op.prev = !a.no_prev;
     if constexpr (PIPE == 3) {
         // space taps centred at 16 (the kernel's are centred at RS)
         __shared__ float tapl[2 * 16 + 1];
@@ -423,6 +432,7 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
             pp.plane = op.plane;
             pp.pbytes = op.pbytes;
             pp.cut = x0 + TW > a.W;
+            pp.prev = op.prev;
             // staging power of two from the input's own maximum
             const float win = first ? bound : __uint_as_float(a.state->wmax[cur]);
             float umul;
@@ -517,6 +527,7 @@ hipError_t launch_fwd(const FwdLaunch &L, hipStream_t stream) {
     a.state = L.state;
     a.partials = L.partials;
     a.fuse = L.state && L.fuse && NTHR >= FINAL_THREADS ? 1 : 0;
+    a.no_prev = L.state && L.no_prev ? 1 : 0;
     a.x_scale = L.x_scale;
     a.norm_in = L.norm_in;
     a.vout = (ST *)L.vout;

@@ -678,7 +678,8 @@ int stpi_time_chain_step(const stpi_problem *p, const void *f, void *x, void *ws
     const int pform = chain_pform(v, total);
     if (product_form) *product_form = pform;
     rc = enqueue_chain_init(p, ops, x, state, partials, 1, total, 0.0, s, v, f, buf1, pform);
-    if (!rc) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, 1, s, pform);
+    // the steps as a fixed-count chain of `total` steps runs them
+    if (!rc) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, 1, s, pform, total, 0);
     if (rc) return rc;
     hipEvent_t e0, e1;
     hipError_t e;
@@ -688,7 +689,7 @@ int stpi_time_chain_step(const stpi_problem *p, const void *f, void *x, void *ws
         return hip_fail(e, "event create");
     }
     e = hipEventRecord(e0, s);
-    if (e == hipSuccess) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, reps, s, pform);
+    if (e == hipSuccess) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, reps, s, pform, total, 1);
     if (e == hipSuccess && !rc) e = hipEventRecord(e1, s);
     if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -793,7 +794,7 @@ int enqueue_chain_tail(const stpi_problem *p, const DtypeOps *ops, const void *f
 }
 
 int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, void *x, void *buf1, DevState *state,
-                        double *partials, int steps, hipStream_t s, int pform) {
+                        double *partials, int steps, hipStream_t s, int pform, int fixed_total, int k0) {
     hipError_t e;
     FwdLaunch FL;
     std::memset(&FL, 0, sizeof(FL));
@@ -815,6 +816,8 @@ int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, 
     const FwdLaunchFn launch = pform ? v->launch_p : v->launch;
     if (!launch) return fail(STPI_EUNSUPPORTED, "variant has no product-form step");
     for (int k = 0; k < steps; ++k) {
+        const int kk = k0 + k;
+        FL.no_prev = fixed_total > 0 && kk >= 2 && kk < fixed_total - 1 ? 1 : 0;
         if ((e = launch(FL, s)) != hipSuccess) return hip_fail(e, "step kernel launch");
         if (!FL.fuse && (e = launch_finalize(partials, nb, state, s)) != hipSuccess)
             return hip_fail(e, "finalize launch");
@@ -826,7 +829,7 @@ int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant 
                       void *buf1, DevState *state, double *partials, int init, int max_iters, double tol,
                       hipStream_t s, int pform) {
     int rc = enqueue_chain_init(p, ops, x, state, partials, init, max_iters, tol, s, v, f, buf1, pform);
-    if (!rc) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, max_iters, s, pform);
+    if (!rc) rc = enqueue_chain_steps(p, v, f, x, buf1, state, partials, max_iters, s, pform, tol > 0.0 ? 0 : max_iters);
     return rc ? rc : enqueue_chain_tail(p, ops, f, x, buf1, state, s, pform);
 }
 

@@ -38,8 +38,12 @@ int chain_pform(const Variant *v, int max_iters);
 int enqueue_chain_init(const stpi_problem *p, const DtypeOps *ops, void *x, DevState *state, double *partials,
                        int init, int max_iters, double tol, hipStream_t s, const Variant *v, const void *f,
                        void *buf1, int pform);
+// fixed_total > 0: the steps are steps k0 .. k0 + steps - 1 of a chain of
+// fixed_total steps with no tolerance, whose inner products with the
+// previous iterate (residual, Rayleigh quotient) are used only on the first
+// two steps and the last: the others do not read the previous iterate.
 int enqueue_chain_steps(const stpi_problem *p, const Variant *v, const void *f, void *x, void *buf1, DevState *state,
-                        double *partials, int steps, hipStream_t s, int pform);
+                        double *partials, int steps, hipStream_t s, int pform, int fixed_total = 0, int k0 = 0);
 int enqueue_chain_tail(const stpi_problem *p, const DtypeOps *ops, const void *f, void *x, void *buf1,
                        DevState *state, hipStream_t s, int pform);
 int enqueue_iteration(const stpi_problem *p, const DtypeOps *ops, const Variant *v, const void *f, void *x,
