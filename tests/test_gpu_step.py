@@ -448,3 +448,26 @@ def test_first_residuals_and_rise_check(P):
     x, r = P.power_iterate(fd, k, tol=1e-6, max_iters=200, x0=to_dev(x0_good, torch.float32), rise_check=True)
     torch.cuda.synchronize()
     assert not (r["flags"] & 4) and r["converged"] and r["iters"] > 2
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("shape,kp", [((16, 128, 250), (5.0, 2.0, 15, 5)), ((9, 40, 70), (2.0, 1.0, 4, 2))])
+def test_fixed_count_skips_no_reported_value(P, dtype, shape, kp):
+    """A fixed-count chain forms the inner product with the previous iterate
+    only on the steps whose residual it reports (the first two and the last);
+    every reported value and the iterate must equal, bitwise, those of a run
+    that forms it on every step (a tolerance run whose tolerance is never
+    reached). Matrix-core product form (r = (15, 5)) and vector loop."""
+    f, _ = synth.blob_clip(*shape, 3, 17)
+    kern = P.Kernel(*kp)
+    fd = to_dev(f, dtype)
+    for iters in (3, 12):
+        x_fix, r_fix = P.power_iterate(fd, kern, iters=iters)
+        x_fix = x_fix.clone()
+        x_all, r_all = P.power_iterate(fd, kern, tol=1e-300, max_iters=iters)
+        torch.cuda.synchronize()
+        print(shape, dtype, iters, r_fix["residual"], r_all["residual"], r_fix["rayleigh"])
+        assert r_fix["iters"] == r_all["iters"] == iters and not r_all["converged"]
+        assert torch.equal(x_fix, x_all)
+        for key in ("residual", "lambda_", "rayleigh", "r1", "r2", "flags"):
+            assert r_fix[key] == r_all[key], (key, r_fix[key], r_all[key])
