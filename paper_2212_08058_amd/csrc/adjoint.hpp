@@ -56,8 +56,8 @@ struct AdjOp {
     struct OutRaw {
         CT f[IPT][QX], z[IPT][QX], v[IPT][QX], g[IPT][QX], z1[IPT][QX], gf[IPT][QX];
     };
-    // one element per load (a fixed count whatever the lanes); GRP unused
-    template <int IPT, int QX, int GRP = 0>
+    // one element per load (a fixed count whatever the lanes)
+    template <int IPT, int QX>
     __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw,
                                               bool live = true) const {
         const auto rf = rs(f, t, live), rz = rs(zk, t, live), rv = rs(vk, t, live), rg = rs(g1, t, live),

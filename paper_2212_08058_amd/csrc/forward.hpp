@@ -108,40 +108,27 @@ struct FwdOp {
     struct OutRaw {
         CT f[IPT][QX], x[IPT][QX];
     };
-    // Epilogue operands. A group of QX = 4 outputs that lies wholly inside its
-    // row moves with one 4-wide access; groups cut by the right edge of the
-    // frame fall back to single elements with per-element out-of-range offsets.
-    // WIDE (QX = 4): every group moves with one 4-wide access at its first
-    // offset, so the count of memory instructions is fixed; a group cut by the
-    // right edge then reads into the next row, and the epilogue must be told
-    // (cut) to take f there as zero.
-    template <int IPT, int QX, bool WIDE = false>
+    // Epilogue operands, in a fixed count of memory instructions whatever the
+    // lanes: with QX = 4 each group moves with one 4-wide access at its first
+    // offset (a group cut by the right edge of the frame then reads into the
+    // next row, and the epilogue, told by cut, takes f there as 0); otherwise
+    // element by element. live = false issues the loads on an empty range.
+    template <int IPT, int QX>
     __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw,
                                               bool live = true) const {
         const auto rf = make_rsrc(f + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
         const auto rx = make_rsrc(src + (size_t)(live ? t : 0) * plane, live && prev ? pbytes : 0u);
-        if constexpr (WIDE) {
-            static_assert(QX == 4, "4-wide groups");
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                IO::load4(rf, off[i][0], raw.f[i]);
-                IO::load4(rx, off[i][0], raw.x[i]);
-            }
-            return;
-        }
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             if constexpr (QX == 4) {
-                if (off[i][3] != OOB) {
-                    IO::load4(rf, off[i][0], raw.f[i]);
-                    IO::load4(rx, off[i][0], raw.x[i]);
-                    continue;
-                }
-            }
+                IO::load4(rf, off[i][0], raw.f[i]);
+                IO::load4(rx, off[i][0], raw.x[i]);
+            } else {
 #pragma unroll
-            for (int q = 0; q < QX; ++q) {
-                raw.f[i][q] = IO::load(rf, off[i][q]);
-                raw.x[i][q] = IO::load(rx, off[i][q]);
+                for (int q = 0; q < QX; ++q) {
+                    raw.f[i][q] = IO::load(rf, off[i][q]);
+                    raw.x[i][q] = IO::load(rx, off[i][q]);
+                }
             }
         }
     }
@@ -288,33 +275,22 @@ struct FwdOpP {
     struct OutRaw {
         CT f[IPT][QX], u[IPT][QX];
     };
-    template <int IPT, int QX, bool WIDE = false>  // WIDE as FwdOp::fetch_out
+    template <int IPT, int QX>  // as FwdOp::fetch_out
     __device__ __forceinline__ void fetch_out(int t, const uint32_t (&off)[IPT][QX], OutRaw<IPT, QX> &raw,
                                               bool live = true) const {
         const auto rf = make_rsrc(f + (size_t)(live ? t : 0) * plane, live ? pbytes : 0u);
         const auto ru = make_rsrc(src + (size_t)(live ? t : 0) * plane, live && prev ? pbytes : 0u);
-        if constexpr (WIDE) {
-            static_assert(QX == 4, "4-wide groups");
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                IO::load4(rf, off[i][0], raw.f[i]);
-                IO::load4(ru, off[i][0], raw.u[i]);
-            }
-            return;
-        }
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             if constexpr (QX == 4) {
-                if (off[i][3] != OOB) {
-                    IO::load4(rf, off[i][0], raw.f[i]);
-                    IO::load4(ru, off[i][0], raw.u[i]);
-                    continue;
-                }
-            }
+                IO::load4(rf, off[i][0], raw.f[i]);
+                IO::load4(ru, off[i][0], raw.u[i]);
+            } else {
 #pragma unroll
-            for (int q = 0; q < QX; ++q) {
-                raw.f[i][q] = IO::load(rf, off[i][q]);
-                raw.u[i][q] = IO::load(ru, off[i][q]);
+                for (int q = 0; q < QX; ++q) {
+                    raw.f[i][q] = IO::load(rf, off[i][q]);
+                    raw.u[i][q] = IO::load(ru, off[i][q]);
+                }
             }
         }
     }

@@ -313,13 +313,15 @@ __device__ __forceinline__ void ring_loop(int n, F &&body) {
 // Streams one tile through all frames. Op (forward step or adjoint step)
 // provides, with ESZ its element size in bytes:
 //   template <int NPF> struct Raw                 raw prefetched operands
-//   template <int NPF> void fetch(int t, const uint32_t (&boff)[NPF], Raw<NPF> &raw)
-//       issue the loads of frame t at in-frame byte offsets (OOB offsets give 0)
+//   template <int NPF> void fetch(int t, const uint32_t (&boff)[NPF], Raw<NPF> &raw, bool live)
+//       issue the loads of frame t at in-frame byte offsets (OOB offsets give 0;
+//       an empty range when !live)
 //   template <int NPF> CT input(const Raw<NPF> &raw, int k)
 //       pass input u of prefetched element k (e.g. f * x)
 //   template <int IPT, int QX> struct OutRaw      operands the epilogue reads
 //   template <int IPT, int QX> void fetch_out(int t, const uint32_t (&boff)[IPT][QX],
-//       OutRaw<IPT, QX> &raw)  issue the epilogue's loads of output frame t early
+//       OutRaw<IPT, QX> &raw, bool live)  issue the epilogue's loads of output frame t
+//       early, in a fixed count of instructions (on an empty range when !live)
 //   template <int IPT, int QX> void emit_frame(int t, const CT (&acc)[IPT][QX],
 //       const OutRaw<IPT, QX> &raw, const uint32_t (&boff)[IPT][QX], double &d1, double &d2)
 //       epilogue of output frame t (OOB offsets are dropped stores, zero sums)
@@ -398,7 +400,7 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
         // both load groups are issued for every frame (on an empty range when
         // not needed), so that the memory-counter waits before each use allow
         // for the younger group instead of draining it
-        op.template fetch_out<IPT, QX, 1>(tout, ooff, oraw, emit);
+        op.template fetch_out<IPT, QX>(tout, ooff, oraw, emit);
         op.template fetch<NPF>(tin + 1, poff, pf, tin + 1 < te);
         if (live) {
             __syncthreads();
@@ -542,7 +544,7 @@ __device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &
         }
         // both load groups in every phase (empty range when not needed): the
         // memory-counter waits then allow for the younger group
-        op.template fetch_out<IPT, QX, 1>(tout, ooff, oraw, emit);
+        op.template fetch_out<IPT, QX>(tout, ooff, oraw, emit);
         op.template fetch<NPF>(ts + p + 1, poff, pf, p + 1 < nin);
         // y-pass of local frame p - 1
         if (p >= 1 && p - 1 < nin) {

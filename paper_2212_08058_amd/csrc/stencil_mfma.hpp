@@ -304,7 +304,7 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
         // Both load groups are issued in every phase (on an empty range when
         // not needed) so that the memory-counter waits before each use allow
         // for the younger group instead of draining it.
-        op.template fetch_out<XPW, 4, true>(tout, ooff, oraw, emit);
+        op.template fetch_out<XPW, 4>(tout, ooff, oraw, emit);
         // matrix-core products of both passes (frames p - 2 and p - 1; the
         // buffers they read were written before the last barrier), issued
         // before the vector work of the phase so that they run beside it
