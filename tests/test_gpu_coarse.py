@@ -108,6 +108,24 @@ def test_scale_kernel(P, dtype):
             ref = torch.from_numpy(want.astype(np.float32)).to(dtype).double().numpy()
         got = y.double().cpu().numpy()
         assert np.array_equal(got, ref), (dtype, s, np.max(np.abs(got - ref)))
+    if dtype == torch.bfloat16:
+        # x = +-m 2^e with m odd in [129, 169]: 1.5 x = 3m 2^(e-1) has a 9-bit
+        # odd significand, exactly halfway between two bfloat16 values, so
+        # every element tests the conversion's ties-to-even rule (half of
+        # them round up, half down)
+        m = np.arange(129, 170, 2, dtype=np.float64)
+        e = np.arange(-20, 21, dtype=np.float64)
+        tv = (m[:, None] * np.exp2(e)[None, :]).ravel()
+        tv = np.concatenate([tv, -tv])
+        t = torch.from_numpy(tv).to(torch.bfloat16)
+        assert np.array_equal(t.double().numpy(), tv)
+        want = (tv * 1.5).astype(np.float32)
+        assert np.array_equal(want.astype(np.float64), tv * 1.5)
+        ref = torch.from_numpy(want).to(torch.bfloat16).double().numpy()
+        up = np.abs(ref) > np.abs(tv * 1.5)
+        assert 0 < up.sum() < up.size
+        got = api.scale(t.to(DEV), 1.5).double().cpu().numpy()
+        assert np.array_equal(got, ref), np.flatnonzero(got != ref)[:8]
     z = x.clone()
     api.scale(z, 3.0, out=z)
     torch.cuda.synchronize()
