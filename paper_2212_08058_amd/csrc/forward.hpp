@@ -298,34 +298,51 @@ struct FwdOpP {
     __device__ __forceinline__ void emit_frame(int t, const CT (&acc)[IPT][QX], const OutRaw<IPT, QX> &raw,
                                                const uint32_t (&off)[IPT][QX], double &d1, double &d2) const {
         const auto rw = make_rsrc(dst + (size_t)t * plane, pbytes);
+        CT wr[IPT][QX], r[IPT][QX];  // what the stores leave in memory, 1/f
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            CT w[QX], wr[QX], fv[QX];  // w_new, what its store leaves in memory, f
+            CT w[QX];
 #pragma unroll
             for (int q = 0; q < QX; ++q) {
-                fv[q] = cut && off[i][q] == OOB ? CT(0) : raw.f[i][q];
-                w[q] = (acc[i][q] * (fv[q] * fv[q])) * sg;
+                const CT fv = cut && off[i][q] == OOB ? CT(0) : raw.f[i][q];
+                w[q] = (acc[i][q] * (fv * fv)) * sg;
+                r[i][q] = recip_or_zero(fv);
             }
             bool whole = false;
             if constexpr (QX == 4) {
                 if (off[i][3] != OOB) {
-                    IO::store4_rounded(rw, off[i][0], w, wr);
+                    IO::store4_rounded(rw, off[i][0], w, wr[i]);
                     whole = true;
                 }
             }
             if (!whole) {
 #pragma unroll
-                for (int q = 0; q < QX; ++q) wr[q] = IO::store_rounded(rw, off[i][q], w[q]);
+                for (int q = 0; q < QX; ++q) wr[i][q] = IO::store_rounded(rw, off[i][q], w[q]);
             }
+        }
+        // The sums after every store of the frame: the branch on prev (uniform)
+        // then holds no memory operation, so the waits that follow count the
+        // same younger operations on both paths.
+        if (prev) {
 #pragma unroll
-            for (int q = 0; q < QX; ++q) {
-                const CT r = recip_or_zero(fv[q]);
-                wmax = fmaxf(wmax, fabsf(wr[q]));
-                const double xn = (double)(wr[q] * r);
-                const double xp = (double)(raw.u[i][q] * r);
-                d2 = fma(xn, xn, d2);
-                d1 = fma(xp, xn, d1);
-            }
+            for (int i = 0; i < IPT; ++i)
+#pragma unroll
+                for (int q = 0; q < QX; ++q) {
+                    wmax = fmaxf(wmax, fabsf(wr[i][q]));
+                    const double xn = (double)(wr[i][q] * r[i][q]);
+                    const double xp = (double)(raw.u[i][q] * r[i][q]);
+                    d2 = fma(xn, xn, d2);
+                    d1 = fma(xp, xn, d1);
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < IPT; ++i)
+#pragma unroll
+                for (int q = 0; q < QX; ++q) {
+                    wmax = fmaxf(wmax, fabsf(wr[i][q]));
+                    const double xn = (double)(wr[i][q] * r[i][q]);
+                    d2 = fma(xn, xn, d2);
+                }
         }
     }
 };
