@@ -496,3 +496,68 @@ def test_product_form_long_chain_matches_vector_loop(P):
           f"down to {np.abs(b[low]).min() / m:.1e}) {e_low:.3e}; lambda {r['lambda_']:.9g} vs {rv['lambda_']:.9g}")
     assert e_all <= 1e-5 and e_low <= 1e-5
     assert abs(r["lambda_"] - rv["lambda_"]) <= 1e-6 * rv["lambda_"]
+
+
+SEGMENT_CASES = [
+    ((21, 64, 128), (5.0, 2.0, 15, 5)),   # two frame segments
+    ((30, 64, 128), (5.0, 2.0, 15, 5)),   # three: the middle one walks forward with both halos
+    ((16, 64, 128), (2.0, 1.0, 4, 2)),    # four
+    ((12, 32, 64), (4.0, 1.5, 8, 3)),     # one tile, two segments
+]
+
+
+@pytest.mark.parametrize("shape,kp", SEGMENT_CASES)
+def test_frame_segments_walk_both_ways(P, shape, kp):
+    """When a launch splits the frames, the segment that ends at the last frame
+    (and starts after the first) is walked backward, so its last outputs need
+    no ring steps past its input. Per matrix-core variant that splits this
+    shape: one step against the oracle's direct application with every frame's
+    error bounded on its own (the frames next to each segment boundary and the
+    last r_t frames are where a wrong frame order or a missed output shows),
+    and 6-step product-form chains (FP32 and BF16 storage) against the
+    oracle's iteration."""
+    from paper_2212_08058_amd import _native as N
+    kern = P.Kernel(*kp)
+    ok = OKf(kern)
+    T = shape[0]
+    rng = np.random.default_rng(sum(shape) + 7)
+    f = rng.uniform(0.05, 1.0, shape).astype(np.float32)
+    x = rng.uniform(0.0, 1.0, shape).astype(np.float32)
+    ref = oracle.apply(f.astype(np.float64), x.astype(np.float64), ok)
+    xr, info = oracle.iterate(f, ok, iters=6)
+    fb = torch.from_numpy(f).to(torch.bfloat16)
+    xrb, infob = oracle.iterate(fb.double().numpy(), ok, iters=6)
+    fd, xd, fbd = torch.from_numpy(f).to(DEV), torch.from_numpy(x).to(DEV), fb.to(DEV)
+    split = 0
+    for code, dt in ((N.STPI_F32, torch.float32), (N.STPI_BF16, torch.bfloat16)):
+        for i, vi in mfma_variants(code):
+            if vi[1] < kern.r_t or vi[0] < kern.r_s:
+                continue
+            nseg = P.launch_shape(shape, kern, dtype=dt, variant=i)["segments"]
+            if nseg < 2:
+                continue
+            split += 1
+            with forced(i):
+                if dt == torch.float32:
+                    z, _ = P.step(fd, xd, kern)
+                    xg, r = P.power_iterate(fd, kern, iters=6)
+                else:
+                    xg, r = P.power_iterate(fbd, kern, iters=6)
+                torch.cuda.synchronize()
+            if dt == torch.float32:
+                zz = z.double().cpu().numpy()
+                per_frame = [rel_l2(zz[t], ref[t]) for t in range(T)]
+                print(shape, kp, "variant", i, vi[:5], "segments", nseg, f"worst frame {max(per_frame):.2e}")
+                assert max(per_frame) <= 1e-5, (i, nseg, per_frame)
+                err = rel_l2(xg.double().cpu().numpy(), xr)
+                assert r["iters"] == 6 and err <= 1e-5, (i, err)
+                assert abs(r["lambda_"] - info.lambdas[-1]) <= 1e-5 * info.lambdas[-1]
+                assert abs(r["residual"] - info.residuals[-1]) <= 1e-4 * info.residuals[-1] + 1e-6
+            else:
+                xx = xg.double().cpu().numpy()
+                err = rel_l2(xx, xrb)
+                worst = max(rel_l2(xx[t], xrb[t]) for t in range(T))
+                print(shape, kp, "bf16 variant", i, vi[:5], "segments", nseg, f"rel L2 {err:.2e}, worst frame {worst:.2e}")
+                assert err <= 2.0 ** -8 and worst <= 2.0 ** -7, (i, err, worst)
+                assert abs(r["lambda_"] - infob.lambdas[-1]) <= 2.0 ** -8 * infob.lambdas[-1]
+    assert split, "no matrix-core variant split the frames of this shape"
