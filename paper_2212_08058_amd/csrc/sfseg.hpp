@@ -118,8 +118,7 @@ __global__ __launch_bounds__(NTHR) void sfseg_step_kernel(SfsegArgs<ST> a) {
 #pragma unroll
                 for (int q = 0; q < QX; ++q) acc[m][s][i][q] = CT(0);
 
-    const int ts = t0 - RT > 0 ? t0 - RT : 0;
-    const int te = t1 + RT < a.T ? t1 + RT : a.T;
+    const FrameWalk<RT> fw(a.T, t0, t1);  // frame order (the last segment walks backward)
     CT ps[NPF], pfv[NPF], px[NPF];
     // ok = false issues the same loads on an empty range (they return 0 and
     // touch no memory): both load groups below are issued in every frame, so
@@ -138,17 +137,16 @@ __global__ __launch_bounds__(NTHR) void sfseg_step_kernel(SfsegArgs<ST> a) {
             px[k] = IO::load(rx, poff[k]);
         }
     };
-    fetch(ts, true);
+    fetch(fw.in(0), true);
     CT os[IPT][QX], of[IPT][QX], ox[IPT][QX];
     double d1 = 0.0, d2 = 0.0;
 
-    ring_loop<NTS, 0>(t1 + RT - ts, [&](auto ring_pos, int i) __attribute__((always_inline)) {
+    ring_loop<NTS, 0>(fw.nstep, [&](auto ring_pos, int i) __attribute__((always_inline)) {
         constexpr int J = decltype(ring_pos)::value;
         CT v[3][IPT][QX];
-        const int tin = ts + i;
-        const bool live = tin < te;
-        const int tout = tin - RT;
-        const bool emit = tout >= t0;
+        const bool live = i < fw.nin;
+        const int tout = fw.out(i);
+        const bool emit = tout >= t0 && tout < t1;
         {
             // the epilogue's operands (empty range when the frame is not emitted)
             const size_t to = emit ? (size_t)tout : 0;
@@ -179,7 +177,7 @@ __global__ __launch_bounds__(NTHR) void sfseg_step_kernel(SfsegArgs<ST> a) {
                 }
             }
         }
-        fetch(tin + 1, tin + 1 < te);
+        fetch(fw.in(i + 1), i + 1 < fw.nin);
         if (live) {
             __syncthreads();
             // y-pass of each field: RY rows of one halo column per item

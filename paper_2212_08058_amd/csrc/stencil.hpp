@@ -310,6 +310,34 @@ __device__ __forceinline__ void ring_loop(int n, F &&body) {
     for (int base = 0; base < n; base += NTS) ring_loop_unroll<NTS, SHIFT, 0>(base, n, body);
 }
 
+// Frame order of a block that produces output frames [t0, t1) of a clip of T
+// frames from input frames [ts, te) = [t0 - RT, t1 + RT) clipped to the clip.
+// Walking forward, a range that ends at T completes its last RT output
+// frames only after RT more ring steps with no input (the frames past T are
+// zero): steps that do nothing but the epilogue. A range that ends at T and
+// starts after 0 is walked backward instead: its missing inputs are then the
+// ones it never reaches, and its last output frame completes with its last
+// input frame. The ring needs no change for that: the temporal taps are even
+// in the frame distance (built from its square), so a reversed walk applies
+// the same taps. Local step k takes input frame in(k) (while k < nin) and
+// completes the ring slot of output frame out(k); the last owned output
+// frame completes at step nstep - 1.
+template <int RT>
+struct FrameWalk {
+    int ts, te, nin, fb, dir, nstep;
+    __device__ __forceinline__ FrameWalk(int T, int t0, int t1) {
+        ts = t0 - RT > 0 ? t0 - RT : 0;
+        te = t1 + RT < T ? t1 + RT : T;
+        nin = te - ts;
+        const bool rev = t1 == T && t0 > 0;
+        dir = rev ? -1 : 1;
+        fb = rev ? te - 1 : ts;
+        nstep = (rev ? te - t0 : t1 - ts) + RT;
+    }
+    __device__ __forceinline__ int in(int k) const { return fb + dir * k; }
+    __device__ __forceinline__ int out(int k) const { return fb + dir * (k - RT); }
+};
+
 // Streams one tile through all frames. Op (forward step or adjoint step)
 // provides, with ESZ its element size in bytes:
 //   template <int NPF> struct Raw                 raw prefetched operands
@@ -372,21 +400,19 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
 #pragma unroll
             for (int q = 0; q < QX; ++q) acc[s][i][q] = CT(0);
 
-    const int ts = t0 - RT > 0 ? t0 - RT : 0;  // first input frame
-    const int te = t1 + RT < T ? t1 + RT : T;  // one past the last input frame
+    const FrameWalk<RT> fw(T, t0, t1);
     typename Op::template Raw<NPF> pf;
-    op.template fetch<NPF>(ts, poff, pf);
+    op.template fetch<NPF>(fw.in(0), poff, pf);
 
     typename Op::template OutRaw<IPT, QX> oraw;
-    // local step i takes input frame ts + i (none once past te) and emits
-    // output frame ts + i - RT when the block owns it
-    ring_loop<NTS, 0>(t1 + RT - ts, [&](auto ring_pos, int i) __attribute__((always_inline)) {
+    // local step i takes input frame fw.in(i) (none once past nin) and emits
+    // output frame fw.out(i) when the block owns it
+    ring_loop<NTS, 0>(fw.nstep, [&](auto ring_pos, int i) __attribute__((always_inline)) {
         constexpr int J = decltype(ring_pos)::value;  // i % NTS
         CT v[IPT][QX];
-        const int tin = ts + i;
-        const bool live = tin < te;
-        const int tout = tin - RT;
-        const bool emit = tout >= t0;
+        const bool live = i < fw.nin;
+        const int tout = fw.out(i);
+        const bool emit = tout >= t0 && tout < t1;
         if (live) {
             // stage this frame's prefetched input; then the epilogue's operands
             // load while this frame is filtered (after the staging: loads
@@ -401,7 +427,7 @@ __device__ __forceinline__ void stencil_tile(const Op &op, const Taps<CT> &tp, i
         // not needed), so that the memory-counter waits before each use allow
         // for the younger group instead of draining it
         op.template fetch_out<IPT, QX>(tout, ooff, oraw, emit);
-        op.template fetch<NPF>(tin + 1, poff, pf, tin + 1 < te);
+        op.template fetch<NPF>(fw.in(i + 1), poff, pf, i + 1 < fw.nin);
         if (live) {
             __syncthreads();
             // y-pass
@@ -518,20 +544,19 @@ __device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &
 #pragma unroll
             for (int q = 0; q < QX; ++q) acc[s][i][q] = CT(0);
 
-    const int ts = t0 - RT > 0 ? t0 - RT : 0;  // first input frame
-    const int te = t1 + RT < T ? t1 + RT : T;  // one past the last input frame
-    const int nin = te - ts;                   // input frames (local 0 .. nin - 1)
+    const FrameWalk<RT> fw(T, t0, t1);
+    const int nin = fw.nin;  // input frames (local 0 .. nin - 1)
     typename Op::template Raw<NPF> pf;
-    op.template fetch<NPF>(ts, poff, pf);
+    op.template fetch<NPF>(fw.in(0), poff, pf);
     typename Op::template OutRaw<IPT, QX> oraw;
 
-    // local frame i is input frame ts + i; its output slot holds frame ts + i - RT
-    const int nphase = t1 + RT - ts + 2;
+    // local frame i is input frame fw.in(i); its output slot holds frame fw.out(i)
+    const int nphase = fw.nstep + 2;
     ring_loop<NTS, -2>(nphase, [&](auto ring_pos, int p) __attribute__((always_inline)) {
         constexpr int J = decltype(ring_pos)::value;  // (p - 2) mod NTS
         const int tx = p - 2;  // local frame of the x-pass / ring step
-        const int tout = ts + tx - RT;
-        const bool emit = tx >= 0 && tout >= t0;
+        const int tout = fw.out(tx);
+        const bool emit = tx >= 0 && tout >= t0 && tout < t1;
         // stage local frame p; the epilogue's loads are issued after the staged
         // values are consumed (loads complete in issue order)
         if (p < nin) {
@@ -545,7 +570,7 @@ __device__ __forceinline__ void stencil_tile_pipe(const Op &op, const Taps<CT> &
         // both load groups in every phase (empty range when not needed): the
         // memory-counter waits then allow for the younger group
         op.template fetch_out<IPT, QX>(tout, ooff, oraw, emit);
-        op.template fetch<NPF>(ts + p + 1, poff, pf, p + 1 < nin);
+        op.template fetch<NPF>(fw.in(p + 1), poff, pf, p + 1 < nin);
         // y-pass of local frame p - 1
         if (p >= 1 && p - 1 < nin) {
             const CT *U = U0 + ((p - 1) & 1) * PG::UB;
@@ -649,19 +674,18 @@ __device__ __forceinline__ void stencil_tile_flat(const Op &op, const Taps<CT> &
 #pragma unroll
             for (int q = 0; q < QX; ++q) acc[s][i][q] = CT(0);
 
-    const int ts = t0 - RT > 0 ? t0 - RT : 0;  // first input frame
-    const int te = t1 + RT < T ? t1 + RT : T;  // one past the last input frame
-    const int nin = te - ts;                   // input frames (local 0 .. nin - 1)
+    const FrameWalk<RT> fw(T, t0, t1);
+    const int nin = fw.nin;  // input frames (local 0 .. nin - 1)
     typename Op::template Raw<NPF> pf;
-    op.template fetch<NPF>(ts, poff, pf);
+    op.template fetch<NPF>(fw.in(0), poff, pf);
     typename Op::template OutRaw<IPT, QX> oraw;
 
-    const int nphase = t1 + RT - ts + 2;
+    const int nphase = fw.nstep + 2;
     ring_loop<NTS, -2>(nphase, [&](auto ring_pos, int p) __attribute__((always_inline)) {
         constexpr int J = decltype(ring_pos)::value;  // (p - 2) mod NTS
         const int tx = p - 2;                         // local frame of the x-pass / t-scatter
-        const int tout = ts + tx - RT;
-        const bool emit = tx >= 0 && tout >= t0;
+        const int tout = fw.out(tx);
+        const bool emit = tx >= 0 && tout >= t0 && tout < t1;
         const bool xlive = tx >= 0 && tx < nin;
         // stage local frame p, then issue the epilogue's loads (every phase, a
         // valid frame, so the count is fixed) and the prefetch of local frame
@@ -672,9 +696,9 @@ __device__ __forceinline__ void stencil_tile_flat(const Op &op, const Taps<CT> &
 #pragma unroll
             for (int k = 0; k < NPF - 1; ++k) U[tid + k * NTHR] = op.template input<NPF>(pf, k);
             U[elast] = op.template input<NPF>(pf, NPF - 1);
-            op.template fetch_out_fixed<IPT, QX>(tout >= t0 ? tout : t0, ooff, oraw);
+            op.template fetch_out_fixed<IPT, QX>(emit ? tout : t0, ooff, oraw);
             const int pn = p + 1 < nin ? p + 1 : nin - 1;
-            op.template fetch<NPF>(ts + pn, poff, pf);
+            op.template fetch<NPF>(fw.in(pn), poff, pf);
         }
         // y-pass of local frame p - 1
         {

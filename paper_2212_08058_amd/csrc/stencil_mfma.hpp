@@ -284,32 +284,18 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[s][i][q] = CT(0);
 
-    const int ts = t0 - RT > 0 ? t0 - RT : 0;
-    const int te = t1 + RT < T ? t1 + RT : T;
-    const int nin = te - ts;
-    // Frame order. Walking forward, the last r_t output frames of a range that
-    // ends at T complete only after r_t more ring steps with no input (the
-    // frames past T are zero): phases that do nothing but the epilogue. A
-    // range that ends at T and starts after 0 is walked backward instead:
-    // its missing inputs are then the ones it never reaches, and its last
-    // output completes with its last staged frame. Local frame k is frame
-    // fb + dir k. The ring needs no change: the temporal taps are even in the
-    // frame distance (the host builds them from its square), so a reversed
-    // walk applies the same taps.
-    const bool rev = t1 == T && t0 > 0;
-    const int dir = rev ? -1 : 1, fb = rev ? te - 1 : ts;
+    const FrameWalk<RT> fw(T, t0, t1);  // frame order (the last segment walks backward)
+    const int nin = fw.nin;
     typename Op::template Raw<NPF> pf;
-    op.template fetch<NPF>(fb, poff, pf);
+    op.template fetch<NPF>(fw.in(0), poff, pf);
     typename Op::template OutRaw<XPW, 4> oraw;
 
-    // the last output frame (t1 - 1 forward, t0 backward) completes with the
-    // ring step of local frame t1 - 1 + RT - ts (te - 1 - t0 + RT backward)
-    const int nphase = (rev ? te - t0 : t1 - ts) + RT + 2;
+    const int nphase = fw.nstep + 2;
     const float one = opaque(1.f);
     ring_loop<NTS, -2>(nphase, [&](auto ring_pos, int p) __attribute__((always_inline)) {
         constexpr int J = decltype(ring_pos)::value;
         const int tx = p - 2;
-        const int tout = fb + dir * (tx - RT);
+        const int tout = fw.out(tx);
         const bool emit = tx >= 0 && tout >= t0 && tout < t1;
         const bool xlive = tx >= 0 && tx < nin;
         const bool ylive = p >= 1 && p - 1 < nin;
@@ -364,7 +350,7 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
                 }
             }
         }
-        op.template fetch<NPF>(fb + dir * (p + 1), poff, pf, p + 1 < nin);
+        op.template fetch<NPF>(fw.in(p + 1), poff, pf, p + 1 < nin);
         if (tx >= 0) {
             CT v[XPW][4];
 #pragma unroll

@@ -510,8 +510,9 @@ SEGMENT_CASES = [
 def test_frame_segments_walk_both_ways(P, shape, kp):
     """When a launch splits the frames, the segment that ends at the last frame
     (and starts after the first) is walked backward, so its last outputs need
-    no ring steps past its input. Per matrix-core variant that splits this
-    shape: one step against the oracle's direct application with every frame's
+    no ring steps past its input. Per compiled variant (matrix-core and vector
+    tile loops) that splits this shape: one step against the oracle's direct
+    application with every frame's
     error bounded on its own (the frames next to each segment boundary and the
     last r_t frames are where a wrong frame order or a missed output shows),
     and 6-step product-form chains (FP32 and BF16 storage) against the
@@ -530,7 +531,10 @@ def test_frame_segments_walk_both_ways(P, shape, kp):
     fd, xd, fbd = torch.from_numpy(f).to(DEV), torch.from_numpy(x).to(DEV), fb.to(DEV)
     split = 0
     for code, dt in ((N.STPI_F32, torch.float32), (N.STPI_BF16, torch.bfloat16)):
-        for i, vi in mfma_variants(code):
+        for i in range(N.lib.stpi_variant_count(code)):
+            info_c = (ctypes.c_int * 9)()
+            assert N.lib.stpi_variant_info(code, i, info_c) == 0
+            vi = list(info_c)
             if vi[1] < kern.r_t or vi[0] < kern.r_s:
                 continue
             nseg = P.launch_shape(shape, kern, dtype=dt, variant=i)["segments"]
