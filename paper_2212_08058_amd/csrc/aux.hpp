@@ -100,18 +100,34 @@ __global__ void bound_kernel(size_t n, const ST *f, const ST *x, uint32_t *out) 
     const size_t stride = (size_t)gridDim.x * AUX_THREADS, tid = (size_t)blockIdx.x * AUX_THREADS + threadIdx.x;
     size_t head = 0;
     if ((((uintptr_t)f | (uintptr_t)x) & 15) == 0) {
-        // 16-byte chunks
+        // 16-byte chunks, four independent loads in flight per thread
         const size_t nv = n / VEC;
-        for (size_t i = tid; i < nv; i += stride) {
-            Chunk16<ST> cf, cx;
-            cf.u = reinterpret_cast<const uint4 *>(f)[i];
-            if (x) cx.u = reinterpret_cast<const uint4 *>(x)[i];
+        const uint4 *f4 = reinterpret_cast<const uint4 *>(f), *x4 = reinterpret_cast<const uint4 *>(x);
+        auto take = [&](const Chunk16<ST> &cf, const Chunk16<ST> &cx) __attribute__((always_inline)) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 float v = fabsf((float)ld(&cf.e[e]));
                 if (x) v *= fabsf((float)ld(&cx.e[e]));
                 r = v > r ? v : r;
             }
+        };
+        constexpr int U = 4;
+        size_t i = tid;
+        for (; i + (U - 1) * stride < nv; i += U * stride) {
+            Chunk16<ST> cf[U], cx[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                cf[k].u = f4[i + k * stride];
+                if (x) cx[k].u = x4[i + k * stride];
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) take(cf[k], cx[k]);
+        }
+        for (; i < nv; i += stride) {
+            Chunk16<ST> cf, cx;
+            cf.u = f4[i];
+            if (x) cx.u = x4[i];
+            take(cf, cx);
         }
         head = nv * VEC;
     }

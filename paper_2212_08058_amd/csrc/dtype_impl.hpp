@@ -29,7 +29,7 @@ hipError_t normalize_impl(void *x, const void *buf1, size_t n, const DevState *s
 }
 
 hipError_t bound_impl(size_t n, const void *f, const void *x, uint32_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(bound_kernel<ST_>, dim3(4096), dim3(AUX_THREADS), 0, s, n, (const ST_ *)f,
+    hipLaunchKernelGGL(bound_kernel<ST_>, dim3(1024), dim3(AUX_THREADS), 0, s, n, (const ST_ *)f,
                        (const ST_ *)x, out);
     return hipGetLastError();
 }
