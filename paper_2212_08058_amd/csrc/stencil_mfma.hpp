@@ -51,6 +51,8 @@
 namespace stpi {
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
@@ -140,10 +142,8 @@ __device__ __forceinline__ void split4(const float4_t &v, half4_t &h, half4_t &l
     for (int j = 0; j < 4; ++j) l[j] = (_Float16)__builtin_fmaf(-(float)h[j], one, v[j]);
 }
 
-// y-pass products of one 16 x 16 block of Y (one dependency chain). EXACT:
-// the staged values are exact in half precision (no lo plane, two products
-// per K block).
-template <class G, bool EXACT>
+// y-pass products of one 16 x 16 block of Y (one dependency chain).
+template <class G>
 __device__ __forceinline__ float4_t mfma_yblock_mma(const _Float16 *U, int b, int lane, const half8_t (&thi)[G::KB],
                                                     const half8_t (&tlo)[G::KB]) {
     const int rb = b / G::NYC, cb = b % G::NYC;
@@ -153,12 +153,29 @@ __device__ __forceinline__ float4_t mfma_yblock_mma(const _Float16 *U, int b, in
 #pragma unroll
     for (int kb = 0; kb < G::KB; ++kb) {
         const half8_t ah = *reinterpret_cast<const half8_t *>(p + 32 * kb);
+        const half8_t al = *reinterpret_cast<const half8_t *>(p + G::UPL + 32 * kb);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, thi[kb], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, tlo[kb], acc, 0, 0, 0);
-        if constexpr (!EXACT) {
-            const half8_t al = *reinterpret_cast<const half8_t *>(p + G::UPL + 32 * kb);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], acc, 0, 0, 0);
-        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, thi[kb], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// The same for bfloat16 inputs staged as they are (one plane of raw
+// bfloat16): bfloat16 products with the taps (times the staging multiplier)
+// split into two bfloat16 parts, hi + lo (about 16 significant bits).
+template <class G>
+__device__ __forceinline__ float4_t mfma_yblock_mma_bf16(const _Float16 *U, int b, int lane,
+                                                         const bf16x8_t (&bhi)[G::KB], const bf16x8_t (&blo)[G::KB]) {
+    const int rb = b / G::NYC, cb = b % G::NYC;
+    const int li = lane & 15, lg = lane >> 4;
+    const _Float16 *p = U + (16 * cb + li) * G::UP + 16 * rb + 8 * lg;
+    float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < G::KB; ++kb) {
+        const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(p + 32 * kb);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bhi[kb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, blo[kb], acc, 0, 0, 0);
     }
     return acc;
 }
@@ -199,10 +216,11 @@ __device__ __forceinline__ float4_t mfma_xblock_mma(const _Float16 *Y, int b, in
 // f * x at staging and op.scale must be 2^-S. rs is the problem's space
 // radius (slab rows and columns beyond it are not read). lds holds
 // MfmaGeometry::LDS_FLOATS floats; tapl holds the 33 space taps centred at 16.
-// EXACT: every staged value input * umul is exact in half precision (umul a
-// power of two, inputs with at most 11 significant bits in range, as
-// bfloat16 storage gives): one U plane, no split, two products per y-pass K
-// block.
+// EXACT: the inputs are bfloat16 values (op.input returns them exactly as
+// floats) and umul is a power of two: U holds the inputs as they are, one
+// plane of raw bfloat16 with no conversion at staging, and the y-pass takes
+// umul into its taps (bfloat16 products, mfma_yblock_mma_bf16). The result
+// is stored in bfloat16, so taps with about 16 significant bits suffice.
 template <class CT, int RT, int TH, int TW, int NTHR, int PAD, bool EXACT = false, class Op>
 __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &tp, const float *tapl, float umul,
                                                   int rs, int T, int t0, int t1, int H, int W, int x0, int y0,
@@ -230,6 +248,21 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
             thi[kb][j] = h;
             tlo[kb][j] = l;
         }
+    // EXACT: the y-pass taps times umul (a power of two, so exact in float) as
+    // two bfloat16 parts
+    bf16x8_t bhi[G::KB], blo[G::KB];
+    if constexpr (EXACT) {
+#pragma unroll
+        for (int kb = 0; kb < G::KB; ++kb)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int d = 32 * kb + 8 * (lane >> 4) + j - PAD - (lane & 15);
+                const float g = ((d >= -16 && d <= 16) ? tapl[d + 16] : 0.f) * umul;
+                const __bf16 h = (__bf16)g;
+                bhi[kb][j] = h;
+                blo[kb][j] = (__bf16)(g - (float)h);
+            }
+    }
 
     // zero the U^T rows [SR, UK) and the Y columns [SC, YW) of both buffers
     // (none when PAD = 8)
@@ -319,7 +352,12 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
 #pragma unroll
             for (int m = 0; m < G::YPW; ++m) {
                 const int b = wid + m * G::NWAVE;
-                if (G::NYB % G::NWAVE == 0 || b < G::NYB) ya[m] = mfma_yblock_mma<G, EXACT>(U, b, lane, thi, tlo);
+                if (G::NYB % G::NWAVE == 0 || b < G::NYB) {
+                    if constexpr (EXACT)
+                        ya[m] = mfma_yblock_mma_bf16<G>(U, b, lane, bhi, blo);
+                    else
+                        ya[m] = mfma_yblock_mma<G>(U, b, lane, thi, tlo);
+                }
             }
         }
         if (p < nin) {
@@ -331,10 +369,11 @@ __device__ __forceinline__ void stencil_tile_mfma(const Op &op, const Taps<CT> &
                     const int c = it % G::SC, g = it / G::SC;
                     _Float16 *q = U + c * G::UP + 8 * g;
                     if constexpr (EXACT) {
-                        half8_t h;
+                        u16x8_t h;  // the inputs' own bfloat16 bits
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) h[j] = (_Float16)(op.template input<NPF>(pf, 8 * m + j) * umul);
-                        *reinterpret_cast<half8_t *>(q) = h;
+                        for (int j = 0; j < 8; ++j)
+                            h[j] = (unsigned short)(__float_as_uint(op.template input<NPF>(pf, 8 * m + j)) >> 16);
+                        *reinterpret_cast<u16x8_t *>(q) = h;
                     } else {
                         half8_t h, l;
 #pragma unroll
