@@ -82,7 +82,7 @@ void batch_step_kernel(BatchArgs<ST> a) {
     using PG = PipeGeometry<RS, RT, TH, TW, NTHR, RY, QX>;
     constexpr int PAD = RS <= 8 ? 8 : 16;
     static_assert(PIPE != 3 || ((RS == 16 || RS == 8) && sizeof(CT) == 4), "matrix-core batch variants");
-    // bfloat16 buffers stage values exact in half precision (one U plane)
+    // bfloat16 buffers stage their raw bfloat16 values (one U plane)
     constexpr bool EXACT = PIPE == 3 && std::is_same<ST, bf16>::value;
     __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR, PAD, EXACT ? 1 : 2>::value
                                 : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];

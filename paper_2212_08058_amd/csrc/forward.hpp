@@ -362,7 +362,7 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
                   "matrix-core variants: RS 8 or 16 (the slab margin), float arithmetic");
     static_assert(!PF || PIPE == 3, "the product form runs on the matrix-core tile loop");
     constexpr int PAD = RS <= 8 ? 8 : 16;
-    // bfloat16 product-form chains stage values exact in half precision
+    // bfloat16 product-form chains stage their raw bfloat16 values (one U plane)
     constexpr bool EXACT = PF && std::is_same<ST, bf16>::value;
     __shared__ CT lds[PIPE == 3 ? MfmaLds<PIPE, TH, TW, NTHR, PAD, EXACT ? 1 : 2>::value
                                 : (PIPE ? PG::LDS_ELEMS : G::LDS_ELEMS)];
@@ -430,8 +430,9 @@ __global__ __launch_bounds__(NTHR, OCC) void fwd_step_kernel(FwdArgs<ST> a) {
             const float win = first ? bound : __uint_as_float(a.state->wmax[cur]);
             float umul;
             if constexpr (EXACT) {
-                // stage w ginv_in 2^(10 - ein) (a power of two times a bfloat16
-                // value: exact in half precision); the scale moves to the epilogue
+                // the y-pass multiplies the staged bfloat16 w by ginv_in
+                // 2^(10 - ein) (a power of two, folded into its taps); the scale
+                // moves to the epilogue
                 const int ein = bound_exponent((float)((double)win * pp.ginv_in), 100);
                 pp.sg = (float)(scale * ldexp(1.0, ein - 10 - 2 * e));
                 umul = (float)ldexp(pp.ginv_in, 10 - ein);

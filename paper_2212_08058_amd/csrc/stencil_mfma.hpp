@@ -41,7 +41,8 @@
 //           which feed the t-ring (2 RT + 1 register slots) and the epilogue.
 // Both band matrices hold g(32 kb + k - PAD - i) at (row i, col k) in the
 // operand layout, so one set of tap registers serves as the y-pass B operand
-// and the x-pass A operand. Rows and columns of the slab beyond the space
+// and the x-pass A operand (bfloat16 inputs stage their raw values and take
+// a second, bfloat16 set for the y-pass: stencil_tile_mfma's EXACT). Rows and columns of the slab beyond the space
 // radius are staged as zeros; with PAD = 16 the 16 extra U rows and Y columns
 // that the last K block of the bottom / right blocks reads are zeroed once.
 #pragma once
@@ -67,8 +68,8 @@ constexpr int mfma_pitch(int n) {
 // PAD (8 or 16) is the slab margin, at least the space radius. An output
 // block of 16 rows (columns) reads 16 + 2 PAD slab rows (columns), that is KB
 // K blocks of 32 (the last 16 of them zero weight when PAD = 16).
-// UPLANES: half-precision planes per staged U buffer: 2 (hi and lo) in
-// general, 1 when the staged values are exact in half precision (see
+// UPLANES: 16-bit planes per staged U buffer: 2 (half-precision hi and lo)
+// in general, 1 for bfloat16 inputs staged as they are (see
 // stencil_tile_mfma's EXACT).
 template <int TH, int TW, int NTHR, int PAD, int UPLANES = 2>
 struct MfmaGeometry {
