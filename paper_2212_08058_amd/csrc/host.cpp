@@ -136,6 +136,38 @@ int device_cus() {
     return cus[dev];
 }
 
+// Phases of the slowest of k frame segments of a T-frame tile: the frame walk
+// of the tile loops (FrameWalk: RT input frames staged beyond each inner
+// boundary, the last segment walked backward when it starts after frame 0)
+// plus the 2 phases that fill the pipeline.
+int segment_phases(int T, int RT, int k) {
+    int worst = 0;
+    for (int s = 0; s < k; ++s) {
+        const int t0 = (int)((long)s * T / k), t1 = (int)((long)(s + 1) * T / k);
+        const int ts = std::max(t0 - RT, 0), te = std::min(t1 + RT, T);
+        const bool rev = t1 == T && t0 > 0;
+        worst = std::max(worst, (rev ? te - t0 : t1 - ts) + RT + 2);
+    }
+    return worst;
+}
+
+// A tile that the rules below leave whole: when every segment can have a CU
+// of its own, the step takes as long as its slowest segment, so split the
+// frames where that lowers the phase count (a whole tile ends with RT
+// epilogue-only phases that a split with a backward last segment avoids;
+// short clips, e.g. the windows of an online run, gain most).
+int split_short_tiles(int tiles, int T, int RT) {
+    const int cus = device_cus();
+    if (2L * tiles > cus) return 1;
+    const int kmax = std::min(std::min(cus / tiles, STPI_NSEG_MAX), T);
+    // more segments only for at least two phases fewer (each adds a
+    // workgroup that re-stages RT frames)
+    int best = 1;
+    for (int k = 2; k <= kmax; ++k)
+        if (segment_phases(T, RT, k) + 1 < segment_phases(T, RT, best)) best = k;
+    return best;
+}
+
 // Frame segments per tile. When a clip has fewer tiles than the chip holds
 // resident workgroups, each tile's frames are split so that more workgroups
 // (with independent barriers) share every CU. A segment re-reads and
@@ -156,6 +188,7 @@ int segments_for(const Variant &v, const stpi_problem *p) {
         const int small = std::min(std::min(fit, p->T / (2 * rt)), STPI_NSEG_MAX);
         if (small > nseg) nseg = small;
     }
+    if (nseg == 1) nseg = split_short_tiles(tiles, p->T, v.RT);
     return nseg;
 }
 

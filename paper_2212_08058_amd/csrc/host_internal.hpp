@@ -30,6 +30,10 @@ void make_taps(const stpi_problem *p, double *gs, double *gt);
 const Variant *choose_variant(const stpi_problem *p, int forced_index, bool allow_mfma = true);
 int grid_blocks(const Variant &v, const stpi_problem *p);
 int segments_for(const Variant &v, const stpi_problem *p);
+// Phases of the slowest of k frame segments of a T-frame tile, and the split
+// of a tile the occupancy rules leave whole (see host.cpp).
+int segment_phases(int T, int RT, int k);
+int split_short_tiles(int tiles, int T, int RT);
 constexpr int STPI_NSEG_MAX = 8;  // frame segments per tile at most
 WsLayout layout_for(const stpi_problem *p);
 constexpr int CHAIN_CHUNK = 16;  // steps per replayed chain segment in long tolerance runs

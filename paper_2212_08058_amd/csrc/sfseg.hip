@@ -41,13 +41,16 @@ int sfseg_tiles(const SfsegVariant &v, const stpi_problem *p) {
 }
 
 // Frame segments per tile: enough work units to fill the resident slots when
-// the frame has few tiles, each segment at least 4 r_t frames long.
+// the frame has few tiles, each segment at least 4 r_t frames long; a tile
+// left whole is split as the single-field step splits it (split_short_tiles).
 int sfseg_segments(const SfsegVariant &v, const stpi_problem *p) {
     const int tiles = sfseg_tiles(v, p);
     const int resident = device_cus() * v.blocks_per_cu();
     const int rt = std::max(v.RT, 1);
     int nseg = std::min(std::min(resident / std::max(tiles, 1), p->T / (4 * rt)), STPI_NSEG_MAX);
-    return nseg < 1 ? 1 : nseg;
+    if (nseg < 1) nseg = 1;
+    if (nseg == 1) nseg = split_short_tiles(std::max(tiles, 1), p->T, v.RT);
+    return nseg;
 }
 
 struct SfsegLayout {

@@ -113,3 +113,41 @@ def test_coarse_problem_host_only(native):
     assert native.lib.stpi_coarse_problem(None, 2, 2, ctypes.byref(c)) == native.STPI_EINVAL
     zero = P(0, 7, 9, 3.0, 1.5, 8, 3, native.STPI_F32)
     assert native.lib.stpi_coarse_problem(ctypes.byref(zero), 2, 2, ctypes.byref(c)) == native.STPI_EINVAL
+
+
+def _walk_phases(T, RT, k):
+    """Phases of the slowest of k frame segments: each segment stages RT frames
+    beyond an inner boundary, the last one (starting after frame 0) walks
+    backward so it has no epilogue-only ring steps at the clip's end, plus 2
+    phases to fill the pipeline."""
+    worst = 0
+    for s in range(k):
+        t0, t1 = s * T // k, (s + 1) * T // k
+        ts, te = max(t0 - RT, 0), min(t1 + RT, T)
+        n = (te - t0 if (t1 == T and t0 > 0) else t1 - ts) + RT + 2
+        worst = max(worst, n)
+    return worst
+
+
+def test_short_clips_split_their_frames(native):
+    """stpi_launch_shape (host logic): a clip whose tiles would leave most CUs
+    idle splits its frames when that saves at least two phases of its slowest
+    segment (a 16-frame window at 480 x 854, r = (15, 5): 15 phases against
+    23 whole); a 3-frame clip stays whole; the full 64-frame clip keeps its
+    two segments."""
+    P = native.Problem
+    info = (ctypes.c_int32 * 5)()
+    cases = [((16, 480, 854), (5.0, 2.0, 15, 5), 2), ((64, 480, 854), (5.0, 2.0, 15, 5), 2),
+             ((3, 45, 108), (4.0, 1.5, 8, 3), 1), ((4, 45, 108), (4.0, 1.5, 8, 3), 2)]
+    for (T, H, W), (ss, st, rs, rt), want in cases:
+        p = P(T, H, W, ss, st, rs, rt, native.STPI_F32)
+        assert native.lib.stpi_launch_shape(ctypes.byref(p), -1, info) == native.STPI_OK
+        variant, tiles, nseg = info[0], info[1], info[2]
+        assert nseg == want, ((T, H, W), list(info))
+        vi = (ctypes.c_int * 9)()
+        assert native.lib.stpi_variant_info(native.STPI_F32, variant, vi) == native.STPI_OK
+        RT = vi[1]
+        if nseg > 1 and T < 4 * RT:
+            # split only by the phase rule: it saves at least two phases
+            assert _walk_phases(T, RT, nseg) + 1 < _walk_phases(T, RT, 1)
+    assert _walk_phases(16, 5, 2) == 15 and _walk_phases(16, 5, 1) == 23

@@ -50,13 +50,16 @@ def test_batch_fixed_iterations_match_oracle(P):
 
 def test_batch_bitwise_equals_single_clip_path(P):
     """Same kernel variant, same tiles, same reduction order: per-clip results are
-    identical where the single-clip launch does not split the clip's frames
-    (a split changes the order of the partial sums), and agree to rounding
-    where it does."""
+    identical where the single-clip launch does not split the clip's frames,
+    and agree to float rounding where it does (a split changes the order of
+    the partial sums, and its backward-walked last segment the order of each
+    output's temporal sum, so the iterates differ by float rounding)."""
     Pm, B = P
     from paper_2212_08058_amd import _native as N
     kern = Pm.Kernel(4.0, 1.5, 8, 3)
-    shapes = [(11, 60, 216), (4, 45, 108), (20, 30, 150)]
+    # the 3-frame clip stays whole in a single-clip launch (splitting it would
+    # save less than two phases), so it is compared bitwise
+    shapes = [(11, 60, 216), (3, 45, 108), (20, 30, 150)]
     fs = _clips(shapes, seed=10)
     plan = B.BatchPlan(shapes, kern)
     info = plan.info()
@@ -87,7 +90,7 @@ def test_batch_bitwise_equals_single_clip_path(P):
             else:
                 split += 1
                 assert abs(r["iters"] - rs["iters"]) <= 1 and r["converged"] == rs["converged"]
-                assert abs(r["lambda_"] - rs["lambda_"]) <= 1e-12 * rs["lambda_"]
+                assert abs(r["lambda_"] - rs["lambda_"]) <= 1e-6 * rs["lambda_"]
                 assert float((xs.double() - xv.double()).norm()) <= 1e-5
         assert split < len(fs), "no clip compared bitwise"
     finally:
@@ -156,7 +159,7 @@ def test_pipelined_batch_variant(P, tmp_path):
     Pm, B = P
     from paper_2212_08058_amd import _native as N
     kern = Pm.Kernel(4.0, 1.5, 8, 3)
-    shapes = [(14, 45, 216), (6, 45, 216), (9, 30, 108)]
+    shapes = [(14, 45, 216), (6, 45, 216), (9, 30, 108), (3, 45, 216)]
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     path = tmp_path / "tune.txt"
     path.write_text(f"{arch} 0 8 3 45 216 8 3 15 108 512 5 4 1 1 1.0\n")
@@ -171,6 +174,7 @@ def test_pipelined_batch_variant(P, tmp_path):
         s = torch.cuda.Stream()
         x_flat, res = plan.iterate(f_flat, max_iters=6, tol=0.0, stream=s)
         torch.cuda.synchronize()
+        whole = 0
         for f, xv, r in zip(fs, plan.views(x_flat), res):
             xr, _ = oracle.iterate(f, okf(kern), iters=6)
             err = float(np.linalg.norm(xv.double().cpu().numpy() - xr) / np.linalg.norm(xr))
@@ -178,6 +182,8 @@ def test_pipelined_batch_variant(P, tmp_path):
             xs, rs = Pm.power_iterate(torch.from_numpy(f).to(DEV), kern, iters=6)
             if Pm.launch_shape(f.shape, kern)["segments"] == 1:
                 assert torch.equal(xs, xv), f.shape
+                whole += 1
+        assert whole, "no clip compared bitwise"
     finally:
         B.autotune_clear()
 
