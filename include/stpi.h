@@ -259,8 +259,11 @@ int stpi_variant_info(int dtype, int index, int32_t info[9]);
 /* Launch shape the step of problem p uses with variant `variant` (-1: the
  * variant stpi_step would choose): info[0] = variant index, info[1] = tiles
  * per frame, info[2] = frame segments per tile (a tile's frames are split
- * when the chip holds more resident workgroups than there are tiles; each
- * segment re-reads r_t frames on each inner side), info[3] = workgroups per
+ * when the chip holds more resident workgroups than there are tiles, and a
+ * short clip's frames when that shortens the slowest segment by two frame
+ * steps or more; each segment re-reads r_t frames on each inner side, and
+ * a last segment that starts after frame 0 is walked backward in time, which
+ * changes only the order of its sums), info[3] = workgroups per
  * CU that fit at once, info[4] = workgroups launched. Queries the current
  * device. STPI_EINVAL / STPI_EUNSUPPORTED as for stpi_step. */
 int stpi_launch_shape(const stpi_problem *p, int variant, int32_t info[5]);
