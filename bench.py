@@ -279,11 +279,11 @@ def main():
         # kernel below it is recorded beside it (rocprofv3 SQ counters)
         out["roofline"] = {"bound": "hbm", **hbm, "traffic": None, "kernel": "fwd_step_kernel", "kernel_ms": kern_ms,
                            "alu": alu,
-                           "limiter": "instruction issue and latency, not HBM: per SIMD the vector ALU is busy ~48% "
-                                      "of the kernel time; a wavefront spends ~34% of its life in memory or barrier "
-                                      "waits and ~29% waiting to issue (two wavefronts per SIMD, one LDS-bound "
-                                      "workgroup per CU, a barrier per frame phase; vector-memory latency ~1200 "
-                                      "cycles, L2 hit rate ~55%)"}
+                           "limiter": "instruction issue and latency, not HBM: per SIMD the vector ALU is busy ~50% "
+                                      "of the kernel time; a wavefront spends ~37% of its life in memory or barrier "
+                                      "waits and ~24% waiting to issue (two wavefronts per SIMD, one LDS-bound "
+                                      "workgroup per CU, a barrier per frame phase, 39 phases per workgroup; "
+                                      "vector-memory latency ~1050 cycles, L2 hit rate ~59%)"}
     else:
         out["roofline"] = {"bound": "alu", **alu, "traffic": None, "kernel": "fwd_step_kernel", "kernel_ms": kern_ms,
                            "hbm": hbm}
