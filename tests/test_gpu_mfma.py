@@ -322,6 +322,43 @@ def test_product_form_value_ranges(P, kind):
         assert torch.all(x[torch.from_numpy(f).to(DEV) == 0] == 0)
 
 
+@pytest.mark.parametrize("kind", ["tiny", "huge", "holes", "signed", "spread"])
+def test_product_form_bf16_value_ranges(P, kind):
+    """BF16 chains stage the raw bfloat16 values and carry the staging power of
+    two in the y-pass taps: f far from 1 on either side (the scales the FP32
+    product form is tested at; the power of two then far from 1 too), voxels
+    with f = 0, f of both signs and f spread over seven decades (values that
+    half precision would hold only as subnormals) match the oracle iterating
+    on the rounded f to the storage precision."""
+    kern = P.Kernel(5.0, 2.0, 15, 5)
+    shape = (10, 50, 90)
+    rng = np.random.default_rng(19)
+    f = rng.uniform(0.05, 1.0, shape)
+    if kind == "tiny":
+        f = f * 1e-12
+    elif kind == "huge":
+        f = f * 1e8
+    elif kind == "holes":
+        f[rng.uniform(size=shape) < 0.4] = 0.0
+        f[:, 10:20, :] = 0.0
+    elif kind == "signed":
+        f = rng.uniform(-1.0, 1.0, shape)
+    else:
+        f = 10.0 ** rng.uniform(-7.0, 0.0, shape)
+    fb = torch.from_numpy(f.astype(np.float32)).to(torch.bfloat16)
+    xr, info = oracle.iterate(fb.double().numpy(), OKf(kern), iters=8)
+    fd = fb.to(DEV)
+    _, pf = P.time_chain_step(fd, kern, reps=1)
+    x, r = P.power_iterate(fd, kern, iters=8)
+    torch.cuda.synchronize()
+    err = rel_l2(x.double().cpu().numpy(), xr)
+    print(kind, "bf16 product form", pf, f"rel L2 {err:.3e}", r["lambda_"], info.lambdas[-1])
+    assert pf and err <= 2.0 ** -8
+    assert abs(r["lambda_"] - info.lambdas[-1]) <= 2.0 ** -8 * abs(info.lambdas[-1])
+    if kind == "holes":
+        assert torch.all(x[fd == 0] == 0)
+
+
 def test_product_form_agrees_with_plain_form(P):
     """Tolerance runs in the two forms: same stopping step, residuals and
     vectors equal to float rounding (warm start with the rise check too)."""
