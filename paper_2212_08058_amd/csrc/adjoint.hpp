@@ -103,7 +103,7 @@ struct AdjArgs {
     ST *gk, *gf;
     const double *norm_k, *norm_k1, *d_k1;
     double *partials;
-    int T, H, W;
+    int T, H, W, nseg;
     Taps<CT> taps;
 };
 
@@ -114,8 +114,12 @@ __global__ __launch_bounds__(NTHR) void adj_step_kernel(AdjArgs<ST> a) {
     __shared__ CT lds[G::LDS_ELEMS];
     __shared__ double red[NTHR / 64];
     const int nbx = (a.W + TW - 1) / TW, nby = (a.H + TH - 1) / TH;
-    const int tile = xcd_tile(blockIdx.x, nbx * nby);
-    if (tile < 0) return;
+    // work units as the forward step's: frame segments of tiles, segment-major
+    const int ntiles = nbx * nby;
+    const int unit = xcd_tile(blockIdx.x, ntiles * a.nseg);
+    if (unit < 0) return;
+    const int tile = unit % ntiles, seg = unit / ntiles;
+    const int t0 = (int)((int64_t)seg * a.T / a.nseg), t1 = (int)((int64_t)(seg + 1) * a.T / a.nseg);
     AdjOp<ST> op;
     op.f = a.f;
     op.zk = a.zk;
@@ -132,12 +136,12 @@ __global__ __launch_bounds__(NTHR) void adj_step_kernel(AdjArgs<ST> a) {
     op.pbytes = (uint32_t)(op.plane * sizeof(ST));
     double d1 = 0.0, d2 = 0.0;
     const int x0 = (tile % nbx) * TW, y0 = (tile / nbx) * TH;
-    stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, 0, a.T, a.H, a.W, x0, y0, lds, d1, d2);
+    stencil_tile<CT, RS, RT, TH, TW, NTHR, RY, QX>(op, a.taps, a.T, t0, t1, a.H, a.W, x0, y0, lds, d1, d2);
     const double s1 = block_sum<NTHR>(d1, red);
     const double s2 = block_sum<NTHR>(d2, red);
     if (threadIdx.x == 0) {
-        a.partials[2 * tile] = s1;
-        a.partials[2 * tile + 1] = s2;
+        a.partials[2 * unit] = s1;
+        a.partials[2 * unit + 1] = s2;
     }
 }
 
@@ -147,7 +151,7 @@ struct AdjLaunch {
     void *gk, *gf;
     const double *norm_k, *norm_k1, *d_k1;
     double *partials;
-    int T, H, W;
+    int T, H, W, nseg;
     double gs[2 * 16 + 1];
     double gt[2 * 8 + 1];
 };
@@ -175,12 +179,13 @@ hipError_t launch_adj(const AdjLaunch &L, hipStream_t stream) {
     a.T = L.T;
     a.H = L.H;
     a.W = L.W;
+    a.nseg = L.nseg > 0 ? L.nseg : 1;
     for (int i = 0; i < 2 * 16 + 1; ++i) a.taps.gs[i] = CT(0);
     for (int i = 0; i < 2 * 8 + 1; ++i) a.taps.gt[i] = CT(0);
     for (int dd = -RS; dd <= RS; ++dd) a.taps.gs[dd + RS] = (CT)L.gs[dd + 16];
     for (int dd = -RT; dd <= RT; ++dd) a.taps.gt[dd + RT] = (CT)L.gt[dd + 8];
-    const int ntiles = ((L.W + TW - 1) / TW) * ((L.H + TH - 1) / TH);
-    const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+    const int nunits = ((L.W + TW - 1) / TW) * ((L.H + TH - 1) / TH) * a.nseg;
+    const int per = (nunits + NUM_XCD - 1) / NUM_XCD;
     hipLaunchKernelGGL((adj_step_kernel<ST, RS, RT, TH, TW, NTHR, RY, QX>), dim3(per * NUM_XCD), dim3(NTHR), 0,
                        stream, a);
     return hipGetLastError();

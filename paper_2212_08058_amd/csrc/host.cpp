@@ -205,7 +205,7 @@ size_t partials_capacity(const stpi_problem *p) {
     }
     for (int i = 0; i < ops->nadj; ++i) {
         const AdjVariant &v = ops->adj_variants[i];
-        const size_t g = (size_t)(((p->W + v.TW - 1) / v.TW) * ((p->H + v.TH - 1) / v.TH));
+        const size_t g = (size_t)(((p->W + v.TW - 1) / v.TW) * ((p->H + v.TH - 1) / v.TH)) * STPI_NSEG_MAX;
         if (g > cap) cap = g;
     }
     return cap;

@@ -36,8 +36,20 @@ const AdjVariant *choose_adj_variant(const stpi_problem *p) {
     return best;
 }
 
+// Frame segments of an adjoint launch (one workgroup per CU): as the forward
+// step's, at least 4 r_t frames long while the tiles leave CUs idle, and a
+// tile left whole split where that shortens its slowest segment.
+int adj_segments(const AdjVariant &v, const stpi_problem *p) {
+    const int tiles = ((p->W + v.TW - 1) / v.TW) * ((p->H + v.TH - 1) / v.TH);
+    const int rt = v.RT > 0 ? v.RT : 1;
+    int nseg = std::min(std::min(device_cus() / tiles, p->T / (4 * rt)), 4);
+    if (nseg < 1) nseg = 1;
+    if (nseg == 1) nseg = split_short_tiles(tiles, p->T, v.RT);
+    return nseg;
+}
+
 int adj_grid_blocks(const AdjVariant &v, const stpi_problem *p) {
-    return ((p->W + v.TW - 1) / v.TW) * ((p->H + v.TH - 1) / v.TH);
+    return ((p->W + v.TW - 1) / v.TW) * ((p->H + v.TH - 1) / v.TH) * adj_segments(v, p);
 }
 
 }  // namespace stpi
@@ -120,6 +132,7 @@ int stpi_adjoint_step(const stpi_problem *p, const void *f, const void *z_k, con
     AL.T = p->T;
     AL.H = p->H;
     AL.W = p->W;
+    AL.nseg = adj_segments(*v, p);
     make_taps(p, AL.gs, AL.gt);
     hipError_t e = v->launch(AL, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint launch");
