@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="let the autotuner pick the FP32 tile (default: the cost model's choice, which the "
                          "committed counter profile covers); the BF16 leg is always tuned")
-    ap.add_argument("--extras", default="bf16,copy,sfseg,taylor,online,objective,batch,warm",
+    ap.add_argument("--extras", default="bf16,copy,sfseg,taylor,online,objective,channels,batch,warm",
                     help="comma list of extra measurements to attach: bf16, copy, sfseg, taylor, online, objective, "
                          "batch, channels, warm (or none)")
     ap.add_argument("--warm-train", type=int, default=200, help="training clips for the warm-start extra")
